@@ -1,0 +1,390 @@
+// C ABI entry points of libdawn (declared in include/dawn.h): argument
+// checks, the graph table, device-memory accounting and error text.  The
+// traversal work itself lives in sssp.hip / mssp.hip / serve.cpp.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace dawn {
+
+static thread_local char g_err[512] = "";
+
+dawn_status fail(dawn_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+dawn_status dev_alloc(Ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 1;
+  long long left = ctx->fail_after.load();
+  if (left >= 0) {
+    if (left == 0) return fail(DAWN_E_NO_MEMORY, "device allocation refused (injected failure)");
+    ctx->fail_after.fetch_sub(1);
+  }
+  uint64_t used = ctx->used.fetch_add(bytes) + bytes;
+  if (used > ctx->budget) {
+    ctx->used.fetch_sub(bytes);
+    return fail(DAWN_E_NO_MEMORY, "HBM budget exceeded: need %zu more bytes, %llu of %llu in use",
+                bytes, (unsigned long long)(used - bytes), (unsigned long long)ctx->budget);
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    ctx->used.fetch_sub(bytes);
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(DAWN_E_NO_MEMORY, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return DAWN_OK;
+}
+
+void dev_free(Ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  hipFree(p);
+  if (ctx && bytes) ctx->used.fetch_sub(bytes == 0 ? 1 : bytes);
+}
+
+dawn_status get_graph(Ctx* ctx, int32_t id, std::shared_ptr<GraphRec>* out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->graphs.find(id);
+  if (it == ctx->graphs.end()) return fail(DAWN_E_NOT_FOUND, "no resident graph %d", id);
+  *out = it->second;
+  return DAWN_OK;
+}
+
+dawn_params default_params(const GraphRec& g) {
+  dawn_params p;
+  memset(&p, 0, sizeof(p));
+  p.driver = 1;
+  p.direction = 3;
+  p.block = 256;
+  p.blocks_per_cu = 0;
+  p.big_degree = 2048;
+  p.pull_lane_edges = 32;
+  p.alpha = 14.0f;
+  p.beta = 24.0f;
+  p.graph_levels = 8;
+  p.small_n = 0;
+  p.batch_alpha = 4.0f;
+  p.batch_lanes = 4096;
+  (void)g;
+  return p;
+}
+
+dawn_status check_params(const dawn_params& p) {
+  if (p.driver < 1 || p.driver > 3) return fail(DAWN_E_INVALID_ARG, "driver must be 1, 2 or 3");
+  if (p.direction < 1 || p.direction > 3) return fail(DAWN_E_INVALID_ARG, "direction must be 1..3");
+  if (p.block != 256 && p.block != 512 && p.block != 1024)
+    return fail(DAWN_E_INVALID_ARG, "block must be 256, 512 or 1024");
+  if (p.blocks_per_cu < 0 || p.blocks_per_cu > 64) return fail(DAWN_E_INVALID_ARG, "blocks_per_cu");
+  if (p.big_degree < 64) return fail(DAWN_E_INVALID_ARG, "big_degree must be >= 64");
+  if (p.pull_lane_edges < 1) return fail(DAWN_E_INVALID_ARG, "pull_lane_edges must be >= 1");
+  if (!(p.alpha > 0.f) || !(p.beta > 0.f)) return fail(DAWN_E_INVALID_ARG, "alpha, beta > 0");
+  if (p.graph_levels < 1 || p.graph_levels > 1024) return fail(DAWN_E_INVALID_ARG, "graph_levels");
+  if (p.small_n < 0) return fail(DAWN_E_INVALID_ARG, "small_n");
+  if (!(p.batch_alpha > 0.f)) return fail(DAWN_E_INVALID_ARG, "batch_alpha > 0");
+  if (p.batch_lanes < 64 || p.batch_lanes > 4096 || p.batch_lanes % 64)
+    return fail(DAWN_E_INVALID_ARG, "batch_lanes must be a multiple of 64 in [64, 4096]");
+  return DAWN_OK;
+}
+
+static dawn_status check_ctx(dawn_ctx* c) {
+  if (!c) return fail(DAWN_E_INVALID_ARG, "null context");
+  return DAWN_OK;
+}
+
+static Ctx* C(dawn_ctx* c) { return reinterpret_cast<Ctx*>(c); }
+
+}  // namespace dawn
+
+using namespace dawn;
+
+extern "C" {
+
+const char* dawn_last_error(void) { return g_err; }
+
+dawn_status dawn_create(int32_t device, uint64_t hbm_budget_bytes, dawn_ctx** out) {
+  clear_error();
+  if (!out) return fail(DAWN_E_INVALID_ARG, "null output handle");
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0)
+    return fail(DAWN_E_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+  if (device < 0 || device >= count)
+    return fail(DAWN_E_INVALID_ARG, "device %d outside [0, %d)", device, count);
+  DAWN_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  DAWN_HIP(hipGetDeviceProperties(&prop, device));
+  size_t freeb = 0, totalb = 0;
+  DAWN_HIP(hipMemGetInfo(&freeb, &totalb));
+  Ctx* ctx = new Ctx();
+  ctx->device = device;
+  ctx->num_cu = prop.multiProcessorCount;
+  ctx->coop = prop.cooperativeLaunch;
+  uint64_t budget = hbm_budget_bytes;
+  if (budget == 0) {
+    const char* env = getenv("DAWN_HBM_BUDGET");
+    if (env && *env) budget = strtoull(env, nullptr, 10);
+  }
+  if (budget == 0) budget = (uint64_t)(freeb * 0.9);
+  ctx->budget = budget;
+  const char* fa = getenv("DAWN_FAIL_ALLOC_AFTER");
+  if (fa && *fa) ctx->fail_after = atoll(fa);
+  *out = reinterpret_cast<dawn_ctx*>(ctx);
+  return DAWN_OK;
+}
+
+dawn_status dawn_destroy(dawn_ctx* c) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  Ctx* ctx = C(c);
+  hipSetDevice(ctx->device);
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (ctx->server) {
+      server_stop(ctx->server);
+      ctx->server = nullptr;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->graphs.clear();
+  }
+  hipDeviceSynchronize();
+  delete ctx;
+  return DAWN_OK;
+}
+
+dawn_status dawn_memory(dawn_ctx* c, uint64_t* used, uint64_t* budget) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (used) *used = C(c)->used.load();
+  if (budget) *budget = C(c)->budget;
+  return DAWN_OK;
+}
+
+dawn_status dawn_graph_upload(dawn_ctx* c, int32_t n, int64_t m, const int32_t* row_ptr,
+                              const int32_t* col, uint32_t flags, int32_t* graph_out) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (n <= 0) return fail(DAWN_E_INVALID_ARG, "n must be positive (got %d)", n);
+  if (m < 0 || m > 0x7fffffffLL) return fail(DAWN_E_INVALID_ARG, "m must be in [0, INT32_MAX]");
+  if (!row_ptr || (m > 0 && !col) || !graph_out) return fail(DAWN_E_INVALID_ARG, "null pointer");
+  if (flags != 0) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
+  Ctx* ctx = C(c);
+  DAWN_HIP(hipSetDevice(ctx->device));
+  auto g = std::make_shared<GraphRec>();
+  g->n = n;
+  g->m = m;
+  dawn_status st = graph_build(ctx, g.get(), row_ptr, col);
+  if (st != DAWN_OK) return st;
+  g->params = default_params(*g);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  g->id = ctx->next_graph++;
+  ctx->graphs[g->id] = g;
+  *graph_out = g->id;
+  return DAWN_OK;
+}
+
+dawn_status dawn_graph_release(dawn_ctx* c, int32_t graph) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  Ctx* ctx = C(c);
+  hipSetDevice(ctx->device);
+  std::shared_ptr<GraphRec> g;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->graphs.find(graph);
+    if (it == ctx->graphs.end()) return fail(DAWN_E_NOT_FOUND, "no resident graph %d", graph);
+    g = it->second;
+    ctx->graphs.erase(it);
+  }
+  // running calls hold their own reference; the buffers go with the last one
+  g.reset();
+  return DAWN_OK;
+}
+
+dawn_status dawn_graph_get_info(dawn_ctx* c, int32_t graph, dawn_graph_info* out) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!out) return fail(DAWN_E_INVALID_ARG, "null output");
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(C(c), graph, &g));
+  std::lock_guard<std::mutex> lk(g->mu);
+  out->n = g->n;
+  out->m = g->m;
+  out->max_out_degree = g->max_out_deg;
+  out->zero_out_degree = g->zero_out;
+  out->s_wcc = g->wcc_ready ? (int32_t)g->wcc_nodes.size() : -1;
+  out->device_bytes = (int64_t)g->bytes;
+  return DAWN_OK;
+}
+
+dawn_status dawn_get_params(dawn_ctx* c, int32_t graph, dawn_params* out) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!out) return fail(DAWN_E_INVALID_ARG, "null output");
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(C(c), graph, &g));
+  std::lock_guard<std::mutex> lk(g->mu);
+  *out = g->params;
+  return DAWN_OK;
+}
+
+dawn_status dawn_set_params(dawn_ctx* c, int32_t graph, const dawn_params* in) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!in) return fail(DAWN_E_INVALID_ARG, "null input");
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(C(c), graph, &g));
+  dawn_params d = default_params(*g);
+  dawn_params p = *in;
+#define KEEP(f) \
+  if (p.f == 0) p.f = d.f
+  KEEP(driver); KEEP(direction); KEEP(block); KEEP(big_degree); KEEP(pull_lane_edges);
+  KEEP(alpha); KEEP(beta); KEEP(graph_levels); KEEP(batch_alpha); KEEP(batch_lanes);
+#undef KEEP
+  DAWN_TRY(check_params(p));
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->params = p;
+  if (g->wcc_sub) g->wcc_sub->params = p;
+  return DAWN_OK;
+}
+
+dawn_status dawn_sssp(dawn_ctx* c, int32_t graph, int32_t source, int32_t* dist, uint32_t flags,
+                      dawn_run_stats* stats) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!dist) return fail(DAWN_E_INVALID_ARG, "null dist");
+  if (flags & ~DAWN_DEVICE_OUT) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  if (source < 0 || source >= g->n)
+    return fail(DAWN_E_INVALID_ARG, "source %d outside [0, %d)", source, g->n);
+  DAWN_HIP(hipSetDevice(ctx->device));
+  dawn_params p;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    p = g->params;
+  }
+  return sssp_run(ctx, g.get(), p, source, dist, (flags & DAWN_DEVICE_OUT) != 0, stats);
+}
+
+dawn_status dawn_mssp(dawn_ctx* c, int32_t graph, const int32_t* sources, int32_t k, int32_t* dist,
+                      uint32_t flags, dawn_run_stats* stats) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (k < 0) return fail(DAWN_E_INVALID_ARG, "k must be >= 0");
+  if (flags & ~DAWN_DEVICE_OUT) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  if (k == 0) {
+    if (stats) {
+      stats->levels = stats->push_levels = stats->pull_levels = stats->launches = 0;
+      stats->edges_examined = stats->source_edges = stats->reached = 0;
+      stats->kernel_ms = stats->total_ms = 0;
+    }
+    return DAWN_OK;
+  }
+  if (!sources || !dist) return fail(DAWN_E_INVALID_ARG, "null pointer");
+  for (int32_t r = 0; r < k; ++r)
+    if (sources[r] < 0 || sources[r] >= g->n)
+      return fail(DAWN_E_INVALID_ARG, "sources[%d] = %d outside [0, %d)", r, sources[r], g->n);
+  DAWN_HIP(hipSetDevice(ctx->device));
+  dawn_params p;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    p = g->params;
+  }
+  return mssp_run(ctx, g.get(), p, sources, k, dist, (flags & DAWN_DEVICE_OUT) != 0, g->n, stats);
+}
+
+dawn_status dawn_apsp_wcc(dawn_ctx* c, int32_t graph, int32_t* wcc_nodes, int32_t* s_wcc,
+                          int32_t* dist, uint32_t flags, dawn_run_stats* stats) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!wcc_nodes || !s_wcc) return fail(DAWN_E_INVALID_ARG, "null pointer");
+  if (flags & ~DAWN_DEVICE_OUT) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  DAWN_HIP(hipSetDevice(ctx->device));
+  std::shared_ptr<GraphRec> sub;
+  std::vector<int32_t> nodes;
+  dawn_params p;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->wcc_ready) {
+      hipStream_t s = nullptr;
+      DAWN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      dawn_status st = graph_wcc(ctx, g.get(), s);
+      hipStreamDestroy(s);
+      if (st != DAWN_OK) return st;
+    }
+    sub = g->wcc_sub;
+    nodes = g->wcc_nodes;
+    p = g->params;
+  }
+  const int32_t S = (int32_t)nodes.size();
+  if (dist && S > 0) {
+    std::vector<int32_t> srcs(S);
+    for (int32_t i = 0; i < S; ++i) srcs[i] = i;   // subgraph ids are WCC ranks
+    DAWN_TRY(mssp_run(ctx, sub.get(), p, srcs.data(), S, dist, (flags & DAWN_DEVICE_OUT) != 0, S,
+                      stats));
+  } else if (stats) {
+    memset(stats, 0, offsetof(dawn_run_stats, frontier_sizes));
+  }
+  memcpy(wcc_nodes, nodes.data(), (size_t)S * 4);
+  *s_wcc = S;
+  return DAWN_OK;
+}
+
+dawn_status dawn_autotune(dawn_ctx* c, int32_t graph, const int32_t* sources, int32_t k,
+                          uint32_t what, dawn_params* best) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (k <= 0 || !sources) return fail(DAWN_E_INVALID_ARG, "need k > 0 sample sources");
+  if (what == 0 || (what & ~3u)) return fail(DAWN_E_INVALID_ARG, "what must be 1, 2 or 3");
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  for (int32_t r = 0; r < k; ++r)
+    if (sources[r] < 0 || sources[r] >= g->n)
+      return fail(DAWN_E_INVALID_ARG, "sources[%d] outside [0, n)", r);
+  DAWN_HIP(hipSetDevice(ctx->device));
+  return autotune(ctx, g.get(), sources, k, what, best);
+}
+
+dawn_status dawn_serve_submit(dawn_ctx* c, int32_t graph, const int32_t* sources, int32_t k,
+                              int32_t* dist_out, uint32_t flags, uint64_t* ticket) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  return serve_submit(C(c), graph, sources, k, dist_out, flags, ticket);
+}
+
+dawn_status dawn_serve_poll(dawn_ctx* c, uint64_t ticket, dawn_query_stats* qs) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  return serve_poll(C(c), ticket, 0, qs);
+}
+
+dawn_status dawn_serve_wait(dawn_ctx* c, uint64_t ticket, int32_t timeout_ms,
+                            dawn_query_stats* qs) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  return serve_poll(C(c), ticket, timeout_ms < 0 ? -1 : std::max(timeout_ms, 1), qs);
+}
+
+}  // extern "C"

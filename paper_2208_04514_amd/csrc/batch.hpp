@@ -1,0 +1,87 @@
+// Shared declarations of the batched (bitmask-lane) traversal, used by the
+// multi-source driver (mssp.hip) and the serving scheduler (serve.cpp).
+#pragma once
+
+#include "internal.hpp"
+
+namespace dawn {
+
+// Counters of one level of a batch (two slots, indexed level & 1).
+struct BatchLevel {
+  u64 nodes;          // nodes that received a new bit
+  u64 bits;           // new (node, source) pairs
+  u64 se;             // sum over new pairs of the node's out-degree
+  u64 mf;             // sum of out-degrees of the nodes with a new bit
+  u64 edges;          // adjacency entries read by the expansion
+  unsigned nfront;    // entries of the frontier node list
+  unsigned nchunks;   // entries of the frontier out-edge chunk list
+};
+
+struct BatchCtrl {
+  BatchLevel lv[2];
+  u64 laneact[2][64]; // OR of the new bits of each word, per level
+};
+
+struct BatchArgs {
+  int32_t n;
+  int32_t W;          // 64-bit words per node row (sources / 64, rounded up)
+  long long m;
+  const int32_t* rp;
+  const int32_t* col;
+  const int32_t* ip;
+  const int32_t* isrc;
+  u64* vis;           // [n][W]
+  u64* nxt[2];        // [n][W] new bits per level parity
+  u64* touched;       // one bit per node: new bits this level
+  int32_t* fl[2];     // frontier node lists per level parity
+  int32_t* cu[2];     // frontier out-edge chunks: node
+  int32_t* ck[2];     //                           chunk index
+  BatchCtrl* ctrl;
+  const u64* act;     // [W] sources still expanding
+  int32_t* const* rows;   // [lanes] distance row of each source (device)
+  const int32_t* base;    // [lanes] level at which each source joined
+};
+
+struct BatchWs {
+  Ctx* ctx = nullptr;
+  int n = 0;
+  int lanes = 0;
+  int Wmax = 0;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  u64* vis = nullptr;
+  u64* nxt[2] = {nullptr, nullptr};
+  u64* touched = nullptr;
+  int32_t* fl[2] = {nullptr, nullptr};
+  int32_t* cu[2] = {nullptr, nullptr};
+  int32_t* ck[2] = {nullptr, nullptr};
+  BatchCtrl* ctrl = nullptr;
+  u64* act = nullptr;
+  int32_t** rows = nullptr;
+  int32_t* base = nullptr;
+  int32_t* src = nullptr;
+  int32_t* stage = nullptr;       // device rows for host-destination calls
+  size_t stage_ints = 0;
+  BatchCtrl* h_ctrl = nullptr;
+};
+
+struct BatchTotals {
+  int levels, push_levels, pull_levels, launches;
+  u64 edges, source_edges, reached;
+  double kernel_ms;
+};
+
+dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage_ints,
+                            BatchWs** out);
+BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W);
+dawn_status batch_launch_expand(Ctx* ctx, const BatchArgs& a, bool pull, int L, hipStream_t s);
+dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t s);
+dawn_status batch_launch_fill(Ctx* ctx, const BatchArgs& a, int r0, int k, hipStream_t s);
+dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
+dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src, int k,
+                              hipStream_t s);
+bool batch_choose_pull(const dawn_params& p, const BatchLevel& last, long long m);
+
+}  // namespace dawn

@@ -1,0 +1,228 @@
+// Internal declarations of libdawn (host runtime + device helpers).
+// Nothing here is part of the C ABI; include/dawn.h is.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dawn.h"
+
+namespace dawn {
+
+// ------------------------------------------------------------------ errors --
+dawn_status fail(dawn_status st, const char* fmt, ...);
+void clear_error();
+
+#define DAWN_HIP(expr)                                                          \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess)                                                       \
+      return ::dawn::fail(DAWN_E_DEVICE, "%s failed: %s (%s:%d)", #expr,       \
+                          hipGetErrorString(_e), __FILE__, __LINE__);           \
+  } while (0)
+
+#define DAWN_TRY(expr)                  \
+  do {                                  \
+    dawn_status _s = (expr);            \
+    if (_s != DAWN_OK) return _s;       \
+  } while (0)
+
+inline uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// ------------------------------------------------------------ device data --
+typedef unsigned long long u64;
+
+// Software grid barrier state (zeroed once at allocation; self-resetting).
+struct GridBarrier {
+  unsigned int count;
+  unsigned int gen;
+  unsigned int abort;         // set when a wait timed out; every later wait returns at once
+  unsigned int pad;
+};
+
+// Counters produced by one level step (ring of three, indexed level % 3).
+struct LevelSlot {
+  unsigned int nf;            // nodes found at this level
+  unsigned int small_count;   // entries appended to the small-degree queue
+  unsigned int big_chunks;    // chunks appended to the big-degree queue
+  unsigned int pad;
+  u64 mf;                     // sum of out-degrees of the nodes found
+  u64 edges;                  // adjacency entries examined
+};
+
+// Level-loop state shared by every workgroup of a traversal.
+struct LevelState {
+  int level;                  // last level executed (0 = seeded)
+  int cur;                    // which visited bitmap is current (0/1)
+  int pull;                   // direction of the next level
+  int done;                   // 0 running, 1 finished, 2 watchdog
+  long long mu;               // out-degree sum of the still-unvisited nodes
+  int last_nonempty;          // last level that found a node
+  int push_levels, pull_levels;
+  int pad;
+  u64 edges_total;
+  u64 source_edges;
+  u64 reached;
+};
+
+struct SsspCtrl {
+  GridBarrier bar;
+  unsigned int ticket;        // last-workgroup detection (per-level kernels)
+  unsigned int pad;
+  LevelSlot slot[3];
+  LevelState st;
+};
+
+// Everything a single-source traversal kernel needs (passed by value).
+struct SsspArgs {
+  int32_t n;
+  int32_t nw;                 // 64-bit words in a visited bitmap
+  long long m;
+  const int32_t* rp;          // CSR row offsets (n+1)
+  const int32_t* col;         // CSR targets (m)
+  const int32_t* ip;          // CSC column offsets (n+1)
+  const int32_t* isrc;        // CSC sources (m)
+  u64* vis0;
+  u64* vis1;
+  int32_t* qs0;               // small-degree queues (level parity 0/1), n entries each
+  int32_t* qs1;
+  int32_t* cu0;               // big-degree chunk lists: node of each chunk
+  int32_t* cu1;
+  int32_t* ck0;               // ... and the chunk's index within the node's row
+  int32_t* ck1;
+  SsspCtrl* ctrl;
+  int32_t* dist;
+  int32_t source;
+  int32_t mode;               // 1 push, 2 pull, 3 switch
+  float alpha, beta;
+  int32_t big_degree;
+  int32_t lane_edges;
+  int32_t* level_nf;          // per-level discovered counts (lrec entries)
+  uint8_t* level_dir;
+  int32_t lrec;
+};
+
+// ----------------------------------------------------------- host objects --
+struct Ctx;
+struct GraphRec;
+
+// Device memory accounted against the context's budget.
+dawn_status dev_alloc(Ctx* ctx, void** p, size_t bytes);
+void dev_free(Ctx* ctx, void* p, size_t bytes);
+
+template <class T>
+dawn_status dev_alloc_n(Ctx* ctx, T** p, size_t count) {
+  return dev_alloc(ctx, (void**)p, count * sizeof(T));
+}
+
+// Per-call buffers of a single-source traversal (pooled per graph).
+struct SsspWs {
+  Ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  u64* vis[2] = {nullptr, nullptr};
+  int32_t* qs[2] = {nullptr, nullptr};
+  int32_t* cu[2] = {nullptr, nullptr};
+  int32_t* ck[2] = {nullptr, nullptr};
+  SsspCtrl* ctrl = nullptr;
+  int32_t* dist = nullptr;      // internal output for host-destination calls
+  int32_t* level_nf = nullptr;
+  uint8_t* level_dir = nullptr;
+  int32_t lrec = 0;
+  bool poisoned = false;        // a launch failed: never reuse these buffers
+  size_t chunk_cap = 0;
+  size_t bytes = 0;
+  SsspCtrl* h_ctrl = nullptr;   // pinned read-back
+  // HIP graph driver cache
+  hipGraphExec_t gexec = nullptr;
+  int gexec_levels = 0;
+  int gexec_block = 0;
+  SsspArgs gexec_args{};        // launch arguments baked into the captured graph
+  ~SsspWs();
+};
+
+struct BatchWs;   // batched traversal buffers (mssp.hip)
+void batch_ws_destroy(BatchWs* ws);
+
+struct GraphRec {
+  Ctx* ctx = nullptr;
+  int32_t id = -1;
+  int32_t n = 0;
+  long long m = 0;
+  int32_t* rp = nullptr;
+  int32_t* col = nullptr;
+  int32_t* ip = nullptr;
+  int32_t* isrc = nullptr;
+  int32_t max_out_deg = 0;
+  int32_t zero_out = 0;
+  size_t bytes = 0;
+  dawn_params params{};
+  std::mutex mu;                          // guards the pools and the WCC cache
+  std::vector<std::unique_ptr<SsspWs>> sssp_pool;
+  std::vector<BatchWs*> batch_pool;
+  // largest-WCC cache (apsp_wcc)
+  bool wcc_ready = false;
+  std::vector<int32_t> wcc_nodes;
+  std::shared_ptr<GraphRec> wcc_sub;      // induced subgraph on the WCC, ids renumbered
+  ~GraphRec();
+};
+
+struct Server;   // serving scheduler (serve.cpp)
+void server_stop(Server* s);
+
+struct Ctx {
+  int device = 0;
+  int num_cu = 0;
+  int coop = 0;
+  uint64_t budget = 0;
+  std::atomic<uint64_t> used{0};
+  std::atomic<long long> fail_after{-1};   // failure injection: allocations left before failing
+  std::mutex mu;
+  std::map<int32_t, std::shared_ptr<GraphRec>> graphs;
+  int32_t next_graph = 0;
+  Server* server = nullptr;
+  std::mutex server_mu;
+};
+
+dawn_status get_graph(Ctx* ctx, int32_t id, std::shared_ptr<GraphRec>* out);
+dawn_params default_params(const GraphRec& g);
+dawn_status check_params(const dawn_params& p);
+
+// graph.hip
+dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_t* h_col);
+dawn_status graph_wcc(Ctx* ctx, GraphRec* g, hipStream_t stream);
+
+// sssp.hip
+dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source,
+                     int32_t* dist, bool device_out, dawn_run_stats* stats);
+
+// mssp.hip
+dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources,
+                     int32_t k, int32_t* dist, bool device_out, int64_t row_stride,
+                     dawn_run_stats* stats);
+
+// tune.cpp
+dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, uint32_t what,
+                     dawn_params* best);
+
+// serve.cpp
+dawn_status serve_submit(Ctx* ctx, int32_t graph, const int32_t* sources, int32_t k,
+                         int32_t* dist_out, uint32_t flags, uint64_t* ticket);
+dawn_status serve_poll(Ctx* ctx, uint64_t ticket, int32_t timeout_ms, dawn_query_stats* qs);
+
+}  // namespace dawn

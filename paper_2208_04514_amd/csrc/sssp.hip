@@ -1,0 +1,686 @@
+// Single-source level loop of DAWN on gfx950.
+//
+// One level step turns the set of nodes found at level L-1 into the set found
+// at level L, in one of two directions:
+//
+//  * push (SOVM, paper Section 3.3, Algorithm 2 and the union-of-rows
+//    identity): every frontier node's out-list is scanned and each target not
+//    yet visited is claimed, gets dist = L and joins the next frontier.  Only
+//    the first claimer of a node wins (an atomic OR on its visited bit), so a
+//    node is queued once.  Frontier nodes with out-degree 0 are never queued
+//    (the paper's processing step 2 skips them).
+//  * pull (BOVM, Section 3.2, Algorithm 1 and the compressed Boolean inner
+//    product): every unvisited node scans its in-list and stops at the first
+//    in-neighbour that is already visited (the early exit after Algorithm 1).
+//    Testing "visited" instead of "in the frontier" gives the same answer: an
+//    unvisited node has distance >= L, and a visited in-neighbour at distance
+//    <= L-1 puts it at exactly L.  New bits go to a second bitmap that becomes
+//    current after the step, so nodes found at level L never label others at
+//    the same level.
+//
+// The loop ends when the nodes found at a level have no out-edges at all
+// (nothing can be expanded), which covers the paper's "the distance vector did
+// not change" stop.  A direction switch in the style of direction-optimising
+// BFS picks push or pull per level from counters of the previous level.
+//
+// Work assignment (64-wide wavefronts):
+//  * frontier nodes with out-degree < big_degree are taken 64 at a time by one
+//    wave; the wave scans their degrees and walks the union of their out-lists
+//    64 edges per step, each lane finding its owner node by a binary search over
+//    the wave's prefix sums (coalesced `col` reads, no idle lanes on skewed
+//    degrees);
+//  * nodes with out-degree >= big_degree are cut into chunks of one workgroup's
+//    width when they are found, and the chunks are spread over every workgroup
+//    of the grid;
+//  * pull gives each wave one 64-bit word of the visited bitmap (64 nodes, one
+//    per lane); a lane scans up to lane_edges in-edges, then the whole wave
+//    takes over the remaining in-list of each lane still searching.
+//
+// Drivers: (1) one persistent cooperative kernel with a software grid barrier
+// between levels, (2) one kernel per level with the counters read back by the
+// host, (3) a HIP graph of level kernels replayed until a device flag says done.
+#include <string.h>
+
+#include <algorithm>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace dawn {
+
+struct Counters {
+  unsigned nf;
+  u64 mf;
+  u64 edges;
+};
+
+__device__ __forceinline__ int32_t* small_q(const SsspArgs& a, int level) {
+  return (level & 1) ? a.qs1 : a.qs0;
+}
+__device__ __forceinline__ int32_t* chunk_u(const SsspArgs& a, int level) {
+  return (level & 1) ? a.cu1 : a.cu0;
+}
+__device__ __forceinline__ int32_t* chunk_k(const SsspArgs& a, int level) {
+  return (level & 1) ? a.ck1 : a.ck0;
+}
+
+// Record node v (claimed at level L by the calling lane when `found`) in the
+// distance vector and in the next frontier.  Must be reached by the whole wave.
+template <int BLOCK>
+__device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool found,
+                                           Counters& c) {
+  int deg = 0;
+  if (found) {
+    a.dist[v] = L;
+    int r0 = a.rp[v];
+    deg = a.rp[v + 1] - r0;
+    c.nf += 1;
+    c.mf += (u64)deg;
+  }
+  LevelSlot* out = &a.ctrl->slot[L % 3];
+  const bool small = found && deg > 0 && deg < a.big_degree;
+  int pos = wave_append(&out->small_count, small);
+  if (small) small_q(a, L)[pos] = v;
+  if (found && deg >= a.big_degree) {
+    unsigned nch = (unsigned)((deg + BLOCK - 1) / BLOCK);
+    unsigned base = atom_add(&out->big_chunks, nch);
+    int32_t* cu = chunk_u(a, L);
+    int32_t* ck = chunk_k(a, L);
+    for (unsigned k = 0; k < nch; ++k) {
+      cu[base + k] = v;
+      ck[base + k] = (int32_t)k;
+    }
+  }
+}
+
+// Claim target v (if `has`) at level L: test, then atomic OR on the visited bit.
+template <int BLOCK>
+__device__ __forceinline__ void visit(const SsspArgs& a, int L, u64* vis, int v, bool has,
+                                      Counters& c) {
+  bool claimed = false;
+  if (has) {
+    c.edges += 1;
+    const u64 bit = 1ull << (v & 63);
+    u64* wp = vis + (v >> 6);
+    if ((*wp & bit) == 0) {
+      u64 old = atom_or(wp, bit);
+      claimed = (old & bit) == 0;
+    }
+  }
+  emit_found<BLOCK>(a, L, v, claimed, c);
+}
+
+template <int BLOCK>
+__device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c) {
+  const LevelSlot* in = &a.ctrl->slot[(L - 1) % 3];
+  const unsigned nsmall = ld_relaxed(&in->small_count);
+  const unsigned nchunks = ld_relaxed(&in->big_chunks);
+
+  // big-degree nodes: one chunk of BLOCK edges per workgroup iteration
+  const int32_t* cu = chunk_u(a, L - 1);
+  const int32_t* ck = chunk_k(a, L - 1);
+  for (unsigned g = blockIdx.x; g < nchunks; g += gridDim.x) {
+    const int u = cu[g];
+    const int k = ck[g];
+    const int start = a.rp[u] + k * BLOCK;
+    const int end = min(start + BLOCK, a.rp[u + 1]);
+    const int e = start + (int)threadIdx.x;
+    const bool has = e < end;
+    const int v = has ? a.col[e] : 0;
+    visit<BLOCK>(a, L, vis, v, has, c);
+  }
+
+  // small-degree nodes: 64 per wave, union of their rows walked 64 edges a step
+  const int lane = lane_id();
+  const int wpb = BLOCK / kWave;
+  const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
+  const unsigned nwaves = gridDim.x * wpb;
+  const int32_t* q = small_q(a, L - 1);
+  for (unsigned base = gw * kWave; base < nsmall; base += nwaves * kWave) {
+    const unsigned i = base + lane;
+    int rs = 0, deg = 0;
+    if (i < nsmall) {
+      const int u = q[i];
+      rs = a.rp[u];
+      deg = a.rp[u + 1] - rs;
+    }
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    for (int eb = 0; eb < total; eb += kWave) {
+      const int x = eb + lane;
+      const bool has = x < total;
+      const int j = wave_owner(incl, has ? x : total - 1);
+      const int inc_j = __shfl(incl, j, kWave);
+      const int deg_j = __shfl(deg, j, kWave);
+      const int rs_j = __shfl(rs, j, kWave);
+      const int v = has ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
+      visit<BLOCK>(a, L, vis, v, has, c);
+    }
+  }
+}
+
+template <int BLOCK>
+__device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, Counters& c) {
+  const int lane = lane_id();
+  const int wpb = BLOCK / kWave;
+  const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
+  const unsigned nwaves = gridDim.x * wpb;
+  for (unsigned w = gw; w < (unsigned)a.nw; w += nwaves) {
+    const u64 word = vin[w];
+    const int v = (int)(w * kWave) + lane;
+    const int valid_n = min(kWave, a.n - (int)(w * kWave));
+    const u64 full = valid_n >= kWave ? ~0ull : ((1ull << valid_n) - 1ull);
+    if ((word & full) == full) {
+      if (lane == 0) vout[w] = word;
+      continue;
+    }
+    bool found = false;
+    bool rest = false;
+    int s = 0, e = 0, lim = 0;
+    if (lane < valid_n && !((word >> lane) & 1ull)) {
+      s = a.ip[v];
+      e = a.ip[v + 1];
+      lim = min(e, s + a.lane_edges);
+      for (int j = s; j < lim; ++j) {
+        const int u = a.isrc[j];
+        c.edges += 1;
+        if ((vin[u >> 6] >> (u & 63)) & 1ull) {
+          found = true;
+          break;
+        }
+      }
+      rest = !found && lim < e;
+    }
+    // the wave finishes long in-lists together, 64 entries a step
+    u64 pending = __ballot(rest);
+    while (pending) {
+      const int j = __ffsll((unsigned long long)pending) - 1;
+      pending &= pending - 1;
+      const int b0 = __shfl(lim, j, kWave);
+      const int b1 = __shfl(e, j, kWave);
+      for (int b = b0; b < b1; b += kWave) {
+        const int idx = b + lane;
+        bool hit = false;
+        if (idx < b1) {
+          const int u = a.isrc[idx];
+          c.edges += 1;
+          hit = (vin[u >> 6] >> (u & 63)) & 1ull;
+        }
+        if (__ballot(hit)) {
+          if (lane == j) found = true;
+          break;
+        }
+      }
+    }
+    const u64 newbits = __ballot(found);
+    if (lane == 0) vout[w] = word | newbits;
+    emit_found<BLOCK>(a, L, v, found, c);
+  }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void flush(const SsspArgs& a, int L, Counters& c) {
+  block_sum3<BLOCK>(c.nf, c.mf, c.edges);
+  if (threadIdx.x == 0) {
+    LevelSlot* out = &a.ctrl->slot[L % 3];
+    if (c.nf) atom_add(&out->nf, c.nf);
+    if (c.mf) atom_add(&out->mf, c.mf);
+    if (c.edges) atom_add(&out->edges, c.edges);
+  }
+  c.nf = 0;
+  c.mf = 0;
+  c.edges = 0;
+}
+
+// Fold level st.level's counters into the state and choose level st.level+1.
+__device__ void decide(const SsspArgs& a, LevelState& st, const LevelSlot& sl, bool record) {
+  const int L = st.level;
+  if (sl.nf > 0) st.last_nonempty = L;
+  st.mu -= (long long)sl.mf;
+  st.edges_total += sl.edges;
+  st.source_edges += sl.mf;
+  st.reached += sl.nf;
+  if (record && L < a.lrec) a.level_nf[L] = (int32_t)sl.nf;
+  if (sl.mf == 0) {
+    st.done = 1;
+    return;
+  }
+  if (L + 1 > a.n) {
+    st.done = 2;
+    return;
+  }
+  bool pull = st.pull;
+  if (a.mode == 1) {
+    pull = false;
+  } else if (a.mode == 2) {
+    pull = true;
+  } else if (!pull) {
+    if ((double)sl.mf * (double)a.alpha > (double)st.mu) pull = true;
+  } else {
+    if ((double)sl.nf * (double)a.beta < (double)a.n) pull = false;
+  }
+  st.pull = pull ? 1 : 0;
+  st.level = L + 1;
+  if (pull) st.pull_levels++; else st.push_levels++;
+  if (record && st.level < a.lrec) a.level_dir[st.level] = pull ? 2 : 1;
+}
+
+__device__ __forceinline__ LevelSlot load_slot(const LevelSlot* s) {
+  LevelSlot r;
+  r.nf = ld_relaxed(&s->nf);
+  r.small_count = ld_relaxed(&s->small_count);
+  r.big_chunks = ld_relaxed(&s->big_chunks);
+  r.pad = 0;
+  r.mf = ld_relaxed(&s->mf);
+  r.edges = ld_relaxed(&s->edges);
+  return r;
+}
+
+__device__ __forceinline__ void zero_slot(LevelSlot* s) {
+  s->nf = 0;
+  s->small_count = 0;
+  s->big_chunks = 0;
+  s->mf = 0;
+  s->edges = 0;
+}
+
+// Seed the source (one thread).
+template <int BLOCK>
+__device__ void seed(const SsspArgs& a) {
+  const int s = a.source;
+  a.dist[s] = 0;
+  a.vis0[s >> 6] |= 1ull << (s & 63);
+  const int deg = a.rp[s + 1] - a.rp[s];
+  LevelSlot* sl = &a.ctrl->slot[0];
+  sl->nf = 1;
+  sl->mf = (u64)deg;
+  sl->edges = 0;
+  sl->small_count = 0;
+  sl->big_chunks = 0;
+  if (deg > 0 && deg < a.big_degree) {
+    a.qs0[0] = s;
+    sl->small_count = 1;
+  } else if (deg >= a.big_degree) {
+    unsigned nch = (unsigned)((deg + BLOCK - 1) / BLOCK);
+    for (unsigned k = 0; k < nch; ++k) {
+      a.cu0[k] = s;
+      a.ck0[k] = (int32_t)k;
+    }
+    sl->big_chunks = nch;
+  }
+  zero_slot(&a.ctrl->slot[1]);
+  zero_slot(&a.ctrl->slot[2]);
+  LevelState& st = a.ctrl->st;
+  st.level = 0;
+  st.cur = 0;
+  st.pull = 0;
+  st.done = 0;
+  st.mu = a.m;
+  st.last_nonempty = 0;
+  st.push_levels = 0;
+  st.pull_levels = 0;
+  st.edges_total = 0;
+  st.source_edges = 0;
+  st.reached = 0;
+  if (a.lrec > 0) a.level_dir[0] = 0;
+}
+
+__device__ __forceinline__ void init_fill(const SsspArgs& a) {
+  const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nt = gridDim.x * blockDim.x;
+  for (unsigned i = tid; i < (unsigned)a.n; i += nt) a.dist[i] = -1;
+  for (unsigned w = tid; w < (unsigned)a.nw; w += nt) a.vis0[w] = 0;
+}
+
+// ------------------------------------------------------- persistent driver --
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a) {
+  init_fill(a);
+  if (!grid_sync(&a.ctrl->bar)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) seed<BLOCK>(a);
+  if (!grid_sync(&a.ctrl->bar)) return;
+
+  LevelState st;
+  st.level = 0; st.cur = 0; st.pull = 0; st.done = 0; st.mu = a.m; st.last_nonempty = 0;
+  st.push_levels = 0; st.pull_levels = 0; st.edges_total = 0; st.source_edges = 0; st.reached = 0;
+  Counters c{0, 0, 0};
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  for (;;) {
+    const LevelSlot prev = load_slot(&a.ctrl->slot[st.level % 3]);
+    decide(a, st, prev, leader);
+    if (st.done) break;
+    const int L = st.level;
+    u64* vcur = st.cur ? a.vis1 : a.vis0;
+    if (st.pull) {
+      u64* vnext = st.cur ? a.vis0 : a.vis1;
+      pull_step<BLOCK>(a, L, vcur, vnext, c);
+      st.cur ^= 1;
+    } else {
+      push_step<BLOCK>(a, L, vcur, c);
+    }
+    flush<BLOCK>(a, L, c);
+    if (leader) zero_slot(&a.ctrl->slot[(L + 1) % 3]);
+    if (!grid_sync(&a.ctrl->bar)) return;
+  }
+  if (leader) a.ctrl->st = st;
+}
+
+// ------------------------------------------------------ per-level drivers --
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sssp_init_fill(SsspArgs a) { init_fill(a); }
+
+template <int BLOCK>
+__global__ void sssp_seed(SsspArgs a) {
+  if (threadIdx.x == 0) {
+    seed<BLOCK>(a);
+    // choose level 1 from the seed's counters
+    LevelState st = a.ctrl->st;
+    decide(a, st, a.ctrl->slot[0], true);
+    a.ctrl->st = st;
+    a.ctrl->ticket = 0;
+  }
+}
+
+// One level: state was chosen by the previous launch's last workgroup.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a) {
+  const LevelState st0 = a.ctrl->st;
+  if (st0.done) return;
+  const int L = st0.level;
+  Counters c{0, 0, 0};
+  u64* vcur = st0.cur ? a.vis1 : a.vis0;
+  if (st0.pull) {
+    u64* vnext = st0.cur ? a.vis0 : a.vis1;
+    pull_step<BLOCK>(a, L, vcur, vnext, c);
+  } else {
+    push_step<BLOCK>(a, L, vcur, c);
+  }
+  flush<BLOCK>(a, L, c);
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = atom_add(&a.ctrl->ticket, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    LevelState st = st0;
+    if (st.pull) st.cur ^= 1;
+    zero_slot(&a.ctrl->slot[(L + 1) % 3]);
+    const LevelSlot cur = load_slot(&a.ctrl->slot[L % 3]);
+    decide(a, st, cur, true);
+    a.ctrl->st = st;
+    a.ctrl->ticket = 0;
+    __threadfence();
+  }
+}
+
+// ------------------------------------------------------------------ host --
+SsspWs::~SsspWs() {
+  if (gexec) hipGraphExecDestroy(gexec);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(ctx, vis[i], 0);
+    dev_free(ctx, qs[i], 0);
+    dev_free(ctx, cu[i], 0);
+    dev_free(ctx, ck[i], 0);
+  }
+  dev_free(ctx, ctrl, 0);
+  dev_free(ctx, dist, 0);
+  dev_free(ctx, level_nf, 0);
+  dev_free(ctx, level_dir, 0);
+  if (ctx) ctx->used -= bytes;
+  if (h_ctrl) hipHostFree(h_ctrl);
+  if (ev0) hipEventDestroy(ev0);
+  if (ev1) hipEventDestroy(ev1);
+  if (stream) hipStreamDestroy(stream);
+}
+
+static dawn_status ws_create(Ctx* ctx, GraphRec* g, std::unique_ptr<SsspWs>* out) {
+  std::unique_ptr<SsspWs> w(new SsspWs());
+  w->ctx = ctx;
+  const int n = g->n;
+  const size_t nw = ((size_t)n + 63) / 64;
+  // chunk lists: every node of out-degree >= 64 could be "big" at the smallest
+  // block size; sum of ceil(deg/64) <= m/64 + n/64 + 1
+  // at most m/64 big nodes (big_degree >= 64), and at most m/256 chunks of
+  // >= 256 edges plus one partial chunk per big node
+  const size_t chunk_cap = (size_t)(g->m / 32) + 64;
+  w->chunk_cap = chunk_cap;
+  w->lrec = std::min(n + 1, 1 << 16);
+  SsspWs* wp = w.get();
+  auto alloc = [&](void** p, size_t bytes) -> dawn_status {
+    dawn_status s = dev_alloc(ctx, p, bytes);
+    if (s == DAWN_OK) wp->bytes += bytes;
+    return s;
+  };
+  dawn_status s = DAWN_OK;
+  for (int i = 0; i < 2 && s == DAWN_OK; ++i) {
+    if ((s = alloc((void**)&w->vis[i], nw * 8 + 256)) != DAWN_OK) break;
+    if ((s = alloc((void**)&w->qs[i], (size_t)n * 4 + 256)) != DAWN_OK) break;
+    if ((s = alloc((void**)&w->cu[i], chunk_cap * 4)) != DAWN_OK) break;
+    if ((s = alloc((void**)&w->ck[i], chunk_cap * 4)) != DAWN_OK) break;
+  }
+  if (s == DAWN_OK) s = alloc((void**)&w->ctrl, sizeof(SsspCtrl));
+  if (s == DAWN_OK) s = alloc((void**)&w->dist, (size_t)n * 4);
+  if (s == DAWN_OK) s = alloc((void**)&w->level_nf, (size_t)w->lrec * 4);
+  if (s == DAWN_OK) s = alloc((void**)&w->level_dir, (size_t)w->lrec);
+  // the destructor frees each buffer and returns `bytes` to the budget at once
+  if (s != DAWN_OK) return s;
+  DAWN_HIP(hipMemset(w->ctrl, 0, sizeof(SsspCtrl)));
+  DAWN_HIP(hipHostMalloc((void**)&w->h_ctrl, sizeof(SsspCtrl), hipHostMallocDefault));
+  DAWN_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+  DAWN_HIP(hipEventCreate(&w->ev0));
+  DAWN_HIP(hipEventCreate(&w->ev1));
+  *out = std::move(w);
+  return DAWN_OK;
+}
+
+static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
+                      int32_t source, int32_t* dist) {
+  memset(&a, 0, sizeof(a));
+  a.n = g->n;
+  a.nw = (g->n + 63) / 64;
+  a.m = g->m;
+  a.rp = g->rp;
+  a.col = g->col;
+  a.ip = g->ip;
+  a.isrc = g->isrc;
+  a.vis0 = w->vis[0];
+  a.vis1 = w->vis[1];
+  a.qs0 = w->qs[0];
+  a.qs1 = w->qs[1];
+  a.cu0 = w->cu[0];
+  a.cu1 = w->cu[1];
+  a.ck0 = w->ck[0];
+  a.ck1 = w->ck[1];
+  a.ctrl = w->ctrl;
+  a.dist = dist;
+  a.source = source;
+  a.mode = p.direction;
+  a.alpha = p.alpha;
+  a.beta = p.beta;
+  a.big_degree = std::max(p.big_degree, 64);
+  a.lane_edges = std::max(p.pull_lane_edges, 1);
+  a.level_nf = w->level_nf;
+  a.level_dir = w->level_dir;
+  a.lrec = w->lrec;
+}
+
+template <int BLOCK>
+static dawn_status launch_persistent(Ctx* ctx, SsspWs* w, const SsspArgs& a, int blocks_per_cu,
+                                     bool single) {
+  int occ = 0;
+  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_persistent<BLOCK>, BLOCK, 0));
+  if (occ < 1) return fail(DAWN_E_DEVICE, "persistent kernel cannot be resident");
+  int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ;
+  int grid = single ? 1 : per_cu * ctx->num_cu;
+  SsspArgs args = a;
+  void* kargs[] = {&args};
+  DAWN_HIP(hipLaunchCooperativeKernel((const void*)sssp_persistent<BLOCK>, dim3(grid),
+                                      dim3(BLOCK), kargs, 0, w->stream));
+  return DAWN_OK;
+}
+
+template <int BLOCK>
+static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, int driver,
+                              int graph_levels, int* launches) {
+  const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
+  hipLaunchKernelGGL(sssp_init_fill<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+  hipLaunchKernelGGL(sssp_seed<BLOCK>, dim3(1), dim3(64), 0, w->stream, a);
+  DAWN_HIP(hipGetLastError());
+  *launches = 2;
+  const long long max_launch = (long long)a.n + 2;
+  if (driver == 2) {
+    for (long long it = 0; it <= max_launch; ++it) {
+      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a);
+      DAWN_HIP(hipGetLastError());
+      ++*launches;
+      DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st, &w->ctrl->st, sizeof(LevelState),
+                              hipMemcpyDeviceToHost, w->stream));
+      DAWN_HIP(hipStreamSynchronize(w->stream));
+      if (w->h_ctrl->st.done) return DAWN_OK;
+    }
+    return fail(DAWN_E_DEVICE, "level loop did not terminate");
+  }
+  // driver 3: HIP graph of `graph_levels` level launches, replayed until done
+  // level launches bake their arguments in: recapture when any of them changed
+  SsspArgs key = a;
+  key.source = 0;
+  if (w->gexec && (w->gexec_levels != graph_levels || w->gexec_block != BLOCK ||
+                   memcmp(&w->gexec_args, &key, sizeof(SsspArgs)) != 0)) {
+    hipGraphExecDestroy(w->gexec);
+    w->gexec = nullptr;
+  }
+  if (!w->gexec) {
+    if (w->gexec) {
+      hipGraphExecDestroy(w->gexec);
+      w->gexec = nullptr;
+    }
+    hipStream_t cs = nullptr;
+    DAWN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < graph_levels; ++i)
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&w->gexec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(DAWN_E_DEVICE, "HIP graph build: %s", hipGetErrorString(e));
+    w->gexec_levels = graph_levels;
+    w->gexec_block = BLOCK;
+    w->gexec_args = key;
+  }
+  for (long long it = 0; it * graph_levels <= max_launch; ++it) {
+    DAWN_HIP(hipGraphLaunch(w->gexec, w->stream));
+    *launches += graph_levels;
+    DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st, &w->ctrl->st, sizeof(LevelState),
+                            hipMemcpyDeviceToHost, w->stream));
+    DAWN_HIP(hipStreamSynchronize(w->stream));
+    if (w->h_ctrl->st.done) return DAWN_OK;
+  }
+  return fail(DAWN_E_DEVICE, "level loop did not terminate");
+}
+
+template <int BLOCK>
+static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_params& p,
+                                 SsspArgs& a, int* launches) {
+  const bool single = g->n <= p.small_n;
+  if (p.driver == 1 || single) {
+    *launches = 1;
+    return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, single);
+  }
+  int occ = 0;
+  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, 0));
+  int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
+  return run_levels<BLOCK>(ctx, w, a, per_cu * ctx->num_cu, p.driver, std::max(p.graph_levels, 1),
+                           launches);
+}
+
+dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source, int32_t* dist,
+                     bool device_out, dawn_run_stats* stats) {
+  const uint64_t t0 = now_ns();
+  std::unique_ptr<SsspWs> w;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->sssp_pool.empty()) {
+      w = std::move(g->sssp_pool.back());
+      g->sssp_pool.pop_back();
+    }
+  }
+  if (!w) DAWN_TRY(ws_create(ctx, g, &w));
+  struct Return {
+    GraphRec* g;
+    std::unique_ptr<SsspWs>& w;
+    ~Return() {
+      if (w && !w->poisoned) {
+        std::lock_guard<std::mutex> lk(g->mu);
+        g->sssp_pool.push_back(std::move(w));
+      }
+    }
+  } ret{g, w};
+
+  int32_t* d_dist = device_out ? dist : w->dist;
+  SsspArgs a;
+  fill_args(a, g, w.get(), p, source, d_dist);
+  int launches = 0;
+  DAWN_HIP(hipEventRecord(w->ev0, w->stream));
+  dawn_status st;
+  switch (p.block) {
+    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, &launches); break;
+    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, &launches); break;
+    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, &launches); break;
+  }
+  if (st != DAWN_OK) {
+    hipStreamSynchronize(w->stream);
+    w->poisoned = true;
+    return st;
+  }
+  DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+  DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(SsspCtrl), hipMemcpyDeviceToHost,
+                          w->stream));
+  const int32_t cap = (stats && stats->frontier_cap > 0) ? std::min(stats->frontier_cap, w->lrec) : 0;
+  std::vector<int32_t> lnf;
+  std::vector<uint8_t> ldir;
+  if (cap > 0) {
+    lnf.resize(cap);
+    ldir.resize(cap);
+    DAWN_HIP(hipMemcpyAsync(lnf.data(), w->level_nf, cap * 4, hipMemcpyDeviceToHost, w->stream));
+    DAWN_HIP(hipMemcpyAsync(ldir.data(), w->level_dir, cap, hipMemcpyDeviceToHost, w->stream));
+  }
+  DAWN_HIP(hipStreamSynchronize(w->stream));
+  const LevelState& rs = w->h_ctrl->st;
+  if (rs.done != 1) w->poisoned = true;
+  if (w->h_ctrl->bar.abort) return fail(DAWN_E_DEVICE, "grid barrier timed out");
+  if (rs.done == 2) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
+  if (rs.done != 1) return fail(DAWN_E_DEVICE, "level loop ended without finishing");
+  if (!device_out) {
+    DAWN_HIP(hipMemcpyAsync(dist, w->dist, (size_t)g->n * 4, hipMemcpyDeviceToHost, w->stream));
+    DAWN_HIP(hipStreamSynchronize(w->stream));
+  }
+  if (stats) {
+    float ms = 0.f;
+    DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    stats->levels = rs.last_nonempty + 1;
+    stats->push_levels = rs.push_levels;
+    stats->pull_levels = rs.pull_levels;
+    stats->launches = launches;
+    stats->edges_examined = (int64_t)rs.edges_total;
+    stats->source_edges = (int64_t)rs.source_edges;
+    stats->reached = (int64_t)rs.reached;
+    stats->kernel_ms = ms;
+    const int32_t nl = std::min(cap, stats->levels);
+    if (cap > 0 && stats->frontier_sizes)
+      for (int i = 0; i < nl; ++i) stats->frontier_sizes[i] = lnf[i];
+    if (cap > 0 && stats->directions)
+      for (int i = 0; i < nl; ++i) stats->directions[i] = ldir[i];
+    stats->total_ms = (now_ns() - t0) / 1e6;
+  }
+  return DAWN_OK;
+}
+
+}  // namespace dawn

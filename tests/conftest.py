@@ -29,3 +29,47 @@ def load_golden(name):
             elif t[0] == "d":
                 rows[int(t[1])] = np.array([int(x) for x in t[2:]], dtype=np.int32)
     return n, edges, rows
+
+
+def header_functions():
+    """Names of the functions declared in include/dawn.h."""
+    import re
+    with open(os.path.join(ROOT, "include", "dawn.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dawn_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="session")
+def dawn_lib():
+    from paper_2208_04514_amd import dawn as D
+    return D.load()
+
+
+@pytest.fixture(scope="session")
+def ctx(dawn_lib):
+    """One context on device 0 for the whole GPU session (fails loudly without a GPU)."""
+    from paper_2208_04514_amd import dawn as D
+    h = D.dawn_create(0, 0)
+    yield h
+    D.dawn_destroy(h)
+
+
+_GRAPHS = {}
+
+
+@pytest.fixture(scope="session")
+def upload(ctx):
+    """upload(name_or_graph) -> (graph handle, Graph, sources); cached per session."""
+    import graphgen as gg
+    from paper_2208_04514_amd import dawn as D
+
+    def _up(key):
+        if isinstance(key, str):
+            if key not in _GRAPHS:
+                g, src = gg.load_config(key)
+                _GRAPHS[key] = (D.dawn_graph_upload(ctx, g.row_ptr, g.col), g, src)
+            return _GRAPHS[key]
+        g = key
+        return D.dawn_graph_upload(ctx, g.row_ptr, g.col), g, None
+    return _up

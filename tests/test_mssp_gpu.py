@@ -1,0 +1,162 @@
+"""Batched multi-source parity: every row of dawn_mssp equals the oracle's row for its source."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from paper_2208_04514_amd import dawn as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _check_rows(g, sources, got, stats=None, threads=16):
+    want = oracle.mssp(g, sources, threads=threads)
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        r, v = bad[0]
+        raise AssertionError(f"{len(bad)} mismatches; first row {r} (source {sources[r]}) node {v}: "
+                             f"got {got[r, v]} want {want[r, v]}")
+    if stats is not None:
+        deg = g.out_degree()
+        reached = want >= 0
+        assert stats["reached"] == int(reached.sum())
+        assert stats["source_edges"] == int((reached.astype(np.int64) @ deg).sum())
+        assert stats["levels"] == int(want.max()) + 1
+    return want
+
+
+@pytest.fixture
+def params(ctx):
+    saved = []
+
+    def _set(h, **kw):
+        saved.append((h, D.dawn_get_params(ctx, h)))
+        return D.dawn_set_params(ctx, h, **kw)
+    yield _set
+    for h, p in reversed(saved):
+        D.dawn_set_params(ctx, h, **p)
+
+
+@pytest.mark.parametrize("k", [1, 2, 63, 64, 65, 127, 200])
+@pytest.mark.parametrize("direction", [1, 2, 3])
+def test_widths_and_directions(ctx, upload, params, k, direction):
+    h, g, _ = upload("rmat12")
+    params(h, direction=direction)
+    src = gg.sample_sources(g.n, k, 1000 + k)
+    _say(f"[mssp] rmat12 k={k} direction={direction}")
+    got, st = D.dawn_mssp(ctx, h, src)
+    _check_rows(g, src, got, st)
+
+
+@pytest.mark.parametrize("name", ["uniform4096", "grid128", "grid128ns"])
+@pytest.mark.parametrize("direction", [1, 2, 3])
+def test_workloads(ctx, upload, params, name, direction):
+    h, g, src = upload(name)
+    params(h, direction=direction)
+    srcs = gg.sample_sources(g.n, 300, 77)
+    _say(f"[mssp] {name} k=300 direction={direction}")
+    got, st = D.dawn_mssp(ctx, h, srcs)
+    _check_rows(g, srcs, got, st)
+
+
+def test_duplicates_and_isolated_sources(ctx, upload, params):
+    h, g, src = upload("rmat12")
+    deg = g.out_degree()
+    zero = np.nonzero(deg == 0)[0][:5].astype(np.int32)
+    srcs = np.concatenate([src[:10], src[:10], zero, src[:3]]).astype(np.int32)
+    got, st = D.dawn_mssp(ctx, h, srcs)
+    want = _check_rows(g, srcs, got, st)
+    assert np.array_equal(got[:10], got[10:20])
+    for r in range(20, 20 + zero.size):
+        assert got[r, srcs[r]] == 0 and (np.delete(got[r], srcs[r]) == -1).all()
+
+
+def test_permutation_permutes_rows(ctx, upload):
+    h, g, src = upload("rmat12")
+    srcs = src[:40]
+    a, _ = D.dawn_mssp(ctx, h, srcs)
+    p = np.random.default_rng(3).permutation(srcs.size)
+    b, _ = D.dawn_mssp(ctx, h, srcs[p])
+    assert np.array_equal(a[p], b)
+
+
+def test_many_batches(ctx, upload, params):
+    # more sources than one batch holds: batches of 64 lanes, ragged tail
+    h, g, _ = upload("uniform4096")
+    params(h, batch_lanes=64)
+    srcs = gg.sample_sources(g.n, 64 * 3 + 17, 5)
+    got, st = D.dawn_mssp(ctx, h, srcs)
+    _check_rows(g, srcs, got, st)
+
+
+@pytest.mark.parametrize("k", [4095, 4096, 4097, 5000])
+def test_batch_edges(ctx, upload, k):
+    h, g, _ = upload("uniform4096")
+    srcs = np.concatenate([np.arange(g.n), np.arange(g.n)])[:k].astype(np.int32)
+    _say(f"[mssp] uniform4096 k={k}")
+    got, st = D.dawn_mssp(ctx, h, srcs)
+    _check_rows(g, srcs, got, st)
+
+
+def test_k_zero_and_errors(ctx, upload):
+    h, g, _ = upload("uniform4096")
+    out, st = D.dawn_mssp(ctx, h, np.empty(0, np.int32))
+    assert out.shape == (0, g.n)
+    buf = np.full((2, g.n), 55, np.int32)
+    with pytest.raises(D.DawnError) as ei:
+        D.dawn_mssp(ctx, h, np.array([0, g.n], np.int32), out=buf)
+    assert ei.value.status == D.DAWN_E_INVALID_ARG
+    assert (buf == 55).all()
+
+
+def test_device_output(ctx, upload):
+    import torch
+    h, g, src = upload("rmat12")
+    out = torch.full((src.size, g.n), 9, dtype=torch.int32, device="cuda")
+    D.dawn_mssp(ctx, h, src, out=out)
+    torch.cuda.synchronize()
+    _check_rows(g, src, out.cpu().numpy())
+
+
+def test_mssp_matches_sssp(ctx, upload):
+    h, g, src = upload("grid128")
+    got, _ = D.dawn_mssp(ctx, h, src[:8])
+    for r, s in enumerate(src[:8]):
+        row, _ = D.dawn_sssp(ctx, h, int(s))
+        assert np.array_equal(row, got[r])
+
+
+def test_full_size_rmat18_4096(ctx, upload):
+    """The batched workload at full size: R-MAT 18, 4096 sources in one launch.
+
+    The oracle runs 64 sampled rows (all 4096 would take minutes of CPU); every
+    row is also checked against properties that hold at any size."""
+    import torch
+    h, g, src = upload("rmat18")
+    assert src.size == 4096
+    out = torch.empty((4096, g.n), dtype=torch.int32, device="cuda")
+    _say("[mssp] rmat18 4096 sources")
+    _, st = D.dawn_mssp(ctx, h, src, out=out)
+    torch.cuda.synchronize()
+    _say(f"  levels {st['levels']} push {st['push_levels']} pull {st['pull_levels']} "
+         f"kernel {st['kernel_ms']:.2f} ms GTEPS {st['source_edges'] / st['kernel_ms'] / 1e6:.1f}")
+    pick = np.random.default_rng(11).choice(4096, size=64, replace=False)
+    sub = out[torch.as_tensor(pick, device="cuda")].cpu().numpy()
+    _check_rows(g, src[pick], sub)
+    # any-size properties on every row: dist[s] = 0, and the reached set is the
+    # source's WCC (the graph is symmetric), so every row reaches the same set
+    full = out.cpu().numpy()
+    assert (full[np.arange(4096), src] == 0).all()
+    reach = full >= 0
+    assert (reach == reach[0]).all()
+    wcc = np.zeros(g.n, bool)
+    wcc[g.meta["wcc_nodes"]] = True
+    assert np.array_equal(reach[0], wcc)
+    deg = g.out_degree()
+    assert st["source_edges"] == 4096 * int(deg[wcc].sum())

@@ -1,0 +1,229 @@
+"""Single-source parity: the HIP path through the C ABI vs the CPU oracle, bit for bit.
+
+Distances are integers, so the bar is exact equality (tolerance 0).  Every
+forced variant (driver, direction, workgroup size, big-degree threshold,
+pull lane budget) must give the oracle's row; the per-level counters must
+match the oracle's distance histogram.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from conftest import load_golden
+from paper_2208_04514_amd import dawn as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _check_row(g, s, got, stats=None, all_push=False):
+    want = oracle.sssp(g, int(s))
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError(f"source {s}: {bad.size} mismatches, first at {bad[:5]}: "
+                             f"got {got[bad[:5]]} want {want[bad[:5]]}")
+    if stats is not None:
+        lv = int(want.max()) + 1
+        assert stats["levels"] == lv
+        deg = g.out_degree()
+        assert stats["reached"] == int((want >= 0).sum())
+        assert stats["source_edges"] == int(deg[want >= 0].sum())
+        if "frontier_sizes" in stats:
+            hist = np.bincount(want[want >= 0], minlength=lv)
+            assert stats["frontier_sizes"] == hist[: len(stats["frontier_sizes"])].tolist()
+        if all_push:
+            # every out-edge of every reached node is examined exactly once
+            assert stats["edges_examined"] == int(deg[want >= 0].sum())
+    return want
+
+
+VARIANTS = [
+    dict(driver=1, direction=3), dict(driver=1, direction=1), dict(driver=1, direction=2),
+    dict(driver=2, direction=3), dict(driver=2, direction=1), dict(driver=2, direction=2),
+    dict(driver=3, direction=3, graph_levels=4), dict(driver=3, direction=1, graph_levels=16),
+    dict(driver=1, direction=3, block=512), dict(driver=1, direction=3, block=1024),
+    dict(driver=1, direction=1, big_degree=64), dict(driver=2, direction=1, big_degree=64, block=1024),
+    dict(driver=1, direction=2, pull_lane_edges=1), dict(driver=1, direction=3, alpha=1e6, beta=1e-3),
+    dict(driver=1, direction=3, blocks_per_cu=1), dict(driver=1, direction=3, small_n=1 << 30),
+]
+
+
+@pytest.fixture
+def restore(ctx):
+    touched = []
+
+    def _set(graph, **kw):
+        if graph not in [t[0] for t in touched]:
+            touched.append((graph, D.dawn_get_params(ctx, graph)))
+        return D.dawn_set_params(ctx, graph, **kw)
+    yield _set
+    for graph, p in touched:
+        D.dawn_set_params(ctx, graph, **p)
+
+
+@pytest.mark.parametrize("name", ["uniform4096", "rmat12", "grid128", "grid128ns"])
+@pytest.mark.parametrize("vi", range(len(VARIANTS)))
+def test_variants_bit_exact(ctx, upload, restore, name, vi):
+    h, g, src = upload(name)
+    v = VARIANTS[vi]
+    _say(f"[sssp] {name} variant {v}")
+    restore(h, **v)
+    for s in src[:4]:
+        got, st = D.dawn_sssp(ctx, h, int(s), frontier_cap=4096)
+        _check_row(g, s, got, st, all_push=(v.get("direction") == 1))
+        dirs = st["directions"]
+        if v.get("direction") == 1:
+            assert set(dirs[1:]) <= {1}
+        if v.get("direction") == 2:
+            assert set(dirs[1:]) <= {2}
+
+
+def test_all_sources_default(ctx, upload):
+    h, g, src = upload("uniform4096")
+    for s in src:
+        got, st = D.dawn_sssp(ctx, h, int(s), frontier_cap=64)
+        _check_row(g, s, got, st)
+
+
+@pytest.mark.parametrize("name", ["hand_directed10.txt", "petersen.txt"])
+def test_golden_graphs(ctx, name):
+    n, edges, rows = load_golden(name)
+    g = gg.gen_edges(n, edges, drop_self=False, dedupe=False)
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    try:
+        for s, want in rows.items():
+            for direction in (1, 2, 3):
+                D.dawn_set_params(ctx, h, direction=direction)
+                got, _ = D.dawn_sssp(ctx, h, s)
+                assert np.array_equal(got, want), (name, s, direction)
+    finally:
+        D.dawn_graph_release(ctx, h)
+
+
+def test_tiny_random_graphs(ctx):
+    rng = np.random.default_rng(7)
+    for i in range(40):
+        n = int(rng.integers(1, 200))
+        m = int(rng.integers(0, 4 * n))
+        e = rng.integers(0, n, size=(m, 2))
+        g = gg.gen_edges(n, e, symmetrize=bool(i % 2), drop_self=False, dedupe=bool(i % 3))
+        h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+        try:
+            for direction, driver in itertools.product((1, 2, 3), (1, 2)):
+                D.dawn_set_params(ctx, h, direction=direction, driver=driver)
+                for s in sorted(set(rng.integers(0, n, size=3).tolist())):
+                    got, st = D.dawn_sssp(ctx, h, s, frontier_cap=256)
+                    _check_row(g, s, got, st, all_push=(direction == 1))
+        finally:
+            D.dawn_graph_release(ctx, h)
+
+
+def test_edge_cases(ctx):
+    # single node, no edges
+    g = gg.gen_edges(1, np.zeros((0, 2), np.int64))
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    got, st = D.dawn_sssp(ctx, h, 0)
+    assert got.tolist() == [0] and st["levels"] == 1
+    D.dawn_graph_release(ctx, h)
+    # out-degree-0 source in a star; a hub whose out-degree exceeds every chunk size
+    n = 5000
+    g = gg.gen_edges(n, [(0, i) for i in range(1, n)] + [(i, 0) for i in range(1, 50)])
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    try:
+        for s in (0, 7, 60):
+            for direction in (1, 2, 3):
+                D.dawn_set_params(ctx, h, direction=direction, big_degree=64)
+                got, st = D.dawn_sssp(ctx, h, s, frontier_cap=16)
+                _check_row(g, s, got, st, all_push=(direction == 1))
+    finally:
+        D.dawn_graph_release(ctx, h)
+    # n not a multiple of 64, a long directed path (many levels)
+    n = 3001
+    g = gg.gen_edges(n, [(i, i + 1) for i in range(n - 1)])
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    try:
+        for driver in (1, 2, 3):
+            D.dawn_set_params(ctx, h, driver=driver, graph_levels=64)
+            got, st = D.dawn_sssp(ctx, h, 5, frontier_cap=8)
+            _check_row(g, 5, got, st)
+            assert st["levels"] == n - 5
+    finally:
+        D.dawn_graph_release(ctx, h)
+
+
+def test_device_output_torch(ctx, upload):
+    import torch
+    h, g, src = upload("rmat12")
+    out = torch.full((3, g.n), 7, dtype=torch.int32, device="cuda")
+    for r, s in enumerate(src[:3]):
+        D.dawn_sssp(ctx, h, int(s), out=out[r])
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for r, s in enumerate(src[:3]):
+        _check_row(g, s, got[r])
+
+
+def test_errors_leave_output_untouched(ctx, upload):
+    h, g, src = upload("uniform4096")
+    out = np.full(g.n, 123, np.int32)
+    for bad in (-1, g.n):
+        with pytest.raises(D.DawnError) as ei:
+            D.dawn_sssp(ctx, h, bad, out=out)
+        assert ei.value.status == D.DAWN_E_INVALID_ARG
+    with pytest.raises(D.DawnError) as ei:
+        D.dawn_sssp(ctx, 987654, 0, out=out)
+    assert ei.value.status == D.DAWN_E_NOT_FOUND
+    assert (out == 123).all()
+
+
+def test_bad_graphs_rejected(ctx):
+    cases = [
+        (np.array([1, 1], np.int32), np.array([0], np.int32)),          # row_ptr[0] != 0
+        (np.array([0, 2, 1], np.int32), np.array([0, 1], np.int32)),    # decreasing
+        (np.array([0, 1, 1], np.int32), np.array([5], np.int32)),       # col out of range
+        (np.array([0, 1, 2], np.int32), np.array([0, -1], np.int32)),
+    ]
+    for rp, col in cases:
+        with pytest.raises(D.DawnError) as ei:
+            D.dawn_graph_upload(ctx, rp, col)
+        assert ei.value.status == D.DAWN_E_BAD_GRAPH
+    lib = D.load()
+    gid = __import__("ctypes").c_int32(-1)
+    rp = np.array([0, 1], np.int32)
+    col = np.array([0], np.int32)
+    st = lib.dawn_graph_upload(ctx, 1, 2, rp.ctypes.data, col.ctypes.data, 0, gid)  # m != row_ptr[n]
+    assert st == D.DAWN_E_BAD_GRAPH
+    st = lib.dawn_graph_upload(ctx, 0, 0, rp.ctypes.data, col.ctypes.data, 0, gid)
+    assert st == D.DAWN_E_INVALID_ARG
+
+
+def test_repeat_runs_identical(ctx, upload):
+    h, g, src = upload("rmat12")
+    a, _ = D.dawn_sssp(ctx, h, int(src[0]))
+    for _ in range(5):
+        b, _ = D.dawn_sssp(ctx, h, int(src[0]))
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,count", [("rmat20", 4), ("grid2048", 2)])
+def test_full_size(ctx, upload, name, count):
+    h, g, src = upload(name)
+    _say(f"[sssp] full size {name} n={g.n} m={g.m}")
+    for s in src[:count]:
+        got, st = D.dawn_sssp(ctx, h, int(s), frontier_cap=8192)
+        want = _check_row(g, s, got, st)
+        _say(f"  source {s}: levels {st['levels']} push {st['push_levels']} "
+             f"pull {st['pull_levels']} kernel {st['kernel_ms']:.3f} ms")
+    # the other drivers on one source
+    for driver in (2, 3):
+        D.dawn_set_params(ctx, h, driver=driver, graph_levels=32)
+        got, st = D.dawn_sssp(ctx, h, int(src[0]))
+        _check_row(g, src[0], got)
+    D.dawn_set_params(ctx, h, driver=1)
