@@ -1,0 +1,209 @@
+"""Benchmark: GTEPS of DAWN's level loop on one MI355X.
+
+Headline (``value``): plain per-source SSSP on R-MAT scale 20 (1,048,576 nodes,
+edge factor 16, a/b/c/d = .57/.19/.19/.05, symmetrised, de-duplicated), 64
+sources from the largest WCC, run one source at a time through ``dawn_sssp``
+with device-resident output.  One step = the 64 sources.  GTEPS counts, per
+source, the out-degrees of every reached node (the SOVM cost E_wcc(s)), summed
+over sources, per second.
+
+Also reported on the same JSON line: the batched form (R-MAT scale 18, 4096
+sources in one ``dawn_mssp`` launch) and the same 4096 sources run plain, the
+roofline of the level-step kernel, and the CPU oracle timed on a bounded
+sample on the host cores.
+
+Inputs are seeded synthetic graphs (the paper's SuiteSparse/Gunrock graphs
+are not available here).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def plain_alg_bytes(g, dist_rows, levels) -> float:
+    """Bytes the push-only level loop must move per the method (all sources summed).
+
+    4 B per out-edge of every reached node (col), 16 B per reached node
+    (row_ptr pair, dist write, queue write and read) and one visited-bitmap
+    pass (n/8 B) per level; the -1 fill of dist belongs to the init kernel.
+    """
+    deg = g.out_degree()
+    total = 0.0
+    for d, lv in zip(dist_rows, levels):
+        reached = d >= 0
+        total += 4.0 * deg[reached].sum() + 16.0 * reached.sum() + lv * g.n / 8.0
+    return total
+
+
+def run_plain(D, ctx, h, g, src, out, steps, warmup):
+    for _ in range(warmup):
+        for i, s in enumerate(src):
+            D.dawn_sssp(ctx, h, int(s), out=out[i])
+    import torch
+    torch.cuda.synchronize()
+    se = 0
+    ks = 0.0
+    levels = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for i, s in enumerate(src):
+            _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
+            se += st["source_edges"]
+            ks += st["kernel_ms"]
+            levels.append(st["levels"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return se, dt, ks, levels
+
+
+def level_kernel_timing(D, ctx, h, src, out):
+    """Per-launch time of the level-step kernel, measured with HIP events that
+    bracket each launch on the stream it runs on (library timing mode 1)."""
+    p = D.dawn_get_params(ctx, h)
+    D.dawn_set_params(ctx, h, driver=2, timing=1)
+    ms = 0.0
+    launches = 0
+    try:
+        for i, s in enumerate(src):
+            _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
+            ms += st["kernel_ms"]
+            launches += st["launches"]
+    finally:
+        D.dawn_set_params(ctx, h, **p)
+    return ms, launches
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sources", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method shards over sources (no collectives), "
+              "and this build runs and reports the single-GPU path only; use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen as gg
+    from paper_2208_04514_amd import dawn as D
+
+    _log("[bench] generating R-MAT 20")
+    g, src = gg.load_config("rmat20")
+    ctx = D.dawn_create(0, 0)
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
+
+    _log("[bench] plain SSSP timed region")
+    se, dt, ks, levels = run_plain(D, ctx, h, g, src, out, args.steps, args.warmup)
+    value = se / dt / 1e9
+    ms_per_step = dt / args.steps * 1e3
+
+    # roofline of the level-step kernel
+    lk_ms, lk_launches = level_kernel_timing(D, ctx, h, src, out)
+    dist_rows = out.cpu().numpy()
+    alg = plain_alg_bytes(g, dist_rows, levels[: src.size])
+    achieved = alg / (lk_ms / 1e3) / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "kernel": "sssp_level", "launches": lk_launches,
+        "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
+        "alg_bytes_per_launch": round(alg / lk_launches, 1),
+    }
+
+    extra = {}
+    if not args.no_batched:
+        _log("[bench] batched R-MAT 18, 4096 sources")
+        g2, src2 = gg.load_config("rmat18")
+        h2 = D.dawn_graph_upload(ctx, g2.row_ptr, g2.col)
+        out2 = torch.empty((src2.size, g2.n), dtype=torch.int32, device="cuda")
+        D.dawn_mssp(ctx, h2, src2, out=out2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, stb = D.dawn_mssp(ctx, h2, src2, out=out2)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        del out2
+        # the same 4096 sources, one at a time through the plain path
+        row = torch.empty(g2.n, dtype=torch.int32, device="cuda")
+        t0 = time.perf_counter()
+        sep = 0
+        for s in src2:
+            _, st = D.dawn_sssp(ctx, h2, int(s), out=row)
+            sep += st["source_edges"]
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        extra["batched"] = {
+            "workload": "rmat18_ef16_sym_4096src_one_launch",
+            "gteps": round(stb["source_edges"] / tb / 1e9, 2),
+            "gteps_device": round(stb["source_edges"] / stb["kernel_ms"] / 1e6, 2),
+            "ms": round(tb * 1e3, 3), "levels": stb["levels"],
+            "plain_same_sources_gteps": round(sep / tp / 1e9, 2),
+            "plain_same_sources_ms": round(tp * 1e3, 1),
+        }
+        D.dawn_graph_release(ctx, h2)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k = min(args.cpu_sources, src.size)
+        _log(f"[bench] CPU oracle on {k} sources (single thread)")
+        t0 = time.perf_counter()
+        ref = oracle.mssp(g, src[:k], threads=1)
+        tc = time.perf_counter() - t0
+        se_cpu = gg.reach_edges_from_dist(g, ref)
+        cpu = {"value": round(se_cpu / tc / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"rmat20 {k} sources, FIFO-queue BFS one source at a time, {tc:.1f} s",
+               "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
+        # parity of the timed rows on the sample (bit-exact)
+        extra["parity_sample_bit_exact"] = bool(np.array_equal(ref, dist_rows[:k]))
+
+    line = {
+        "metric": "GTEPS (source-edge traversals/s), plain per-source SSSP",
+        "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "rmat20_ef16_sym_64src_plain_sssp", "n": g.n, "m": g.m,
+                   "sources": int(src.size), "source_edges_per_step": int(se // args.steps),
+                   "gteps_device": round(se / ks / 1e6, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

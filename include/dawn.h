@@ -100,6 +100,9 @@ typedef struct dawn_params {
   int32_t small_n;            /* graphs with n <= small_n run as one workgroup per source */
   float batch_alpha;          /* batched: push when frontier edges * alpha < unsaturated in-edges */
   int32_t batch_lanes;        /* batched: sources per launch (64..4096, multiple of 64) */
+  int32_t timing;             /* 1: kernel_ms/launches of dawn_sssp cover only the level-step
+                                 kernels, each bracketed by HIP events (driver 2 only);
+                                 2 (default): every kernel of the call */
 } dawn_params;
 
 typedef struct dawn_graph_info {

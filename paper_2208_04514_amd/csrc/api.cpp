@@ -65,7 +65,7 @@ dawn_status get_graph(Ctx* ctx, int32_t id, std::shared_ptr<GraphRec>* out) {
 dawn_params default_params(const GraphRec& g) {
   dawn_params p;
   memset(&p, 0, sizeof(p));
-  p.driver = 1;
+  p.driver = 3;
   p.direction = 3;
   p.block = 256;
   p.blocks_per_cu = 0;
@@ -73,10 +73,11 @@ dawn_params default_params(const GraphRec& g) {
   p.pull_lane_edges = 32;
   p.alpha = 14.0f;
   p.beta = 24.0f;
-  p.graph_levels = 8;
+  p.graph_levels = 16;
   p.small_n = 0;
   p.batch_alpha = 4.0f;
   p.batch_lanes = 4096;
+  p.timing = 2;
   (void)g;
   return p;
 }
@@ -95,6 +96,9 @@ dawn_status check_params(const dawn_params& p) {
   if (!(p.batch_alpha > 0.f)) return fail(DAWN_E_INVALID_ARG, "batch_alpha > 0");
   if (p.batch_lanes < 64 || p.batch_lanes > 4096 || p.batch_lanes % 64)
     return fail(DAWN_E_INVALID_ARG, "batch_lanes must be a multiple of 64 in [64, 4096]");
+  if (p.timing < 1 || p.timing > 2) return fail(DAWN_E_INVALID_ARG, "timing must be 1 or 2");
+  if (p.timing == 1 && p.driver != 2)
+    return fail(DAWN_E_INVALID_ARG, "timing 1 needs driver 2 (one launch per level)");
   return DAWN_OK;
 }
 
@@ -253,6 +257,7 @@ dawn_status dawn_set_params(dawn_ctx* c, int32_t graph, const dawn_params* in) {
   if (p.f == 0) p.f = d.f
   KEEP(driver); KEEP(direction); KEEP(block); KEEP(big_degree); KEEP(pull_lane_edges);
   KEEP(alpha); KEEP(beta); KEEP(graph_levels); KEEP(batch_alpha); KEEP(batch_lanes);
+  KEEP(timing);
 #undef KEEP
   DAWN_TRY(check_params(p));
   std::lock_guard<std::mutex> lk(g->mu);

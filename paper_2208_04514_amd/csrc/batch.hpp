@@ -6,40 +6,51 @@
 
 namespace dawn {
 
-// Counters of one level of a batch (two slots, indexed level & 1).
+constexpr int kMaxPlanes = 16;    // relative levels up to 2^16 - 1 per source
+
+// Counters of one level of a batch (two slots, indexed level & 1), striped
+// over kStripes addresses like the single-source counters.
 struct BatchLevel {
-  u64 nodes;          // nodes that received a new bit
-  u64 bits;           // new (node, source) pairs
-  u64 se;             // sum over new pairs of the node's out-degree
-  u64 mf;             // sum of out-degrees of the nodes with a new bit
-  u64 edges;          // adjacency entries read by the expansion
-  unsigned nfront;    // entries of the frontier node list
-  unsigned nchunks;   // entries of the frontier out-edge chunk list
+  u64 nodes[kStripes];          // nodes that received a new bit
+  u64 bits[kStripes];           // new (node, source) pairs
+  u64 se[kStripes];             // sum over new pairs of the node's out-degree
+  u64 mf[kStripes];             // sum of out-degrees of the nodes with a new bit
+  u64 edges[kStripes];          // adjacency entries read by the expansion
+  unsigned nfront[kStripes];    // entries of each frontier node sub-list
+  unsigned nchunks[kStripes];   // entries of each frontier out-edge chunk sub-list
+};
+
+struct BatchLevelSum {
+  u64 nodes, bits, se, mf, edges;
+  unsigned nfront, nchunks;
 };
 
 struct BatchCtrl {
   BatchLevel lv[2];
-  u64 laneact[2][64]; // OR of the new bits of each word, per level
+  u64 laneact[2][64];           // OR of the new bits of each word, per level
 };
 
 struct BatchArgs {
   int32_t n;
-  int32_t W;          // 64-bit words per node row (sources / 64, rounded up)
+  int32_t W;                    // 64-bit words per node row (sources / 64, rounded up)
   long long m;
   const int32_t* rp;
   const int32_t* col;
   const int32_t* ip;
   const int32_t* isrc;
-  u64* vis;           // [n][W]
-  u64* nxt[2];        // [n][W] new bits per level parity
-  u64* touched;       // one bit per node: new bits this level
-  int32_t* fl[2];     // frontier node lists per level parity
-  int32_t* cu[2];     // frontier out-edge chunks: node
-  int32_t* ck[2];     //                           chunk index
+  u64* vis;                     // [n][W]
+  u64* nxt[2];                  // [n][W] new bits per level parity
+  u64* planes[kMaxPlanes];      // [n][W] bit b of each source's relative level
+  int32_t nplanes;              // planes allocated (levels < 2^nplanes)
+  u64* touched;                 // one bit per node: new bits this level
+  int32_t* fl[2];               // frontier node sub-lists per level parity (kStripes x n)
+  int32_t* cu[2];               // frontier out-edge chunk sub-lists: node
+  int32_t* ck[2];               //                                    chunk index
+  size_t chunk_cap;             // entries per chunk sub-list
   BatchCtrl* ctrl;
-  const u64* act;     // [W] sources still expanding
-  int32_t* const* rows;   // [lanes] distance row of each source (device)
-  const int32_t* base;    // [lanes] level at which each source joined
+  const u64* act;               // [W] sources still expanding
+  int32_t* const* rows;         // [lanes] distance row of each source (device)
+  const int32_t* base;          // [lanes] level at which each source joined
 };
 
 struct BatchWs {
@@ -53,16 +64,21 @@ struct BatchWs {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   u64* vis = nullptr;
   u64* nxt[2] = {nullptr, nullptr};
+  u64* planes[kMaxPlanes] = {};
+  int nplanes = 0;              // allocated
+  int planes_dirty = 0;         // planes that may hold bits from an earlier batch
   u64* touched = nullptr;
   int32_t* fl[2] = {nullptr, nullptr};
   int32_t* cu[2] = {nullptr, nullptr};
   int32_t* ck[2] = {nullptr, nullptr};
+  size_t chunk_cap = 0;
   BatchCtrl* ctrl = nullptr;
   u64* act = nullptr;
+  u64* emask = nullptr;         // [64] lanes to emit
   int32_t** rows = nullptr;
   int32_t* base = nullptr;
   int32_t* src = nullptr;
-  int32_t* stage = nullptr;       // device rows for host-destination calls
+  int32_t* stage = nullptr;     // device rows for host-destination calls
   size_t stage_ints = 0;
   BatchCtrl* h_ctrl = nullptr;
 };
@@ -75,13 +91,16 @@ struct BatchTotals {
 
 dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage_ints,
                             BatchWs** out);
+dawn_status batch_ensure_planes(BatchWs* w, int need, int W);
 BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W);
+BatchLevelSum batch_level_sum(const BatchLevel& l);
 dawn_status batch_launch_expand(Ctx* ctx, const BatchArgs& a, bool pull, int L, hipStream_t s);
 dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t s);
-dawn_status batch_launch_fill(Ctx* ctx, const BatchArgs& a, int r0, int k, hipStream_t s);
+dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
+                              bool clear, hipStream_t s);
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
 dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src, int k,
-                              hipStream_t s);
-bool batch_choose_pull(const dawn_params& p, const BatchLevel& last, long long m);
+                              int lane0, hipStream_t s);
+bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, long long m);
 
 }  // namespace dawn

@@ -55,14 +55,19 @@ struct GridBarrier {
   unsigned int pad;
 };
 
+// Counters of one level step are striped over kStripes addresses (a
+// workgroup adds into stripe blockIdx % kStripes) so that no single address
+// takes more than a few hundred atomics per level; readers sum the stripes.
+constexpr int kStripes = 16;
+
 // Counters produced by one level step (ring of three, indexed level % 3).
 struct LevelSlot {
-  unsigned int nf;            // nodes found at this level
-  unsigned int small_count;   // entries appended to the small-degree queue
-  unsigned int big_chunks;    // chunks appended to the big-degree queue
+  unsigned int nf[kStripes];            // nodes found at this level
+  unsigned int small_count[kStripes];   // entries appended to each small-degree sub-queue
+  u64 mf[kStripes];                     // sum of out-degrees of the nodes found
+  u64 edges[kStripes];                  // adjacency entries examined
+  unsigned int big_chunks;              // chunks appended to the big-degree queue
   unsigned int pad;
-  u64 mf;                     // sum of out-degrees of the nodes found
-  u64 edges;                  // adjacency entries examined
 };
 
 // Level-loop state shared by every workgroup of a traversal.
@@ -74,7 +79,7 @@ struct LevelState {
   long long mu;               // out-degree sum of the still-unvisited nodes
   int last_nonempty;          // last level that found a node
   int push_levels, pull_levels;
-  int pad;
+  unsigned prev_nf;           // nodes found by the level before the last
   u64 edges_total;
   u64 source_edges;
   u64 reached;
@@ -82,8 +87,6 @@ struct LevelState {
 
 struct SsspCtrl {
   GridBarrier bar;
-  unsigned int ticket;        // last-workgroup detection (per-level kernels)
-  unsigned int pad;
   LevelSlot slot[3];
   LevelState st;
 };
@@ -99,8 +102,8 @@ struct SsspArgs {
   const int32_t* isrc;        // CSC sources (m)
   u64* vis0;
   u64* vis1;
-  int32_t* qs0;               // small-degree queues (level parity 0/1), n entries each
-  int32_t* qs1;
+  int32_t* qs0;               // small-degree queues (level parity 0/1): kStripes
+  int32_t* qs1;               //   sub-queues of n entries each
   int32_t* cu0;               // big-degree chunk lists: node of each chunk
   int32_t* cu1;
   int32_t* ck0;               // ... and the chunk's index within the node's row

@@ -18,12 +18,14 @@
 // Push (SOVM, Section 3.3, per bit): every frontier node u ORs
 // nxt[u] & ~vis[v] into the new bits of each out-neighbour v.
 //
-// After each expansion a merge pass folds the new bits into vis tile by tile
-// (64 consecutive nodes), transposes them in LDS and writes the distance
-// rows: row r gets L - base[r] at every node whose bit r is new, as one
-// coalesced 256-byte masked store per (row, tile).  base[r] is the level at
-// which source r joined the batch (0 for dawn_mssp; the serving loop admits
-// sources at later levels).
+// After each expansion a merge pass folds the new bits into vis and records
+// each new bit's relative level L - base[r] in bit-planes: plane b holds bit b
+// of that level for every (node, source).  base[r] is the level at which
+// source r joined the batch (0 for dawn_mssp; the serving loop admits sources
+// at later levels).  Distances are written once, at the end, by an emission
+// pass that rebuilds each level from the planes and stores every row as
+// whole 256-byte segments (64 consecutive nodes), -1 where the source's bit
+// never arrived; no row is touched while the levels run.
 #include <string.h>
 
 #include <algorithm>
@@ -43,6 +45,33 @@ template <int P>
 __device__ __forceinline__ u64 group_mask(int lane) {
   if (P == 64) return ~0ull;
   return ((1ull << P) - 1ull) << (lane & ~(P - 1));
+}
+
+__device__ __forceinline__ u64 shfl_xor64(u64 x, int m) {
+  unsigned lo = __shfl_xor((unsigned)x, m, kWave), hi = __shfl_xor((unsigned)(x >> 32), m, kWave);
+  return ((u64)hi << 32) | lo;
+}
+
+// Prefix of kStripes sub-list lengths in LDS (every thread calls).
+__device__ __forceinline__ void sub_prefix(const unsigned* counts, unsigned* pre) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned acc = 0;
+    for (int s = 0; s < kStripes; ++s) {
+      pre[s] = acc;
+      acc += ld_relaxed(&counts[s]);
+    }
+    pre[kStripes] = acc;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int sub_of(const unsigned* pre, unsigned i) {
+  int lo = 0;
+#pragma unroll
+  for (int step = kStripes / 2; step > 0; step >>= 1)
+    if (pre[lo + step] <= i) lo += step;
+  return lo;
 }
 
 // ------------------------------------------------------------- expansion --
@@ -71,14 +100,14 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
       const int s = a.ip[v], e = a.ip[v + 1];
       int j = s;
       bool sat = false;
-      // four in-neighbours per step: independent loads in flight
+      // four in-neighbours per step keep independent loads in flight; a lane
+      // whose word is already covered issues no further loads
       for (; j + 4 <= e; j += 4) {
         const int u0 = a.isrc[j], u1 = a.isrc[j + 1], u2 = a.isrc[j + 2], u3 = a.isrc[j + 3];
-        if (wok) {
-          acc |= a.vis[(size_t)u0 * W + w] | a.vis[(size_t)u1 * W + w] |
-                 a.vis[(size_t)u2 * W + w] | a.vis[(size_t)u3 * W + w];
+        if (acc != need) {
+          acc |= (a.vis[(size_t)u0 * W + w] | a.vis[(size_t)u1 * W + w] |
+                  a.vis[(size_t)u2 * W + w] | a.vis[(size_t)u3 * W + w]) & need;
         }
-        acc &= need;
         if ((__ballot(acc != need) & gm) == 0) {
           j += 4;
           sat = true;
@@ -87,8 +116,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
       }
       for (; !sat && j < e; ++j) {
         const int u = a.isrc[j];
-        if (wok) acc |= a.vis[(size_t)u * W + w];
-        acc &= need;
+        if (acc != need) acc |= a.vis[(size_t)u * W + w] & need;
         if ((__ballot(acc != need) & gm) == 0) {
           ++j;
           break;
@@ -101,11 +129,12 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     if (any && w == 0) atom_or(&a.touched[v >> 6], 1ull << (v & 63));
   }
   edges = wave_sum(edges);
-  if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges, edges);
+  if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges[blockIdx.x % kStripes], edges);
 }
 
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
+  __shared__ unsigned pre[kStripes + 1];
   const int lane = lane_id();
   const int w = lane & (P - 1);
   const int gpw = kWave / P;
@@ -113,7 +142,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
   const u64 gm = group_mask<P>(lane);
   const size_t W = (size_t)a.W;
   const int pl = (L - 1) & 1;
-  const unsigned nch = ld_relaxed(&a.ctrl->lv[pl].nchunks);
+  sub_prefix(a.ctrl->lv[pl].nchunks, pre);
+  const unsigned nch = pre[kStripes];
   const int32_t* cu = a.cu[pl];
   const int32_t* ck = a.ck[pl];
   const u64* front = a.nxt[pl];
@@ -127,10 +157,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
     int e0 = 0, e1 = 0;
     u64 f = 0;
     if (has) {
-      const int u = cu[c];
-      const int k = ck[c];
-      const int r0 = a.rp[u];
-      e0 = r0 + k * kChunk;
+      const int sidx = sub_of(pre, c);
+      const size_t at = (size_t)sidx * a.chunk_cap + (c - pre[sidx]);
+      const int u = cu[at];
+      const int k = ck[at];
+      e0 = a.rp[u] + k * kChunk;
       e1 = min(e0 + kChunk, a.rp[u + 1]);
       if (wok) f = front[(size_t)u * W + w];
     }
@@ -138,7 +169,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
     for (int e = e0; e < e1; ++e) {
       const int v = a.col[e];
       u64 b = 0;
-      if (wok && f) {
+      if (f) {
         b = f & ~a.vis[(size_t)v * W + w];
         if (b) atom_or(&out[(size_t)v * W + w], b);
       }
@@ -151,163 +182,206 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
     }
   }
   edges = wave_sum(edges);
-  if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges, edges);
+  if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges[blockIdx.x % kStripes], edges);
 }
 
 // ----------------------------------------------------------------- merge --
-// One workgroup per touched tile of 64 nodes (grid-stride).  W <= 64.
+// Fold the new bits of level L into vis and the level planes, build the next
+// frontier (node sub-lists and out-edge chunks), and clear the previous
+// frontier's rows.  One wave per touched tile of 64 nodes (grid-stride).
+template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
-  __shared__ u64 tile[64 * 65];   // tile[w * 65 + j]: new bits of node v0+j, word w
-  __shared__ u64 tor[64];         // OR of the tile per word
-  __shared__ int tj[64];          // touched node offsets in the tile
-  __shared__ int tcount;
+  __shared__ u64 lmask[kMaxPlanes][64];   // bit b of (L - base) for the lanes of each word
+  __shared__ u64 actb[64];
+  __shared__ int rank_j[kBatchBlock / kWave][kWave];
+  __shared__ unsigned pre[kStripes + 1];
+  __shared__ u64 red[4][kBatchBlock / kWave];
   const int tid = threadIdx.x;
   const int lane = lane_id();
-  const int wave = tid / kWave;
+  const int wv = tid / kWave;
   const int W = a.W;
-  u64* nxt = a.nxt[L & 1];
+  const int D = a.nplanes;
+  if (tid < W) {
+    u64 mb[kMaxPlanes];
+    for (int b = 0; b < kMaxPlanes; ++b) mb[b] = 0;
+    for (int r = 0; r < 64; ++r) {
+      const int rel = L - a.base[tid * 64 + r];
+      for (int b = 0; b < D; ++b)
+        if ((rel >> b) & 1) mb[b] |= 1ull << r;
+    }
+    for (int b = 0; b < kMaxPlanes; ++b) lmask[b][tid] = mb[b];
+    actb[tid] = 0;
+  }
   const int cl = L & 1;
   BatchLevel* lv = &a.ctrl->lv[cl];
-  u64 act_acc = 0;   // thread w < W: OR of new bits over this block's tiles
-  u64 bits = 0, se = 0, mf = 0;
-  unsigned nodes = 0;
-  const int ntiles = (a.n + 63) / 64;
-
-  // clear the rows of the previous frontier (their bits were consumed by the
-  // expansion of this level) and retire that frontier list
+  // clear the rows of the previous frontier: the expansion of this level has
+  // consumed their bits
   if (L > 0) {
     const int pl = (L - 1) & 1;
-    const unsigned nprev = ld_relaxed(&a.ctrl->lv[pl].nfront);
+    sub_prefix(a.ctrl->lv[pl].nfront, pre);
+    const unsigned nprev = pre[kStripes];
     u64* prev = a.nxt[pl];
     const int32_t* fl = a.fl[pl];
-    for (unsigned i = blockIdx.x * (kBatchBlock / 64) + wave; i < nprev;
-         i += gridDim.x * (kBatchBlock / 64)) {
-      const int u = fl[i];
-      if (lane < W) prev[(size_t)u * W + lane] = 0;
+    for (unsigned i = blockIdx.x * (kBatchBlock / kWave) + wv; i < nprev;
+         i += gridDim.x * (kBatchBlock / kWave)) {
+      const int sidx = sub_of(pre, i);
+      const int u = fl[(size_t)sidx * a.n + (i - pre[sidx])];
+      for (int x = lane; x < W; x += kWave) prev[(size_t)u * W + x] = 0;
     }
   }
+  __syncthreads();
 
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int w = lane & (P - 1);
+  const int npw = kWave / P;
+  const int sub = lane / P;
+  const bool wok = w < W;
+  const int stripe = blockIdx.x % kStripes;
+  u64* nxt = a.nxt[cl];
+  u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0;
+  const int ntiles = (a.n + 63) / 64;
+  const unsigned gw = (blockIdx.x * kBatchBlock + tid) / kWave;
+  const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
+  for (unsigned t = gw; t < (unsigned)ntiles; t += nwaves) {
     const u64 tw = a.touched[t];
     if (tw == 0) continue;
-    const int v0 = t * 64;
-    if (tid == 0) {
-      int c = 0;
-      u64 m = tw;
-      while (m) {
-        tj[c++] = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-      }
-      tcount = c;
+    const int v0 = (int)t * 64;
+    const bool mine = (tw >> lane) & 1ull;
+    const int rank = __popcll(tw & lanes_below());
+    const int cnt = __popcll(tw);
+    int deg = 0, nch = 0;
+    if (mine) {
+      rank_j[wv][rank] = lane;
+      deg = a.rp[v0 + lane + 1] - a.rp[v0 + lane];
+      nch = (deg + kChunk - 1) / kChunk;
     }
-    for (int i = tid; i < W * 65; i += kBatchBlock) tile[i] = 0;
-    __syncthreads();
-    const int tc = tcount;
-    // each wave takes touched nodes; lane = word
-    for (int i = wave; i < tc; i += kBatchBlock / kWave) {
-      const int j = tj[i];
-      const int v = v0 + j;
-      u64 nb = 0;
-      if (lane < W) {
-        const size_t idx = (size_t)v * W + lane;
-        nb = nxt[idx];
-        a.vis[idx] |= nb;
-        tile[lane * 65 + j] = nb;
+    const int nch_incl = wave_incl_scan(nch);
+    const int nch_tot = __shfl(nch_incl, kWave - 1, kWave);
+    unsigned fbase = 0, cbase = 0;
+    if (lane == 0) {
+      fbase = atom_add(&lv->nfront[stripe], (unsigned)cnt);
+      if (nch_tot) cbase = atom_add(&lv->nchunks[stripe], (unsigned)nch_tot);
+    }
+    fbase = __shfl(fbase, 0, kWave);
+    cbase = __shfl(cbase, 0, kWave);
+    if (mine) {
+      const int v = v0 + lane;
+      a.fl[cl][(size_t)stripe * a.n + fbase + rank] = v;
+      const size_t c0 = (size_t)stripe * a.chunk_cap + cbase + (nch_incl - nch);
+      for (int k = 0; k < nch; ++k) {
+        a.cu[cl][c0 + k] = v;
+        a.ck[cl][c0 + k] = k;
       }
-      const int deg = a.rp[v + 1] - a.rp[v];
-      const u64 pc = (u64)__popcll(nb);
-      bits += pc;
-      se += pc * (u64)deg;
-      // v joins the next frontier: node list and out-edge chunks
-      if (lane == 0) {
-        nodes += 1;
-        mf += (u64)deg;
-        const unsigned pos = atom_add(&lv->nfront, 1u);
-        a.fl[cl][pos] = v;
-        if (deg > 0) {
-          const unsigned nch = (unsigned)((deg + kChunk - 1) / kChunk);
-          const unsigned cb = atom_add(&lv->nchunks, nch);
-          for (unsigned k = 0; k < nch; ++k) {
-            a.cu[cl][cb + k] = v;
-            a.ck[cl][cb + k] = (int32_t)k;
+      nodes += 1;
+      mf += (u64)deg;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int i0 = 0; i0 < cnt; i0 += npw) {
+      const int i = i0 + sub;
+      const int j = rank_j[wv][i < cnt ? i : cnt - 1];
+      const int dj = __shfl(deg, j, kWave);
+      if (i < cnt && wok) {
+        const size_t idx = (size_t)(v0 + j) * W + w;
+        const u64 nb = nxt[idx];
+        if (nb) {
+          a.vis[idx] |= nb;
+          for (int b = 0; b < D; ++b) {
+            const u64 m = lmask[b][w] & nb;
+            if (m) a.planes[b][idx] |= m;
           }
+          const u64 pc = (u64)__popcll(nb);
+          bits += pc;
+          se += pc * (u64)dj;
+          act_acc |= nb;
         }
       }
     }
-    __syncthreads();
-    if (tid < W) {
-      u64 o = 0;
-      for (int j = 0; j < 64; ++j) o |= tile[tid * 65 + j];
-      tor[tid] = o;
-      act_acc |= o;
-    }
-    __syncthreads();
-    // distance rows: wave `wave` takes words wave, wave+4, ...
-    const int vj = v0 + lane;
-    for (int w = wave; w < W; w += kBatchBlock / kWave) {
-      u64 m = tor[w];
-      const u64 mine = tile[w * 65 + lane];
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const int r = w * 64 + b;
-        if (((mine >> b) & 1ull) && vj < a.n) a.rows[r][vj] = L - a.base[r];
-      }
-    }
-    if (tid == 0) a.touched[t] = 0;
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) a.touched[t] = 0;
   }
-  // lane activity and counters
-  if (tid < W && act_acc) {
-    u64* g = &a.ctrl->laneact[cl][tid];
-    if (act_acc & ~ld_relaxed(g)) atom_or(g, act_acc);
-  }
+  // lanes w, w+P, ... hold the same word: fold them, then once per block
+  for (int off = P; off < kWave; off <<= 1) act_acc |= shfl_xor64(act_acc, off);
+  if (lane < P && wok && act_acc) atomicOr(&actb[w], act_acc);
   bits = wave_sum(bits);
   se = wave_sum(se);
-  if (lane == 0) {
-    if (bits) atom_add(&lv->bits, bits);
-    if (se) atom_add(&lv->se, se);
-  }
   nodes = wave_sum(nodes);
   mf = wave_sum(mf);
   if (lane == 0) {
-    if (nodes) atom_add(&lv->nodes, (u64)nodes);
-    if (mf) atom_add(&lv->mf, mf);
+    red[0][wv] = bits;
+    red[1][wv] = se;
+    red[2][wv] = nodes;
+    red[3][wv] = mf;
+  }
+  __syncthreads();
+  if (tid < W && actb[tid]) {
+    u64* gp = &a.ctrl->laneact[cl][tid];
+    if (actb[tid] & ~ld_relaxed(gp)) atom_or(gp, actb[tid]);
+  }
+  if (tid < 4) {
+    u64 x = 0;
+    for (int i = 0; i < kBatchBlock / kWave; ++i) x += red[tid][i];
+    if (x) {
+      u64* dst = tid == 0 ? lv->bits : tid == 1 ? lv->se : tid == 2 ? lv->nodes : lv->mf;
+      atom_add(&dst[stripe], x);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ emit --
+// Write the distance rows of the lanes in emask: for each tile of 64 nodes one
+// workgroup, one wave per word; a lane holds node v0+lane's visited word and
+// level planes, then each emitted lane's row gets 64 consecutive int32 (one
+// 256-byte store).  With `clear` the emitted lanes' bits are removed.
+__global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, const u64* emask,
+                                                          int clear) {
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  const int W = a.W;
+  const int ntiles = (a.n + 63) / 64;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int v = t * 64 + lane;
+    const bool valid = v < a.n;
+    for (int w = wv; w < W; w += kBatchBlock / kWave) {
+      u64 em = emask[w];
+      if (!em) continue;
+      const size_t idx = (size_t)v * W + w;
+      const u64 x = valid ? a.vis[idx] : 0ull;
+      u64 pl[kMaxPlanes];
+#pragma unroll
+      for (int b = 0; b < kMaxPlanes; ++b) pl[b] = (b < D && valid) ? a.planes[b][idx] : 0ull;
+      if (clear && valid) {
+        a.vis[idx] = x & ~em;
+        for (int b = 0; b < D; ++b) a.planes[b][idx] = pl[b] & ~em;
+      }
+      while (em) {
+        const int b = __ffsll((unsigned long long)em) - 1;
+        em &= em - 1;
+        int32_t* row = a.rows[w * 64 + b];
+        if (!row) continue;
+        int val = -1;
+        if ((x >> b) & 1ull) {
+          val = 0;
+#pragma unroll
+          for (int d = 0; d < kMaxPlanes; ++d) val |= (int)((pl[d] >> b) & 1ull) << d;
+        }
+        if (valid) row[v] = val;
+      }
+    }
   }
 }
 
 // ------------------------------------------------------------------ init --
-// rows[r][0..n) = -1 for r < k
-__global__ __launch_bounds__(kBatchBlock) void batch_fill_rows(BatchArgs a, int k, int r0) {
-  const int r = r0 + blockIdx.y;
-  if (r >= k) return;
-  int32_t* row = a.rows[r];
-  if (!row) return;
-  const int n = a.n;
-  const uintptr_t addr = (uintptr_t)row;
-  if ((addr & 15) == 0 && (n & 3) == 0) {
-    int4* r4 = (int4*)row;
-    const int n4 = n >> 2;
-    for (int i = blockIdx.x * kBatchBlock + threadIdx.x; i < n4; i += gridDim.x * kBatchBlock)
-      r4[i] = make_int4(-1, -1, -1, -1);
-  } else {
-    for (int i = blockIdx.x * kBatchBlock + threadIdx.x; i < n; i += gridDim.x * kBatchBlock)
-      row[i] = -1;
-  }
-}
-
 __global__ __launch_bounds__(kBatchBlock) void batch_zero(u64* p, size_t count) {
   for (size_t i = blockIdx.x * (size_t)kBatchBlock + threadIdx.x; i < count;
        i += (size_t)gridDim.x * kBatchBlock)
     p[i] = 0;
 }
 
-// lane r of the batch starts at node src[r]: bit r of nxt[0][src[r]] and the node is touched
-__global__ void batch_seed(BatchArgs a, const int32_t* src, int k) {
+// lane lane0 + r of the batch starts at node src[r]: bit of nxt[0][src[r]], node touched
+__global__ void batch_seed(BatchArgs a, const int32_t* src, int k, int lane0) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < k; r += gridDim.x * blockDim.x) {
     const int s = src[r];
-    const int w = r >> 6;
-    atom_or(&a.nxt[0][(size_t)s * a.W + w], 1ull << (r & 63));
+    const int l = lane0 + r;
+    atom_or(&a.nxt[0][(size_t)s * a.W + (l >> 6)], 1ull << (l & 63));
     atom_or(&a.touched[s >> 6], 1ull << (s & 63));
   }
 }
@@ -319,6 +393,7 @@ void batch_ws_destroy(BatchWs* w) {
   dev_free(ctx, w->vis, 0);
   dev_free(ctx, w->nxt[0], 0);
   dev_free(ctx, w->nxt[1], 0);
+  for (int b = 0; b < kMaxPlanes; ++b) dev_free(ctx, w->planes[b], 0);
   dev_free(ctx, w->touched, 0);
   for (int i = 0; i < 2; ++i) {
     dev_free(ctx, w->fl[i], 0);
@@ -327,6 +402,7 @@ void batch_ws_destroy(BatchWs* w) {
   }
   dev_free(ctx, w->ctrl, 0);
   dev_free(ctx, w->act, 0);
+  dev_free(ctx, w->emask, 0);
   dev_free(ctx, w->rows, 0);
   dev_free(ctx, w->base, 0);
   dev_free(ctx, w->src, 0);
@@ -349,7 +425,8 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   w->Wmax = W;
   const size_t n = (size_t)g->n;
   const size_t nw = (n + 63) / 64;
-  const size_t chunk_cap = (size_t)(g->m / kChunk) + n + 64;
+  // per level at most sum over nodes of ceil(deg / kChunk) <= m / kChunk + n chunks
+  w->chunk_cap = (size_t)(g->m / kChunk) + n + 64;
   dawn_status s = DAWN_OK;
   auto alloc = [&](void** p, size_t bytes) {
     if (s != DAWN_OK) return;
@@ -361,12 +438,13 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   alloc((void**)&w->nxt[1], n * W * 8);
   alloc((void**)&w->touched, nw * 8 + 64);
   for (int i = 0; i < 2; ++i) {
-    alloc((void**)&w->fl[i], n * 4 + 64);
-    alloc((void**)&w->cu[i], chunk_cap * 4);
-    alloc((void**)&w->ck[i], chunk_cap * 4);
+    alloc((void**)&w->fl[i], (size_t)kStripes * n * 4 + 64);
+    alloc((void**)&w->cu[i], (size_t)kStripes * w->chunk_cap * 4);
+    alloc((void**)&w->ck[i], (size_t)kStripes * w->chunk_cap * 4);
   }
   alloc((void**)&w->ctrl, sizeof(BatchCtrl));
   alloc((void**)&w->act, 64 * 8);
+  alloc((void**)&w->emask, 64 * 8);
   alloc((void**)&w->rows, (size_t)4096 * sizeof(int32_t*));
   alloc((void**)&w->base, (size_t)4096 * 4);
   alloc((void**)&w->src, (size_t)4096 * 4);
@@ -389,6 +467,22 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   return DAWN_OK;
 }
 
+// Make sure planes 0 .. need-1 exist (new planes start zeroed).
+dawn_status batch_ensure_planes(BatchWs* w, int need, int W) {
+  if (need > kMaxPlanes)
+    return fail(DAWN_E_DEVICE, "batched traversal exceeds %d levels", (1 << kMaxPlanes) - 1);
+  const size_t bytes = (size_t)w->n * (size_t)w->Wmax * 8;
+  while (w->nplanes < need) {
+    u64* p = nullptr;
+    DAWN_TRY(dev_alloc(w->ctx, (void**)&p, bytes));
+    w->bytes += bytes;
+    DAWN_HIP(hipMemsetAsync(p, 0, bytes, w->stream));
+    w->planes[w->nplanes++] = p;
+  }
+  (void)W;
+  return DAWN_OK;
+}
+
 BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W) {
   BatchArgs a;
   memset(&a, 0, sizeof(a));
@@ -402,17 +496,35 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W) {
   a.vis = w->vis;
   a.nxt[0] = w->nxt[0];
   a.nxt[1] = w->nxt[1];
+  for (int b = 0; b < kMaxPlanes; ++b) a.planes[b] = w->planes[b];
+  a.nplanes = w->nplanes;
   a.touched = w->touched;
   for (int i = 0; i < 2; ++i) {
     a.fl[i] = w->fl[i];
     a.cu[i] = w->cu[i];
     a.ck[i] = w->ck[i];
   }
+  a.chunk_cap = w->chunk_cap;
   a.ctrl = w->ctrl;
   a.act = w->act;
   a.rows = w->rows;
   a.base = w->base;
   return a;
+}
+
+BatchLevelSum batch_level_sum(const BatchLevel& l) {
+  BatchLevelSum s;
+  memset(&s, 0, sizeof(s));
+  for (int i = 0; i < kStripes; ++i) {
+    s.nodes += l.nodes[i];
+    s.bits += l.bits[i];
+    s.se += l.se[i];
+    s.mf += l.mf[i];
+    s.edges += l.edges[i];
+    s.nfront += l.nfront[i];
+    s.nchunks += l.nchunks[i];
+  }
+  return s;
 }
 
 static int pow2_at_least(int x) {
@@ -447,18 +559,33 @@ dawn_status batch_launch_expand(Ctx* ctx, const BatchArgs& a, bool pull, int L, 
 }
 
 dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t s) {
-  hipLaunchKernelGGL(batch_merge, dim3(ctx->num_cu * 8), dim3(kBatchBlock), 0, s, a, L);
+  const int P = pow2_at_least(a.W);
+  const int grid = ctx->num_cu * 8;
+#define DAWN_MERGE(PP)                                                                   \
+  case PP:                                                                               \
+    hipLaunchKernelGGL(batch_merge<PP>, dim3(grid), dim3(kBatchBlock), 0, s, a, L);     \
+    break;
+  switch (P) {
+    DAWN_MERGE(1)
+    DAWN_MERGE(2)
+    DAWN_MERGE(4)
+    DAWN_MERGE(8)
+    DAWN_MERGE(16)
+    DAWN_MERGE(32)
+    DAWN_MERGE(64)
+    default: return fail(DAWN_E_INVALID_ARG, "batch too wide");
+  }
+#undef DAWN_MERGE
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }
 
-dawn_status batch_launch_fill(Ctx* ctx, const BatchArgs& a, int r0, int k, hipStream_t s) {
-  // rows r0 .. k-1, at most 65535 per launch along y
-  for (int b = r0; b < k; b += 65535) {
-    const int rows = std::min(65535, k - b);
-    const int gx = std::max(1, std::min((a.n / 4 + kBatchBlock - 1) / kBatchBlock, 64));
-    hipLaunchKernelGGL(batch_fill_rows, dim3(gx, rows), dim3(kBatchBlock), 0, s, a, k, b);
-  }
+dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
+                              bool clear, hipStream_t s) {
+  const int ntiles = (a.n + 63) / 64;
+  const int grid = std::max(1, std::min(ntiles, ctx->num_cu * 8));
+  hipLaunchKernelGGL(batch_emit, dim3(grid), dim3(kBatchBlock), 0, s, a, nplanes_used, d_emask,
+                     clear ? 1 : 0);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }
@@ -472,19 +599,28 @@ dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s) {
   return DAWN_OK;
 }
 
-dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src, int k,
+dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src, int k, int lane0,
                               hipStream_t s) {
   (void)ctx;
-  hipLaunchKernelGGL(batch_seed, dim3((k + 255) / 256), dim3(256), 0, s, a, d_src, k);
+  hipLaunchKernelGGL(batch_seed, dim3((k + 255) / 256), dim3(256), 0, s, a, d_src, k, lane0);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }
 
 // Choose push or pull for the next level from the counters of the last one.
-bool batch_choose_pull(const dawn_params& p, const BatchLevel& last, long long m) {
+bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, long long m) {
   if (p.direction == 1) return false;
   if (p.direction == 2) return true;
   return (double)last.mf * (double)p.batch_alpha >= (double)m;
+}
+
+static int bit_length(int x) {
+  int b = 0;
+  while (x > 0) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
 }
 
 // One batch of k <= lanes sources through the per-level loop.
@@ -492,29 +628,36 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
                              const int32_t* h_src, int k, int32_t* const* h_rows,
                              BatchTotals* tot) {
   const int W = (k + 63) / 64;
-  BatchArgs a = batch_args(g, w, W);
   hipStream_t s = w->stream;
   const size_t nW = (size_t)g->n * W;
-  std::vector<int32_t> zeros(k, 0);
+  std::vector<int32_t> zeros(64 * W, 0);
+  std::vector<u64> em(W, ~0ull);
+  if (k % 64) em[W - 1] = (1ull << (k % 64)) - 1ull;
+  std::vector<int32_t*> rows(64 * W, nullptr);
+  for (int r = 0; r < k; ++r) rows[r] = h_rows[r];
   DAWN_HIP(hipMemcpyAsync(w->src, h_src, (size_t)k * 4, hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemcpyAsync(w->rows, h_rows, (size_t)k * sizeof(int32_t*), hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemcpyAsync(w->base, zeros.data(), (size_t)k * 4, hipMemcpyHostToDevice, s));
+  DAWN_HIP(hipMemcpyAsync(w->rows, rows.data(), rows.size() * sizeof(int32_t*),
+                          hipMemcpyHostToDevice, s));
+  DAWN_HIP(hipMemcpyAsync(w->base, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, s));
+  DAWN_HIP(hipMemcpyAsync(w->emask, em.data(), (size_t)W * 8, hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemsetAsync(w->ctrl, 0, sizeof(BatchCtrl), s));
+  DAWN_HIP(hipEventRecord(w->ev0, s));
   DAWN_TRY(batch_launch_zero(ctx, w->vis, nW, s));
   DAWN_TRY(batch_launch_zero(ctx, w->nxt[0], nW, s));
   DAWN_TRY(batch_launch_zero(ctx, w->nxt[1], nW, s));
   DAWN_TRY(batch_launch_zero(ctx, w->touched, ((size_t)g->n + 63) / 64, s));
-  DAWN_HIP(hipEventRecord(w->ev0, s));
-  DAWN_TRY(batch_launch_fill(ctx, a, 0, k, s));
-  DAWN_TRY(batch_launch_seed(ctx, a, w->src, k, s));
+  for (int b = 0; b < w->planes_dirty; ++b) DAWN_TRY(batch_launch_zero(ctx, w->planes[b], nW, s));
+  w->planes_dirty = 0;
+  BatchArgs a = batch_args(g, w, W);
+  DAWN_TRY(batch_launch_seed(ctx, a, w->src, k, 0, s));
   DAWN_TRY(batch_launch_merge(ctx, a, 0, s));
-  int launches = 3;
+  int launches = 7 + w->planes_dirty;
   int last_nonempty = 0;
   for (int L = 1;; ++L) {
     const int pl = (L - 1) & 1;
     DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, s));
     DAWN_HIP(hipStreamSynchronize(s));
-    const BatchLevel prev = w->h_ctrl->lv[pl];
+    const BatchLevelSum prev = batch_level_sum(w->h_ctrl->lv[pl]);
     tot->edges += prev.edges;
     tot->reached += prev.bits;
     tot->source_edges += prev.se;
@@ -523,6 +666,12 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
     for (int i = 0; i < W; ++i) any |= w->h_ctrl->laneact[pl][i] != 0;
     if (!any) break;
     if (L > g->n + 1) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
+    const int need = bit_length(L);
+    if (need > w->nplanes) {
+      DAWN_TRY(batch_ensure_planes(w, need, W));
+      a = batch_args(g, w, W);
+    }
+    w->planes_dirty = std::max(w->planes_dirty, need);
     // active lanes and a clean slot for this level
     DAWN_HIP(hipMemcpyAsync(w->act, w->h_ctrl->laneact[pl], (size_t)W * 8, hipMemcpyHostToDevice, s));
     DAWN_HIP(hipMemsetAsync(&w->ctrl->lv[L & 1], 0, sizeof(BatchLevel), s));
@@ -533,6 +682,8 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
     launches += 2;
     if (pull) tot->pull_levels++; else tot->push_levels++;
   }
+  DAWN_TRY(batch_launch_emit(ctx, a, bit_length(last_nonempty), w->emask, false, s));
+  launches += 1;
   DAWN_HIP(hipEventRecord(w->ev1, s));
   DAWN_HIP(hipStreamSynchronize(s));
   float ms = 0.f;

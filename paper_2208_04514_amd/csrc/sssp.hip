@@ -54,6 +54,15 @@ struct Counters {
   u64 edges;
 };
 
+// Entries each wave stages in LDS before one atomic reserves room in its
+// workgroup's sub-queue (an append adds at most 64, so flush above the rest).
+constexpr int kWaveBuf = 256;
+
+struct WaveQueue {
+  int32_t* buf;   // this wave's LDS staging area (kWaveBuf entries)
+  int cnt;        // wave-uniform fill
+};
+
 __device__ __forceinline__ int32_t* small_q(const SsspArgs& a, int level) {
   return (level & 1) ? a.qs1 : a.qs0;
 }
@@ -64,11 +73,26 @@ __device__ __forceinline__ int32_t* chunk_k(const SsspArgs& a, int level) {
   return (level & 1) ? a.ck1 : a.ck0;
 }
 
+// Move the staged entries to this workgroup's sub-queue of level L.  Wave-uniform.
+__device__ __forceinline__ void wq_flush(const SsspArgs& a, int L, WaveQueue& q) {
+  if (q.cnt == 0) return;
+  const int stripe = blockIdx.x % kStripes;
+  const int lane = lane_id();
+  unsigned base = 0;
+  if (lane == 0) base = atom_add(&a.ctrl->slot[L % 3].small_count[stripe], (unsigned)q.cnt);
+  base = __shfl(base, 0, kWave);
+  int32_t* dst = small_q(a, L) + (size_t)stripe * (size_t)a.n + base;
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < q.cnt; i += kWave) dst[i] = q.buf[i];
+  __builtin_amdgcn_wave_barrier();
+  q.cnt = 0;
+}
+
 // Record node v (claimed at level L by the calling lane when `found`) in the
 // distance vector and in the next frontier.  Must be reached by the whole wave.
 template <int BLOCK>
 __device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool found,
-                                           Counters& c) {
+                                           Counters& c, WaveQueue& q) {
   int deg = 0;
   if (found) {
     a.dist[v] = L;
@@ -77,13 +101,17 @@ __device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool
     c.nf += 1;
     c.mf += (u64)deg;
   }
-  LevelSlot* out = &a.ctrl->slot[L % 3];
   const bool small = found && deg > 0 && deg < a.big_degree;
-  int pos = wave_append(&out->small_count, small);
-  if (small) small_q(a, L)[pos] = v;
+  const u64 mask = __ballot(small);
+  if (mask) {
+    const int pos = q.cnt + __popcll(mask & lanes_below());
+    if (small) q.buf[pos] = v;
+    q.cnt += __popcll(mask);
+    if (q.cnt > kWaveBuf - kWave) wq_flush(a, L, q);
+  }
   if (found && deg >= a.big_degree) {
     unsigned nch = (unsigned)((deg + BLOCK - 1) / BLOCK);
-    unsigned base = atom_add(&out->big_chunks, nch);
+    unsigned base = atom_add(&a.ctrl->slot[L % 3].big_chunks, nch);
     int32_t* cu = chunk_u(a, L);
     int32_t* ck = chunk_k(a, L);
     for (unsigned k = 0; k < nch; ++k) {
@@ -96,7 +124,7 @@ __device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool
 // Claim target v (if `has`) at level L: test, then atomic OR on the visited bit.
 template <int BLOCK>
 __device__ __forceinline__ void visit(const SsspArgs& a, int L, u64* vis, int v, bool has,
-                                      Counters& c) {
+                                      Counters& c, WaveQueue& q) {
   bool claimed = false;
   if (has) {
     c.edges += 1;
@@ -107,13 +135,38 @@ __device__ __forceinline__ void visit(const SsspArgs& a, int L, u64* vis, int v,
       claimed = (old & bit) == 0;
     }
   }
-  emit_found<BLOCK>(a, L, v, claimed, c);
+  emit_found<BLOCK>(a, L, v, claimed, c, q);
+}
+
+// Prefix offsets of the kStripes sub-queues of level L-1, in LDS.
+__device__ __forceinline__ void stripe_prefix(const LevelSlot* in, unsigned* pre) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned acc = 0;
+    for (int s = 0; s < kStripes; ++s) {
+      pre[s] = acc;
+      acc += ld_relaxed(&in->small_count[s]);
+    }
+    pre[kStripes] = acc;
+  }
+  __syncthreads();
+}
+
+// Sub-queue holding virtual entry i: largest s with pre[s] <= i.
+__device__ __forceinline__ int stripe_of(const unsigned* pre, unsigned i) {
+  int lo = 0;
+#pragma unroll
+  for (int step = kStripes / 2; step > 0; step >>= 1)
+    if (pre[lo + step] <= i) lo += step;
+  return lo;
 }
 
 template <int BLOCK>
-__device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c) {
+__device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQueue& q,
+                          unsigned* pre) {
   const LevelSlot* in = &a.ctrl->slot[(L - 1) % 3];
-  const unsigned nsmall = ld_relaxed(&in->small_count);
+  stripe_prefix(in, pre);
+  const unsigned nsmall = pre[kStripes];
   const unsigned nchunks = ld_relaxed(&in->big_chunks);
 
   // big-degree nodes: one chunk of BLOCK edges per workgroup iteration
@@ -127,7 +180,7 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c) {
     const int e = start + (int)threadIdx.x;
     const bool has = e < end;
     const int v = has ? a.col[e] : 0;
-    visit<BLOCK>(a, L, vis, v, has, c);
+    visit<BLOCK>(a, L, vis, v, has, c, q);
   }
 
   // small-degree nodes: 64 per wave, union of their rows walked 64 edges a step
@@ -135,12 +188,13 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c) {
   const int wpb = BLOCK / kWave;
   const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
   const unsigned nwaves = gridDim.x * wpb;
-  const int32_t* q = small_q(a, L - 1);
+  const int32_t* q_in = small_q(a, L - 1);
   for (unsigned base = gw * kWave; base < nsmall; base += nwaves * kWave) {
     const unsigned i = base + lane;
     int rs = 0, deg = 0;
     if (i < nsmall) {
-      const int u = q[i];
+      const int s = stripe_of(pre, i);
+      const int u = q_in[(size_t)s * (size_t)a.n + (i - pre[s])];
       rs = a.rp[u];
       deg = a.rp[u + 1] - rs;
     }
@@ -154,13 +208,14 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c) {
       const int deg_j = __shfl(deg, j, kWave);
       const int rs_j = __shfl(rs, j, kWave);
       const int v = has ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
-      visit<BLOCK>(a, L, vis, v, has, c);
+      visit<BLOCK>(a, L, vis, v, has, c, q);
     }
   }
 }
 
 template <int BLOCK>
-__device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, Counters& c) {
+__device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, Counters& c,
+                          WaveQueue& q) {
   const int lane = lane_id();
   const int wpb = BLOCK / kWave;
   const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
@@ -181,13 +236,22 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
       s = a.ip[v];
       e = a.ip[v + 1];
       lim = min(e, s + a.lane_edges);
-      for (int j = s; j < lim; ++j) {
-        const int u = a.isrc[j];
-        c.edges += 1;
-        if ((vin[u >> 6] >> (u & 63)) & 1ull) {
+      int j = s;
+      // four in-neighbours per step keep four independent loads in flight
+      for (; j + 4 <= lim; j += 4) {
+        const int u0 = a.isrc[j], u1 = a.isrc[j + 1], u2 = a.isrc[j + 2], u3 = a.isrc[j + 3];
+        const u64 b0 = vin[u0 >> 6] >> (u0 & 63), b1 = vin[u1 >> 6] >> (u1 & 63);
+        const u64 b2 = vin[u2 >> 6] >> (u2 & 63), b3 = vin[u3 >> 6] >> (u3 & 63);
+        c.edges += 4;
+        if ((b0 | b1 | b2 | b3) & 1ull) {
           found = true;
           break;
         }
+      }
+      for (; !found && j < lim; ++j) {
+        const int u = a.isrc[j];
+        c.edges += 1;
+        if ((vin[u >> 6] >> (u & 63)) & 1ull) found = true;
       }
       rest = !found && lim < e;
     }
@@ -214,26 +278,57 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
     }
     const u64 newbits = __ballot(found);
     if (lane == 0) vout[w] = word | newbits;
-    emit_found<BLOCK>(a, L, v, found, c);
+    emit_found<BLOCK>(a, L, v, found, c, q);
   }
 }
 
+// End of a level step for one workgroup: staged queue entries out, counters
+// summed over the workgroup and added to its stripe.
 template <int BLOCK>
-__device__ __forceinline__ void flush(const SsspArgs& a, int L, Counters& c) {
+__device__ __forceinline__ void finish_level(const SsspArgs& a, int L, Counters& c, WaveQueue& q) {
+  wq_flush(a, L, q);
   block_sum3<BLOCK>(c.nf, c.mf, c.edges);
   if (threadIdx.x == 0) {
     LevelSlot* out = &a.ctrl->slot[L % 3];
-    if (c.nf) atom_add(&out->nf, c.nf);
-    if (c.mf) atom_add(&out->mf, c.mf);
-    if (c.edges) atom_add(&out->edges, c.edges);
+    const int stripe = blockIdx.x % kStripes;
+    if (c.nf) atom_add(&out->nf[stripe], c.nf);
+    if (c.mf) atom_add(&out->mf[stripe], c.mf);
+    if (c.edges) atom_add(&out->edges[stripe], c.edges);
   }
   c.nf = 0;
   c.mf = 0;
   c.edges = 0;
 }
 
+struct SlotSum {
+  unsigned nf;
+  u64 mf;
+  u64 edges;
+};
+
+__device__ __forceinline__ SlotSum sum_slot(const LevelSlot* s) {
+  SlotSum r{0, 0, 0};
+  for (int i = 0; i < kStripes; ++i) {
+    r.nf += ld_relaxed(&s->nf[i]);
+    r.mf += ld_relaxed(&s->mf[i]);
+    r.edges += ld_relaxed(&s->edges[i]);
+  }
+  return r;
+}
+
+// Zero a slot with the calling workgroup's threads (tid / nthreads).
+__device__ __forceinline__ void zero_slot(LevelSlot* s, int tid, int nthreads) {
+  unsigned* w = (unsigned*)s;
+  const int words = (int)(sizeof(LevelSlot) / 4);
+  for (int i = tid; i < words; i += nthreads) w[i] = 0;
+}
+
 // Fold level st.level's counters into the state and choose level st.level+1.
-__device__ void decide(const SsspArgs& a, LevelState& st, const LevelSlot& sl, bool record) {
+// Direction switch in the style of direction-optimising BFS: go bottom-up
+// (pull) when the frontier's out-edges exceed the unvisited out-edges / alpha
+// while the frontier grows, and back top-down (push) when the frontier falls
+// under n / beta while it shrinks.
+__device__ void decide(const SsspArgs& a, LevelState& st, const SlotSum& sl, bool record) {
   const int L = st.level;
   if (sl.nf > 0) st.last_nonempty = L;
   st.mu -= (long long)sl.mf;
@@ -241,6 +336,8 @@ __device__ void decide(const SsspArgs& a, LevelState& st, const LevelSlot& sl, b
   st.source_edges += sl.mf;
   st.reached += sl.nf;
   if (record && L < a.lrec) a.level_nf[L] = (int32_t)sl.nf;
+  const unsigned prev = st.prev_nf;
+  st.prev_nf = sl.nf;
   if (sl.mf == 0) {
     st.done = 1;
     return;
@@ -255,9 +352,9 @@ __device__ void decide(const SsspArgs& a, LevelState& st, const LevelSlot& sl, b
   } else if (a.mode == 2) {
     pull = true;
   } else if (!pull) {
-    if ((double)sl.mf * (double)a.alpha > (double)st.mu) pull = true;
+    if ((double)sl.mf * (double)a.alpha > (double)st.mu && sl.nf > prev) pull = true;
   } else {
-    if ((double)sl.nf * (double)a.beta < (double)a.n) pull = false;
+    if ((double)sl.nf * (double)a.beta < (double)a.n && sl.nf < prev) pull = false;
   }
   st.pull = pull ? 1 : 0;
   st.level = L + 1;
@@ -265,26 +362,7 @@ __device__ void decide(const SsspArgs& a, LevelState& st, const LevelSlot& sl, b
   if (record && st.level < a.lrec) a.level_dir[st.level] = pull ? 2 : 1;
 }
 
-__device__ __forceinline__ LevelSlot load_slot(const LevelSlot* s) {
-  LevelSlot r;
-  r.nf = ld_relaxed(&s->nf);
-  r.small_count = ld_relaxed(&s->small_count);
-  r.big_chunks = ld_relaxed(&s->big_chunks);
-  r.pad = 0;
-  r.mf = ld_relaxed(&s->mf);
-  r.edges = ld_relaxed(&s->edges);
-  return r;
-}
-
-__device__ __forceinline__ void zero_slot(LevelSlot* s) {
-  s->nf = 0;
-  s->small_count = 0;
-  s->big_chunks = 0;
-  s->mf = 0;
-  s->edges = 0;
-}
-
-// Seed the source (one thread).
+// Seed the source (one thread; slots 1 and 2 are zeroed by the caller).
 template <int BLOCK>
 __device__ void seed(const SsspArgs& a) {
   const int s = a.source;
@@ -292,14 +370,11 @@ __device__ void seed(const SsspArgs& a) {
   a.vis0[s >> 6] |= 1ull << (s & 63);
   const int deg = a.rp[s + 1] - a.rp[s];
   LevelSlot* sl = &a.ctrl->slot[0];
-  sl->nf = 1;
-  sl->mf = (u64)deg;
-  sl->edges = 0;
-  sl->small_count = 0;
-  sl->big_chunks = 0;
+  sl->nf[0] = 1;
+  sl->mf[0] = (u64)deg;
   if (deg > 0 && deg < a.big_degree) {
     a.qs0[0] = s;
-    sl->small_count = 1;
+    sl->small_count[0] = 1;
   } else if (deg >= a.big_degree) {
     unsigned nch = (unsigned)((deg + BLOCK - 1) / BLOCK);
     for (unsigned k = 0; k < nch; ++k) {
@@ -308,8 +383,6 @@ __device__ void seed(const SsspArgs& a) {
     }
     sl->big_chunks = nch;
   }
-  zero_slot(&a.ctrl->slot[1]);
-  zero_slot(&a.ctrl->slot[2]);
   LevelState& st = a.ctrl->st;
   st.level = 0;
   st.cur = 0;
@@ -319,6 +392,7 @@ __device__ void seed(const SsspArgs& a) {
   st.last_nonempty = 0;
   st.push_levels = 0;
   st.pull_levels = 0;
+  st.prev_nf = 0;
   st.edges_total = 0;
   st.source_edges = 0;
   st.reached = 0;
@@ -330,11 +404,16 @@ __device__ __forceinline__ void init_fill(const SsspArgs& a) {
   const unsigned nt = gridDim.x * blockDim.x;
   for (unsigned i = tid; i < (unsigned)a.n; i += nt) a.dist[i] = -1;
   for (unsigned w = tid; w < (unsigned)a.nw; w += nt) a.vis0[w] = 0;
+  if (blockIdx.x == 0)
+    for (int i = 0; i < 3; ++i) zero_slot(&a.ctrl->slot[i], threadIdx.x, blockDim.x);
 }
 
 // ------------------------------------------------------- persistent driver --
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a) {
+  __shared__ int32_t qbuf[BLOCK / kWave][kWaveBuf];
+  __shared__ unsigned pre[kStripes + 1];
+  WaveQueue q{qbuf[threadIdx.x / kWave], 0};
   init_fill(a);
   if (!grid_sync(&a.ctrl->bar)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) seed<BLOCK>(a);
@@ -342,24 +421,25 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a) {
 
   LevelState st;
   st.level = 0; st.cur = 0; st.pull = 0; st.done = 0; st.mu = a.m; st.last_nonempty = 0;
-  st.push_levels = 0; st.pull_levels = 0; st.edges_total = 0; st.source_edges = 0; st.reached = 0;
+  st.push_levels = 0; st.pull_levels = 0; st.prev_nf = 0; st.edges_total = 0;
+  st.source_edges = 0; st.reached = 0;
   Counters c{0, 0, 0};
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   for (;;) {
-    const LevelSlot prev = load_slot(&a.ctrl->slot[st.level % 3]);
+    const SlotSum prev = sum_slot(&a.ctrl->slot[st.level % 3]);
     decide(a, st, prev, leader);
     if (st.done) break;
     const int L = st.level;
     u64* vcur = st.cur ? a.vis1 : a.vis0;
     if (st.pull) {
       u64* vnext = st.cur ? a.vis0 : a.vis1;
-      pull_step<BLOCK>(a, L, vcur, vnext, c);
+      pull_step<BLOCK>(a, L, vcur, vnext, c, q);
       st.cur ^= 1;
     } else {
-      push_step<BLOCK>(a, L, vcur, c);
+      push_step<BLOCK>(a, L, vcur, c, q, pre);
     }
-    flush<BLOCK>(a, L, c);
-    if (leader) zero_slot(&a.ctrl->slot[(L + 1) % 3]);
+    finish_level<BLOCK>(a, L, c, q);
+    if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
     if (!grid_sync(&a.ctrl->bar)) return;
   }
   if (leader) a.ctrl->st = st;
@@ -375,15 +455,19 @@ __global__ void sssp_seed(SsspArgs a) {
     seed<BLOCK>(a);
     // choose level 1 from the seed's counters
     LevelState st = a.ctrl->st;
-    decide(a, st, a.ctrl->slot[0], true);
+    SlotSum s0{1, (u64)(a.rp[a.source + 1] - a.rp[a.source]), 0};
+    decide(a, st, s0, true);
     a.ctrl->st = st;
-    a.ctrl->ticket = 0;
   }
 }
 
-// One level: state was chosen by the previous launch's last workgroup.
+// One level; the state was chosen by the decide kernel launched after the
+// previous level (kernel boundaries order the two, no fences needed).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a) {
+  __shared__ int32_t qbuf[BLOCK / kWave][kWaveBuf];
+  __shared__ unsigned pre[kStripes + 1];
+  WaveQueue q{qbuf[threadIdx.x / kWave], 0};
   const LevelState st0 = a.ctrl->st;
   if (st0.done) return;
   const int L = st0.level;
@@ -391,29 +475,31 @@ __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a) {
   u64* vcur = st0.cur ? a.vis1 : a.vis0;
   if (st0.pull) {
     u64* vnext = st0.cur ? a.vis0 : a.vis1;
-    pull_step<BLOCK>(a, L, vcur, vnext, c);
+    pull_step<BLOCK>(a, L, vcur, vnext, c, q);
   } else {
-    push_step<BLOCK>(a, L, vcur, c);
+    push_step<BLOCK>(a, L, vcur, c, q, pre);
   }
-  flush<BLOCK>(a, L, c);
-  __shared__ int last;
-  __syncthreads();
+  finish_level<BLOCK>(a, L, c, q);
+}
+
+// Fold the level just run into the state and choose the next one.
+__global__ void sssp_decide(SsspArgs a) {
+  __shared__ SlotSum sum;
+  __shared__ int go;
+  const LevelState st0 = a.ctrl->st;
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atom_add(&a.ctrl->ticket, 1u);
-    last = (t == gridDim.x - 1);
+    go = !st0.done;
+    if (go) sum = sum_slot(&a.ctrl->slot[st0.level % 3]);
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
+  if (!go) return;
+  const int L = st0.level;
+  zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) {
     LevelState st = st0;
     if (st.pull) st.cur ^= 1;
-    zero_slot(&a.ctrl->slot[(L + 1) % 3]);
-    const LevelSlot cur = load_slot(&a.ctrl->slot[L % 3]);
-    decide(a, st, cur, true);
+    decide(a, st, sum, true);
     a.ctrl->st = st;
-    a.ctrl->ticket = 0;
-    __threadfence();
   }
 }
 
@@ -458,7 +544,7 @@ static dawn_status ws_create(Ctx* ctx, GraphRec* g, std::unique_ptr<SsspWs>* out
   dawn_status s = DAWN_OK;
   for (int i = 0; i < 2 && s == DAWN_OK; ++i) {
     if ((s = alloc((void**)&w->vis[i], nw * 8 + 256)) != DAWN_OK) break;
-    if ((s = alloc((void**)&w->qs[i], (size_t)n * 4 + 256)) != DAWN_OK) break;
+    if ((s = alloc((void**)&w->qs[i], (size_t)kStripes * n * 4 + 256)) != DAWN_OK) break;
     if ((s = alloc((void**)&w->cu[i], chunk_cap * 4)) != DAWN_OK) break;
     if ((s = alloc((void**)&w->ck[i], chunk_cap * 4)) != DAWN_OK) break;
   }
@@ -525,7 +611,7 @@ static dawn_status launch_persistent(Ctx* ctx, SsspWs* w, const SsspArgs& a, int
 
 template <int BLOCK>
 static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, int driver,
-                              int graph_levels, int* launches) {
+                              int graph_levels, int* launches, double* level_ms) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
   hipLaunchKernelGGL(sssp_init_fill<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
   hipLaunchKernelGGL(sssp_seed<BLOCK>, dim3(1), dim3(64), 0, w->stream, a);
@@ -533,14 +619,27 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
   *launches = 2;
   const long long max_launch = (long long)a.n + 2;
   if (driver == 2) {
+    int level_launches = 0;
     for (long long it = 0; it <= max_launch; ++it) {
+      if (level_ms) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
       hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a);
+      if (level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+      hipLaunchKernelGGL(sssp_decide, dim3(1), dim3(64), 0, w->stream, a);
       DAWN_HIP(hipGetLastError());
-      ++*launches;
+      *launches += 2;
+      ++level_launches;
       DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st, &w->ctrl->st, sizeof(LevelState),
                               hipMemcpyDeviceToHost, w->stream));
       DAWN_HIP(hipStreamSynchronize(w->stream));
-      if (w->h_ctrl->st.done) return DAWN_OK;
+      if (level_ms) {
+        float ms = 0.f;
+        DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+        *level_ms += ms;
+      }
+      if (w->h_ctrl->st.done) {
+        if (level_ms) *launches = level_launches;
+        return DAWN_OK;
+      }
     }
     return fail(DAWN_E_DEVICE, "level loop did not terminate");
   }
@@ -563,8 +662,10 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      for (int i = 0; i < graph_levels; ++i)
+      for (int i = 0; i < graph_levels; ++i) {
         hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a);
+        hipLaunchKernelGGL(sssp_decide, dim3(1), dim3(64), 0, cs, a);
+      }
       e = hipStreamEndCapture(cs, &graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&w->gexec, graph, nullptr, nullptr, 0);
@@ -577,7 +678,7 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
   }
   for (long long it = 0; it * graph_levels <= max_launch; ++it) {
     DAWN_HIP(hipGraphLaunch(w->gexec, w->stream));
-    *launches += graph_levels;
+    *launches += 2 * graph_levels;
     DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st, &w->ctrl->st, sizeof(LevelState),
                             hipMemcpyDeviceToHost, w->stream));
     DAWN_HIP(hipStreamSynchronize(w->stream));
@@ -588,7 +689,7 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
 
 template <int BLOCK>
 static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_params& p,
-                                 SsspArgs& a, int* launches) {
+                                 SsspArgs& a, int* launches, double* level_ms) {
   const bool single = g->n <= p.small_n;
   if (p.driver == 1 || single) {
     *launches = 1;
@@ -598,7 +699,7 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
   DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, 0));
   int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
   return run_levels<BLOCK>(ctx, w, a, per_cu * ctx->num_cu, p.driver, std::max(p.graph_levels, 1),
-                           launches);
+                           launches, level_ms);
 }
 
 dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source, int32_t* dist,
@@ -628,19 +729,22 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   SsspArgs a;
   fill_args(a, g, w.get(), p, source, d_dist);
   int launches = 0;
+  const bool level_timing = p.timing == 1 && p.driver == 2 && g->n > p.small_n;
+  double level_ms = 0.0;
+  double* lm = level_timing ? &level_ms : nullptr;
   DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
-    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, &launches); break;
-    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, &launches); break;
-    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, &launches); break;
+    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, &launches, lm); break;
+    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, &launches, lm); break;
+    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, &launches, lm); break;
   }
+  if (!level_timing) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
     hipStreamSynchronize(w->stream);
     w->poisoned = true;
     return st;
   }
-  DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(SsspCtrl), hipMemcpyDeviceToHost,
                           w->stream));
   const int32_t cap = (stats && stats->frontier_cap > 0) ? std::min(stats->frontier_cap, w->lrec) : 0;
@@ -664,7 +768,10 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   }
   if (stats) {
     float ms = 0.f;
-    DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    if (level_timing)
+      ms = (float)level_ms;
+    else
+      DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
     stats->levels = rs.last_nonempty + 1;
     stats->push_levels = rs.push_levels;
     stats->pull_levels = rs.pull_levels;

@@ -70,7 +70,7 @@ class Params(ctypes.Structure):
         ("pull_lane_edges", ctypes.c_int32), ("alpha", ctypes.c_float),
         ("beta", ctypes.c_float), ("graph_levels", ctypes.c_int32),
         ("small_n", ctypes.c_int32), ("batch_alpha", ctypes.c_float),
-        ("batch_lanes", ctypes.c_int32),
+        ("batch_lanes", ctypes.c_int32), ("timing", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
