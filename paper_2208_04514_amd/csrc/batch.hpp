@@ -16,13 +16,13 @@ struct BatchLevel {
   u64 se[kStripes];             // sum over new pairs of the node's out-degree
   u64 mf[kStripes];             // sum of out-degrees of the nodes with a new bit
   u64 edges[kStripes];          // adjacency entries read by the expansion
-  unsigned nfront[kStripes];    // entries of each frontier node sub-list
-  unsigned nchunks[kStripes];   // entries of each frontier out-edge chunk sub-list
+  unsigned nchunks;             // entries of the big-degree out-edge chunk list
+  unsigned pad;
 };
 
 struct BatchLevelSum {
   u64 nodes, bits, se, mf, edges;
-  unsigned nfront, nchunks;
+  unsigned nchunks;
 };
 
 struct BatchCtrl {
@@ -42,11 +42,10 @@ struct BatchArgs {
   u64* nxt[2];                  // [n][W] new bits per level parity
   u64* planes[kMaxPlanes];      // [n][W] bit b of each source's relative level
   int32_t nplanes;              // planes allocated (levels < 2^nplanes)
-  u64* touched;                 // one bit per node: new bits this level
-  int32_t* fl[2];               // frontier node sub-lists per level parity (kStripes x n)
-  int32_t* cu[2];               // frontier out-edge chunk sub-lists: node
-  int32_t* ck[2];               //                                    chunk index
-  size_t chunk_cap;             // entries per chunk sub-list
+  u64* touched[2];              // one bit per node with new bits at a level of that
+                                //   parity: the frontier of the next level
+  int32_t* cu[2];               // out-edge chunks of big-degree frontier nodes: node
+  int32_t* ck[2];               //                                             chunk index
   BatchCtrl* ctrl;
   const u64* act;               // [W] sources still expanding
   int32_t* const* rows;         // [lanes] distance row of each source (device)
@@ -67,17 +66,16 @@ struct BatchWs {
   u64* planes[kMaxPlanes] = {};
   int nplanes = 0;              // allocated
   int planes_dirty = 0;         // planes that may hold bits from an earlier batch
-  u64* touched = nullptr;
-  int32_t* fl[2] = {nullptr, nullptr};
+  u64* touched[2] = {nullptr, nullptr};
   int32_t* cu[2] = {nullptr, nullptr};
   int32_t* ck[2] = {nullptr, nullptr};
-  size_t chunk_cap = 0;
   BatchCtrl* ctrl = nullptr;
   u64* act = nullptr;
   u64* emask = nullptr;         // [64] lanes to emit
   int32_t** rows = nullptr;
   int32_t* base = nullptr;
   int32_t* src = nullptr;
+  int32_t* lane = nullptr;      // lane of each seeded source
   int32_t* stage = nullptr;     // device rows for host-destination calls
   size_t stage_ints = 0;
   BatchCtrl* h_ctrl = nullptr;
@@ -99,8 +97,8 @@ dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t 
 dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
                               bool clear, hipStream_t s);
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
-dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src, int k,
-                              int lane0, hipStream_t s);
+dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src,
+                              const int32_t* d_lane, int k, int L, bool live, hipStream_t s);
 bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, long long m);
 
 }  // namespace dawn

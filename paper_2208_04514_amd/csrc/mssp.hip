@@ -38,7 +38,8 @@
 namespace dawn {
 
 constexpr int kBatchBlock = 256;
-constexpr int kChunk = 32;        // out-edges per push work item
+constexpr int kBigB = 256;        // out-degree from which a frontier node's edges are chunked
+constexpr int kChunkB = 64;       // out-edges per chunk of a big-degree node
 
 // group of P lanes per node: lane w of the group handles word w
 template <int P>
@@ -52,26 +53,14 @@ __device__ __forceinline__ u64 shfl_xor64(u64 x, int m) {
   return ((u64)hi << 32) | lo;
 }
 
-// Prefix of kStripes sub-list lengths in LDS (every thread calls).
-__device__ __forceinline__ void sub_prefix(const unsigned* counts, unsigned* pre) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned acc = 0;
-    for (int s = 0; s < kStripes; ++s) {
-      pre[s] = acc;
-      acc += ld_relaxed(&counts[s]);
-    }
-    pre[kStripes] = acc;
+// Append the out-edge chunks of big-degree node v to level L's chunk list.
+__device__ __forceinline__ void push_chunks(const BatchArgs& a, int L, int v, int deg) {
+  const unsigned nch = (unsigned)((deg + kChunkB - 1) / kChunkB);
+  const unsigned cb = atom_add(&a.ctrl->lv[L & 1].nchunks, nch);
+  for (unsigned k = 0; k < nch; ++k) {
+    a.cu[L & 1][cb + k] = v;
+    a.ck[L & 1][cb + k] = (int32_t)k;
   }
-  __syncthreads();
-}
-
-__device__ __forceinline__ int sub_of(const unsigned* pre, unsigned i) {
-  int lo = 0;
-#pragma unroll
-  for (int step = kStripes / 2; step > 0; step >>= 1)
-    if (pre[lo + step] <= i) lo += step;
-  return lo;
 }
 
 // ------------------------------------------------------------- expansion --
@@ -86,6 +75,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   const u64 actw = wok ? a.act[w] : 0ull;
   const size_t W = (size_t)a.W;
   u64* nxt = a.nxt[L & 1];
+  u64* T = a.touched[L & 1];
   u64 edges = 0;
   const unsigned gw = (blockIdx.x * kBatchBlock + threadIdx.x) / kWave;
   const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
@@ -126,59 +116,102 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     }
     if (acc) nxt[(size_t)v * W + w] = acc;
     const bool any = (__ballot(acc != 0) & gm) != 0;
-    if (any && w == 0) atom_or(&a.touched[v >> 6], 1ull << (v & 63));
+    if (any && w == 0) atom_or(&T[v >> 6], 1ull << (v & 63));
   }
   edges = wave_sum(edges);
   if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges[blockIdx.x % kStripes], edges);
 }
 
+// Push bits f of a frontier node along its edge to v (group-uniform call).
+template <int P>
+__device__ __forceinline__ void relax(const BatchArgs& a, u64* out, u64* T, int v, u64 f, int w,
+                                      u64 gm) {
+  u64 b = 0;
+  if (f) {
+    b = f & ~a.vis[(size_t)v * a.W + w];
+    if (b) atom_or(&out[(size_t)v * a.W + w], b);
+  }
+  const bool any = (__ballot(b != 0) & gm) != 0;
+  if (any && w == 0) {
+    u64* tw = &T[v >> 6];
+    const u64 bit = 1ull << (v & 63);
+    if (!(*tw & bit)) atom_or(tw, bit);
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
-  __shared__ unsigned pre[kStripes + 1];
   const int lane = lane_id();
   const int w = lane & (P - 1);
-  const int gpw = kWave / P;
+  const int npw = kWave / P;
+  const int sub = lane / P;
   const bool wok = w < a.W;
   const u64 gm = group_mask<P>(lane);
   const size_t W = (size_t)a.W;
   const int pl = (L - 1) & 1;
-  sub_prefix(a.ctrl->lv[pl].nchunks, pre);
-  const unsigned nch = pre[kStripes];
-  const int32_t* cu = a.cu[pl];
-  const int32_t* ck = a.ck[pl];
+  const u64* F = a.touched[pl];
   const u64* front = a.nxt[pl];
   u64* out = a.nxt[L & 1];
+  u64* T = a.touched[L & 1];
   u64 edges = 0;
   const unsigned gw = (blockIdx.x * kBatchBlock + threadIdx.x) / kWave;
   const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
-  for (unsigned cb = gw * gpw; cb < nch; cb += nwaves * gpw) {
-    const unsigned c = cb + (unsigned)(lane / P);
+
+  // big-degree frontier nodes: chunks of kChunkB out-edges, one per lane group
+  const unsigned nch = ld_relaxed(&a.ctrl->lv[pl].nchunks);
+  for (unsigned cb = gw * npw; cb < nch; cb += nwaves * npw) {
+    const unsigned c = cb + (unsigned)sub;
     const bool has = c < nch;
     int e0 = 0, e1 = 0;
     u64 f = 0;
     if (has) {
-      const int sidx = sub_of(pre, c);
-      const size_t at = (size_t)sidx * a.chunk_cap + (c - pre[sidx]);
-      const int u = cu[at];
-      const int k = ck[at];
-      e0 = a.rp[u] + k * kChunk;
-      e1 = min(e0 + kChunk, a.rp[u + 1]);
+      const int u = a.cu[pl][c];
+      const int k = a.ck[pl][c];
+      e0 = a.rp[u] + k * kChunkB;
+      e1 = min(e0 + kChunkB, a.rp[u + 1]);
       if (wok) f = front[(size_t)u * W + w];
     }
     if (has && w == 0) edges += (u64)(e1 - e0);
-    for (int e = e0; e < e1; ++e) {
-      const int v = a.col[e];
-      u64 b = 0;
-      if (f) {
-        b = f & ~a.vis[(size_t)v * W + w];
-        if (b) atom_or(&out[(size_t)v * W + w], b);
+    int e = e0;
+    for (; e + 2 <= e1; e += 2) {
+      const int v0 = a.col[e], v1 = a.col[e + 1];
+      relax<P>(a, out, T, v0, f, w, gm);
+      relax<P>(a, out, T, v1, f, w, gm);
+    }
+    for (; e < e1; ++e) relax<P>(a, out, T, a.col[e], f, w, gm);
+  }
+
+  // other frontier nodes, 64 per wave (one frontier word): the wave walks the
+  // union of their out-lists, each lane group taking one edge per step
+  const int nwords = (a.n + 63) / 64;
+  for (unsigned t = gw; t < (unsigned)nwords; t += nwaves) {
+    const u64 fw = F[t];
+    if (!fw) continue;
+    const int u = (int)t * 64 + lane;
+    int deg = 0, rs = 0;
+    if ((fw >> lane) & 1ull) {
+      rs = a.rp[u];
+      deg = a.rp[u + 1] - rs;
+      if (deg >= kBigB) deg = 0;
+    }
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    if (w == 0 && sub == 0) edges += (u64)total;
+    for (int eb = 0; eb < total; eb += npw) {
+      const int x = eb + sub;
+      const bool has = x < total;
+      const int j = wave_owner(incl, has ? x : total - 1);
+      const int inc_j = __shfl(incl, j, kWave);
+      const int deg_j = __shfl(deg, j, kWave);
+      const int rs_j = __shfl(rs, j, kWave);
+      const int uj = (int)t * 64 + j;
+      int v = 0;
+      u64 f = 0;
+      if (has) {
+        v = a.col[rs_j + (x - (inc_j - deg_j))];
+        if (wok) f = front[(size_t)uj * W + w];
       }
-      const bool any = (__ballot(b != 0) & gm) != 0;
-      if (any && w == 0) {
-        u64* tw = &a.touched[v >> 6];
-        const u64 bit = 1ull << (v & 63);
-        if (!(*tw & bit)) atom_or(tw, bit);
-      }
+      relax<P>(a, out, T, v, f, w, gm);
     }
   }
   edges = wave_sum(edges);
@@ -186,15 +219,14 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
 }
 
 // ----------------------------------------------------------------- merge --
-// Fold the new bits of level L into vis and the level planes, build the next
-// frontier (node sub-lists and out-edge chunks), and clear the previous
-// frontier's rows.  One wave per touched tile of 64 nodes (grid-stride).
+// Fold the new bits of level L into vis and the level planes, list the
+// big-degree nodes' out-edge chunks for the next push, and clear the rows and
+// bitmap of the previous frontier.  One wave per 64-node word (grid-stride).
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   __shared__ u64 lmask[kMaxPlanes][64];   // bit b of (L - base) for the lanes of each word
   __shared__ u64 actb[64];
   __shared__ int rank_j[kBatchBlock / kWave][kWave];
-  __shared__ unsigned pre[kStripes + 1];
   __shared__ u64 red[4][kBatchBlock / kWave];
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -212,67 +244,54 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
     for (int b = 0; b < kMaxPlanes; ++b) lmask[b][tid] = mb[b];
     actb[tid] = 0;
   }
-  const int cl = L & 1;
-  BatchLevel* lv = &a.ctrl->lv[cl];
-  // clear the rows of the previous frontier: the expansion of this level has
-  // consumed their bits
-  if (L > 0) {
-    const int pl = (L - 1) & 1;
-    sub_prefix(a.ctrl->lv[pl].nfront, pre);
-    const unsigned nprev = pre[kStripes];
-    u64* prev = a.nxt[pl];
-    const int32_t* fl = a.fl[pl];
-    for (unsigned i = blockIdx.x * (kBatchBlock / kWave) + wv; i < nprev;
-         i += gridDim.x * (kBatchBlock / kWave)) {
-      const int sidx = sub_of(pre, i);
-      const int u = fl[(size_t)sidx * a.n + (i - pre[sidx])];
-      for (int x = lane; x < W; x += kWave) prev[(size_t)u * W + x] = 0;
-    }
-  }
   __syncthreads();
 
+  const int cl = L & 1;
+  BatchLevel* lv = &a.ctrl->lv[cl];
   const int w = lane & (P - 1);
   const int npw = kWave / P;
   const int sub = lane / P;
   const bool wok = w < W;
   const int stripe = blockIdx.x % kStripes;
-  u64* nxt = a.nxt[cl];
-  u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0;
-  const int ntiles = (a.n + 63) / 64;
+  const int nwords = (a.n + 63) / 64;
   const unsigned gw = (blockIdx.x * kBatchBlock + tid) / kWave;
   const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
-  for (unsigned t = gw; t < (unsigned)ntiles; t += nwaves) {
-    const u64 tw = a.touched[t];
+
+  // the previous frontier's bits were consumed by this level's expansion
+  if (L > 0) {
+    u64* F = a.touched[(L - 1) & 1];
+    u64* prev = a.nxt[(L - 1) & 1];
+    for (unsigned t = gw; t < (unsigned)nwords; t += nwaves) {
+      const u64 fw = F[t];
+      if (!fw) continue;
+      const int cnt = __popcll(fw);
+      if ((fw >> lane) & 1ull) rank_j[wv][__popcll(fw & lanes_below())] = lane;
+      __builtin_amdgcn_wave_barrier();
+      for (int i0 = 0; i0 < cnt; i0 += npw) {
+        const int i = i0 + sub;
+        if (i < cnt && wok) prev[(size_t)((int)t * 64 + rank_j[wv][i]) * W + w] = 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) F[t] = 0;
+    }
+  }
+
+  u64* nxt = a.nxt[cl];
+  const u64* T = a.touched[cl];
+  u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0;
+  for (unsigned t = gw; t < (unsigned)nwords; t += nwaves) {
+    const u64 tw = T[t];
     if (tw == 0) continue;
     const int v0 = (int)t * 64;
     const bool mine = (tw >> lane) & 1ull;
-    const int rank = __popcll(tw & lanes_below());
     const int cnt = __popcll(tw);
-    int deg = 0, nch = 0;
+    int deg = 0;
     if (mine) {
-      rank_j[wv][rank] = lane;
+      rank_j[wv][__popcll(tw & lanes_below())] = lane;
       deg = a.rp[v0 + lane + 1] - a.rp[v0 + lane];
-      nch = (deg + kChunk - 1) / kChunk;
-    }
-    const int nch_incl = wave_incl_scan(nch);
-    const int nch_tot = __shfl(nch_incl, kWave - 1, kWave);
-    unsigned fbase = 0, cbase = 0;
-    if (lane == 0) {
-      fbase = atom_add(&lv->nfront[stripe], (unsigned)cnt);
-      if (nch_tot) cbase = atom_add(&lv->nchunks[stripe], (unsigned)nch_tot);
-    }
-    fbase = __shfl(fbase, 0, kWave);
-    cbase = __shfl(cbase, 0, kWave);
-    if (mine) {
-      const int v = v0 + lane;
-      a.fl[cl][(size_t)stripe * a.n + fbase + rank] = v;
-      const size_t c0 = (size_t)stripe * a.chunk_cap + cbase + (nch_incl - nch);
-      for (int k = 0; k < nch; ++k) {
-        a.cu[cl][c0 + k] = v;
-        a.ck[cl][c0 + k] = k;
-      }
       nodes += 1;
       mf += (u64)deg;
+      if (deg >= kBigB) push_chunks(a, L, v0 + lane, deg);
     }
     __builtin_amdgcn_wave_barrier();
     for (int i0 = 0; i0 < cnt; i0 += npw) {
@@ -296,7 +315,6 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
       }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane == 0) a.touched[t] = 0;
   }
   // lanes w, w+P, ... hold the same word: fold them, then once per block
   for (int off = P; off < kWave; off <<= 1) act_acc |= shfl_xor64(act_acc, off);
@@ -376,13 +394,25 @@ __global__ __launch_bounds__(kBatchBlock) void batch_zero(u64* p, size_t count) 
     p[i] = 0;
 }
 
-// lane lane0 + r of the batch starts at node src[r]: bit of nxt[0][src[r]], node touched
-__global__ void batch_seed(BatchArgs a, const int32_t* src, int k, int lane0) {
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < k; r += gridDim.x * blockDim.x) {
-    const int s = src[r];
-    const int l = lane0 + r;
-    atom_or(&a.nxt[0][(size_t)s * a.W + (l >> 6)], 1ull << (l & 63));
-    atom_or(&a.touched[s >> 6], 1ull << (s & 63));
+// Lane lane[i] starts at node src[i] at level L: its bit joins the new bits
+// of level L (nxt) and the node joins that level's frontier bitmap.  With
+// `live` (sources admitted after level L's merge ran) the seed also does the
+// merge's part: the visited bit and the big-degree chunks.
+__global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane, int k, int L,
+                           int live) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const int s = src[i];
+    const int l = lane[i];
+    const size_t idx = (size_t)s * a.W + (l >> 6);
+    const u64 bit = 1ull << (l & 63);
+    atom_or(&a.nxt[L & 1][idx], bit);
+    const u64 sbit = 1ull << (s & 63);
+    const u64 old = atom_or(&a.touched[L & 1][s >> 6], sbit);
+    if (live) {
+      atom_or(&a.vis[idx], bit);
+      const int deg = a.rp[s + 1] - a.rp[s];
+      if (!(old & sbit) && deg >= kBigB) push_chunks(a, L, s, deg);
+    }
   }
 }
 
@@ -394,9 +424,8 @@ void batch_ws_destroy(BatchWs* w) {
   dev_free(ctx, w->nxt[0], 0);
   dev_free(ctx, w->nxt[1], 0);
   for (int b = 0; b < kMaxPlanes; ++b) dev_free(ctx, w->planes[b], 0);
-  dev_free(ctx, w->touched, 0);
   for (int i = 0; i < 2; ++i) {
-    dev_free(ctx, w->fl[i], 0);
+    dev_free(ctx, w->touched[i], 0);
     dev_free(ctx, w->cu[i], 0);
     dev_free(ctx, w->ck[i], 0);
   }
@@ -406,6 +435,7 @@ void batch_ws_destroy(BatchWs* w) {
   dev_free(ctx, w->rows, 0);
   dev_free(ctx, w->base, 0);
   dev_free(ctx, w->src, 0);
+  dev_free(ctx, w->lane, 0);
   dev_free(ctx, w->stage, 0);
   if (ctx) ctx->used -= w->bytes;
   if (w->h_ctrl) hipHostFree(w->h_ctrl);
@@ -425,8 +455,9 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   w->Wmax = W;
   const size_t n = (size_t)g->n;
   const size_t nw = (n + 63) / 64;
-  // per level at most sum over nodes of ceil(deg / kChunk) <= m / kChunk + n chunks
-  w->chunk_cap = (size_t)(g->m / kChunk) + n + 64;
+  // chunks per level: sum over frontier nodes of degree >= kBigB of
+  // ceil(deg / kChunkB) <= m / kChunkB + m / kBigB
+  const size_t chunk_cap = (size_t)(g->m / kChunkB) + (size_t)(g->m / kBigB) + 64;
   dawn_status s = DAWN_OK;
   auto alloc = [&](void** p, size_t bytes) {
     if (s != DAWN_OK) return;
@@ -436,11 +467,10 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   alloc((void**)&w->vis, n * W * 8);
   alloc((void**)&w->nxt[0], n * W * 8);
   alloc((void**)&w->nxt[1], n * W * 8);
-  alloc((void**)&w->touched, nw * 8 + 64);
   for (int i = 0; i < 2; ++i) {
-    alloc((void**)&w->fl[i], (size_t)kStripes * n * 4 + 64);
-    alloc((void**)&w->cu[i], (size_t)kStripes * w->chunk_cap * 4);
-    alloc((void**)&w->ck[i], (size_t)kStripes * w->chunk_cap * 4);
+    alloc((void**)&w->touched[i], nw * 8 + 64);
+    alloc((void**)&w->cu[i], chunk_cap * 4);
+    alloc((void**)&w->ck[i], chunk_cap * 4);
   }
   alloc((void**)&w->ctrl, sizeof(BatchCtrl));
   alloc((void**)&w->act, 64 * 8);
@@ -448,6 +478,7 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   alloc((void**)&w->rows, (size_t)4096 * sizeof(int32_t*));
   alloc((void**)&w->base, (size_t)4096 * 4);
   alloc((void**)&w->src, (size_t)4096 * 4);
+  alloc((void**)&w->lane, (size_t)4096 * 4);
   if (stage_ints) alloc((void**)&w->stage, stage_ints * 4);
   w->stage_ints = stage_ints;
   if (s != DAWN_OK) {
@@ -498,13 +529,11 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W) {
   a.nxt[1] = w->nxt[1];
   for (int b = 0; b < kMaxPlanes; ++b) a.planes[b] = w->planes[b];
   a.nplanes = w->nplanes;
-  a.touched = w->touched;
   for (int i = 0; i < 2; ++i) {
-    a.fl[i] = w->fl[i];
+    a.touched[i] = w->touched[i];
     a.cu[i] = w->cu[i];
     a.ck[i] = w->ck[i];
   }
-  a.chunk_cap = w->chunk_cap;
   a.ctrl = w->ctrl;
   a.act = w->act;
   a.rows = w->rows;
@@ -521,9 +550,8 @@ BatchLevelSum batch_level_sum(const BatchLevel& l) {
     s.se += l.se[i];
     s.mf += l.mf[i];
     s.edges += l.edges[i];
-    s.nfront += l.nfront[i];
-    s.nchunks += l.nchunks[i];
   }
+  s.nchunks = l.nchunks;
   return s;
 }
 
@@ -599,10 +627,11 @@ dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s) {
   return DAWN_OK;
 }
 
-dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src, int k, int lane0,
-                              hipStream_t s) {
+dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src,
+                              const int32_t* d_lane, int k, int L, bool live, hipStream_t s) {
   (void)ctx;
-  hipLaunchKernelGGL(batch_seed, dim3((k + 255) / 256), dim3(256), 0, s, a, d_src, k, lane0);
+  hipLaunchKernelGGL(batch_seed, dim3((k + 255) / 256), dim3(256), 0, s, a, d_src, d_lane, k, L,
+                     live ? 1 : 0);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }
@@ -635,7 +664,10 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
   if (k % 64) em[W - 1] = (1ull << (k % 64)) - 1ull;
   std::vector<int32_t*> rows(64 * W, nullptr);
   for (int r = 0; r < k; ++r) rows[r] = h_rows[r];
+  std::vector<int32_t> lanes(k);
+  for (int r = 0; r < k; ++r) lanes[r] = r;
   DAWN_HIP(hipMemcpyAsync(w->src, h_src, (size_t)k * 4, hipMemcpyHostToDevice, s));
+  DAWN_HIP(hipMemcpyAsync(w->lane, lanes.data(), (size_t)k * 4, hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemcpyAsync(w->rows, rows.data(), rows.size() * sizeof(int32_t*),
                           hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemcpyAsync(w->base, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, s));
@@ -645,11 +677,12 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
   DAWN_TRY(batch_launch_zero(ctx, w->vis, nW, s));
   DAWN_TRY(batch_launch_zero(ctx, w->nxt[0], nW, s));
   DAWN_TRY(batch_launch_zero(ctx, w->nxt[1], nW, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->touched, ((size_t)g->n + 63) / 64, s));
+  DAWN_TRY(batch_launch_zero(ctx, w->touched[0], ((size_t)g->n + 63) / 64, s));
+  DAWN_TRY(batch_launch_zero(ctx, w->touched[1], ((size_t)g->n + 63) / 64, s));
   for (int b = 0; b < w->planes_dirty; ++b) DAWN_TRY(batch_launch_zero(ctx, w->planes[b], nW, s));
   w->planes_dirty = 0;
   BatchArgs a = batch_args(g, w, W);
-  DAWN_TRY(batch_launch_seed(ctx, a, w->src, k, 0, s));
+  DAWN_TRY(batch_launch_seed(ctx, a, w->src, w->lane, k, 0, false, s));
   DAWN_TRY(batch_launch_merge(ctx, a, 0, s));
   int launches = 7 + w->planes_dirty;
   int last_nonempty = 0;

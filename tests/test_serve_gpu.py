@@ -1,0 +1,183 @@
+"""Serving: continuous batching through dawn_serve_submit / dawn_serve_poll.
+
+Every served row must equal the oracle's row for its source, and a query's
+rows must be identical whether it runs alone (dawn_mssp) or mixed with other
+queries that join and leave the shared batch (tolerance 0: integers).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from paper_2208_04514_amd import dawn as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _wait(ctx, t, timeout_s=60):
+    st, q = D.dawn_serve_wait(ctx, t, int(timeout_s * 1000))
+    assert st == D.DAWN_OK, f"ticket {t} still pending after {timeout_s}s"
+    return q
+
+
+def _log_uniform_k(rng, hi):
+    return int(np.floor(np.exp(rng.uniform(0, np.log(hi + 1)))))
+
+
+@pytest.fixture
+def lanes(ctx):
+    saved = []
+
+    def _set(h, n):
+        saved.append((h, D.dawn_get_params(ctx, h)))
+        D.dawn_set_params(ctx, h, batch_lanes=n)
+    yield _set
+    for h, p in reversed(saved):
+        D.dawn_set_params(ctx, h, **p)
+
+
+def test_single_query_host_and_device(ctx, upload):
+    import torch
+    h, g, src = upload("rmat12")
+    out = np.full((10, g.n), 77, np.int32)
+    t = D.dawn_serve_submit(ctx, h, src[:10], out)
+    q = _wait(ctx, t)
+    assert np.array_equal(out, oracle.mssp(g, src[:10]))
+    assert q["k"] == 10 and q["submit_ns"] <= q["admit_ns"] <= q["done_ns"]
+    assert q["levels"] == int(out.max()) + 1
+    dev = torch.full((5, g.n), 3, dtype=torch.int32, device="cuda")
+    t = D.dawn_serve_submit(ctx, h, src[10:15], dev)
+    _wait(ctx, t)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), oracle.mssp(g, src[10:15]))
+
+
+def test_poll_semantics(ctx, upload):
+    h, g, src = upload("uniform4096")
+    out = np.empty((2, g.n), np.int32)
+    t = D.dawn_serve_submit(ctx, h, src[:2], out)
+    _wait(ctx, t)
+    with pytest.raises(D.DawnError) as ei:
+        D.dawn_serve_poll(ctx, t)
+    assert ei.value.status == D.DAWN_E_NOT_FOUND
+    with pytest.raises(D.DawnError) as ei:
+        D.dawn_serve_poll(ctx, 123456789)
+    assert ei.value.status == D.DAWN_E_NOT_FOUND
+
+
+def test_mix_equals_alone(ctx, upload, lanes):
+    """Many queries of uneven size on one graph share the batch; each equals
+    its rows run alone and the oracle's rows."""
+    h, g, _ = upload("rmat12")
+    lanes(h, 512)
+    rng = np.random.default_rng(5)
+    queries = []
+    for i in range(40):
+        k = _log_uniform_k(rng, 200)
+        srcs = rng.integers(0, g.n, size=k).astype(np.int32)
+        queries.append(srcs)
+    outs, tickets = [], []
+    for srcs in queries:
+        out = np.full((srcs.size, g.n), -7, np.int32)
+        outs.append(out)
+        tickets.append(D.dawn_serve_submit(ctx, h, srcs, out))
+    peaks = []
+    for t in tickets:
+        peaks.append(_wait(ctx, t)["batch_peak"])
+    _say(f"[serve] mix: batch peaks {sorted(peaks)[-5:]}")
+    assert max(peaks) > max(q.size for q in queries), "queries never shared a batch"
+    for srcs, out in zip(queries, outs):
+        alone, _ = D.dawn_mssp(ctx, h, srcs)
+        assert np.array_equal(out, alone)
+        assert np.array_equal(out, oracle.mssp(g, srcs, threads=8))
+
+
+def test_join_mid_flight(ctx, upload, lanes):
+    """A query submitted while a long traversal runs is admitted at a later
+    level of the same batch (its distances still start at 0)."""
+    h, g, src = upload("grid128ns")       # hundreds of levels
+    lanes(h, 256)
+    first = np.full((4, g.n), -9, np.int32)
+    t1 = D.dawn_serve_submit(ctx, h, src[:4], first)
+    time.sleep(0.005)
+    late = []
+    for i in range(6):
+        out = np.full((3, g.n), -9, np.int32)
+        late.append((src[4 + i:7 + i].copy(), out, D.dawn_serve_submit(ctx, h, src[4 + i:7 + i], out)))
+        time.sleep(0.002)
+    q1 = _wait(ctx, t1)
+    joined_mid = 0
+    for srcs, out, t in late:
+        q = _wait(ctx, t)
+        if q["admit_ns"] < q1["done_ns"]:
+            joined_mid += 1
+        assert np.array_equal(out, oracle.mssp(g, srcs))
+    assert np.array_equal(first, oracle.mssp(g, src[:4]))
+    _say(f"[serve] {joined_mid} of {len(late)} late queries joined while the first ran "
+         f"({q1['levels']} levels)")
+    assert joined_mid >= 1
+
+
+def test_three_graphs_concurrently(ctx, upload):
+    graphs = [upload(name) for name in ("rmat12", "grid128", "uniform4096")]
+    rng = np.random.default_rng(9)
+    work = []
+    for i in range(30):
+        h, g, _ = graphs[i % 3]
+        k = _log_uniform_k(rng, 64)
+        srcs = rng.integers(0, g.n, size=k).astype(np.int32)
+        out = np.empty((k, g.n), np.int32)
+        work.append((g, srcs, out, D.dawn_serve_submit(ctx, h, srcs, out)))
+    for g, srcs, out, t in work:
+        _wait(ctx, t)
+        assert np.array_equal(out, oracle.mssp(g, srcs))
+
+
+def test_errors(ctx, upload, lanes):
+    h, g, src = upload("uniform4096")
+    lanes(h, 128)
+    with pytest.raises(D.DawnError) as ei:      # more sources than lanes
+        D.dawn_serve_submit(ctx, h, np.zeros(129, np.int32), np.empty((129, g.n), np.int32))
+    assert ei.value.status == D.DAWN_E_INVALID_ARG
+    with pytest.raises(D.DawnError) as ei:
+        D.dawn_serve_submit(ctx, h, np.array([g.n], np.int32), np.empty((1, g.n), np.int32))
+    assert ei.value.status == D.DAWN_E_INVALID_ARG
+    with pytest.raises(D.DawnError) as ei:
+        D.dawn_serve_submit(ctx, 99999, np.array([0], np.int32), np.empty((1, g.n), np.int32))
+    assert ei.value.status == D.DAWN_E_NOT_FOUND
+
+
+def test_budget_queues_and_never_fits(dawn_lib):
+    """Under a tiny HBM budget queries wait for memory and still complete; a
+    query that can never fit is refused with DAWN_E_NO_MEMORY."""
+    g, src = gg.load_config("uniform4096")
+    ctx = D.dawn_create(0, 4 << 20)
+    try:
+        h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+        D.dawn_set_params(ctx, h, batch_lanes=256)
+        with pytest.raises(D.DawnError) as ei:      # 256 rows x 16 KiB = 4 MiB of staging alone
+            D.dawn_serve_submit(ctx, h, np.arange(256, dtype=np.int32),
+                                np.empty((256, g.n), np.int32))
+        assert ei.value.status == D.DAWN_E_NO_MEMORY
+        outs, tickets = [], []
+        rng = np.random.default_rng(1)
+        for i in range(12):
+            srcs = rng.integers(0, g.n, size=60).astype(np.int32)   # ~1 MiB staging each
+            out = np.empty((60, g.n), np.int32)
+            outs.append((srcs, out))
+            tickets.append(D.dawn_serve_submit(ctx, h, srcs, out))
+        for t in tickets:
+            _wait(ctx, t)
+        for srcs, out in outs:
+            assert np.array_equal(out, oracle.mssp(g, srcs))
+        used, budget = D.dawn_memory(ctx)
+        assert used <= budget
+    finally:
+        D.dawn_destroy(ctx)
