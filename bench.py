@@ -100,6 +100,124 @@ def level_kernel_timing(D, ctx, h, src, out):
     return ms, launches
 
 
+def component_edge_sums(g):
+    """Per node: sum of out-degrees over its weakly connected component.
+
+    For a symmetric graph this is E_reach of every source in the component
+    (reachability = the component), the GTEPS numerator of a served source."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    a = csr_matrix((np.ones(g.m, dtype=np.int8), g.col, g.row_ptr), shape=(g.n, g.n))
+    _, lab = connected_components(a, directed=True, connection="weak")
+    sums = np.bincount(lab, weights=g.out_degree().astype(np.float64))
+    return sums[lab].astype(np.int64)
+
+
+def serve_run(D, ctx, graphs, queries, arrivals=None, window=48):
+    """Submit `queries` [(graph index, sources)], at `arrivals` (seconds from
+    start; None = keep `window` queries in flight), and collect latencies."""
+    import torch
+    t0 = time.perf_counter()
+    inflight = {}
+    lat, se, ks = [], 0, 0
+    i = 0
+    while i < len(queries) or inflight:
+        now = time.perf_counter() - t0
+        while i < len(queries) and (
+                (arrivals is None and len(inflight) < window) or
+                (arrivals is not None and arrivals[i] <= now)):
+            gi, srcs = queries[i]
+            h, g, esum = graphs[gi]
+            out = torch.empty((srcs.size, g.n), dtype=torch.int32, device="cuda")
+            t = D.dawn_serve_submit(ctx, h, srcs, out)
+            inflight[t] = (out, int(esum[srcs].sum()), srcs.size)
+            i += 1
+        progressed = False
+        for t in list(inflight):
+            st, q = D.dawn_serve_poll(ctx, t)
+            if st == D.DAWN_OK:
+                out, e, k = inflight.pop(t)
+                lat.append((q["done_ns"] - q["submit_ns"]) / 1e6)
+                se += e
+                ks += k
+                progressed = True
+        if not progressed:
+            time.sleep(0.0002)
+    dt = time.perf_counter() - t0
+    return dt, np.array(lat), se, ks
+
+
+def serving_bench(D, ctx, nq=200, seed=105):
+    """Three resident graphs, queries of 1..1024 sources (log-uniform), first
+    saturated (a window of queries in flight), then Poisson arrivals at 0.5
+    and 0.9 of the saturated query rate."""
+    import graphgen as gg
+    graphs = []
+    for name in ("rmat16", "rmat20", "grid1024"):
+        g, _ = gg.load_config(name)
+        h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+        graphs.append((h, g, component_edge_sums(g)))
+    rng = np.random.default_rng(seed)
+    queries = []
+    for _ in range(nq):
+        gi = int(rng.integers(0, 3))
+        k = int(np.floor(np.exp(rng.uniform(0, np.log(1025)))))
+        k = max(1, min(k, 1024))
+        pool = graphs[gi][1].meta["wcc_nodes"]
+        queries.append((gi, rng.choice(pool, size=k, replace=False).astype(np.int32)))
+    warm = queries[:20]
+    serve_run(D, ctx, graphs, warm)
+    dt, lat, se, ks = serve_run(D, ctx, graphs, queries)
+    cap_qps = len(queries) / dt
+    res = {"graphs": ["rmat16", "rmat20", "grid1024"], "queries": nq,
+           "mean_k": round(float(np.mean([q[1].size for q in queries])), 1),
+           "saturated": {"qps": round(cap_qps, 1), "sources_per_s": round(ks / dt, 1),
+                         "gteps": round(se / dt / 1e9, 2),
+                         "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3)}}
+    for frac in (0.5, 0.9):
+        lam = frac * cap_qps
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
+        dt, lat, se, ks = serve_run(D, ctx, graphs, queries, arrivals=arr)
+        res[f"load_{frac}"] = {"offered_qps": round(lam, 1), "gteps": round(se / dt / 1e9, 2),
+                               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                               "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    used, budget = D.dawn_memory(ctx)
+    res["hbm_used_gb"] = round(used / 1e9, 2)
+    for h, _, _ in graphs:
+        D.dawn_graph_release(ctx, h)
+    return res
+
+
+def roofline_only(D, ctx, params_json):
+    """The level-kernel measurement alone (for profiling), with fixed knobs,
+    then a 256 MiB device copy whose counters calibrate FETCH/WRITE_SIZE."""
+    import torch
+    import graphgen as gg
+    g, src = gg.load_config("rmat20")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
+    p = json.loads(params_json) if params_json else {}
+    if p:
+        D.dawn_set_params(ctx, h, **p)
+    lk_ms, lk_launches = level_kernel_timing(D, ctx, h, src, out)
+    levels = []
+    for i, s in enumerate(src):
+        _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
+        levels.append(st["levels"])
+    alg = plain_alg_bytes(g, out.cpu().numpy(), levels)
+    a = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    achieved = alg / (lk_ms / 1e3) / 1e9
+    print(json.dumps({"kernel": "sssp_level", "launches": lk_launches,
+                      "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
+                      "alg_bytes_per_launch": round(alg / lk_launches, 1),
+                      "achieved_gbs": round(achieved, 2), "frac": round(achieved / HBM_PEAK_GBS, 5),
+                      "calibration_copy_bytes": 2 * a.numel() * 4, "params": p}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +225,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=64)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the level-kernel timing pass (for rocprofv3)")
+    ap.add_argument("--params", default="", help="JSON knobs for --roofline-only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method shards over sources (no collectives), "
@@ -118,6 +240,11 @@ def main():
     import torch
     import graphgen as gg
     from paper_2208_04514_amd import dawn as D
+
+    if args.roofline_only:
+        ctx = D.dawn_create(0, 0)
+        roofline_only(D, ctx, args.params)
+        return
 
     _log("[bench] generating R-MAT 20")
     g, src = gg.load_config("rmat20")
@@ -184,6 +311,10 @@ def main():
                                               "batch_alpha")},
         }
         D.dawn_graph_release(ctx, h2)
+
+    if not args.no_serve:
+        _log("[bench] serving: R-MAT 16, R-MAT 20, grid 1024^2")
+        extra["served"] = serving_bench(D, ctx)
 
     cpu = None
     if not args.no_cpu:

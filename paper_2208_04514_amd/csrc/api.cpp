@@ -24,28 +24,47 @@ dawn_status fail(dawn_status st, const char* fmt, ...) {
 
 void clear_error() { g_err[0] = 0; }
 
-dawn_status dev_alloc(Ctx* ctx, void** p, size_t bytes) {
+dawn_status dev_alloc(Ctx* ctx, void** p, size_t bytes, bool from_reserve) {
   *p = nullptr;
   if (bytes == 0) bytes = 1;
+  // failure injection ($DAWN_FAIL_ALLOC_AFTER = N): the allocation after the
+  // next N fails once, then allocations succeed again
   long long left = ctx->fail_after.load();
   if (left >= 0) {
-    if (left == 0) return fail(DAWN_E_NO_MEMORY, "device allocation refused (injected failure)");
     ctx->fail_after.fetch_sub(1);
+    if (left == 0) return fail(DAWN_E_NO_MEMORY, "device allocation refused (injected failure)");
   }
-  uint64_t used = ctx->used.fetch_add(bytes) + bytes;
-  if (used > ctx->budget) {
-    ctx->used.fetch_sub(bytes);
-    return fail(DAWN_E_NO_MEMORY, "HBM budget exceeded: need %zu more bytes, %llu of %llu in use",
-                bytes, (unsigned long long)(used - bytes), (unsigned long long)ctx->budget);
+  std::lock_guard<std::mutex> lk(ctx->budget_mu);
+  const uint64_t used = ctx->used.load(), res = ctx->reserved.load();
+  if (from_reserve) {
+    if (res < bytes) return fail(DAWN_E_NO_MEMORY, "reservation exhausted");
+  } else if (used + res + bytes > ctx->budget) {
+    return fail(DAWN_E_NO_MEMORY, "HBM budget exceeded: need %zu more bytes, %llu in use, "
+                "%llu reserved, budget %llu", bytes, (unsigned long long)used,
+                (unsigned long long)res, (unsigned long long)ctx->budget);
   }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
-    ctx->used.fetch_sub(bytes);
     *p = nullptr;
     (void)hipGetLastError();
     return fail(DAWN_E_NO_MEMORY, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
   }
+  ctx->used += bytes;
+  if (from_reserve) ctx->reserved -= bytes;
   return DAWN_OK;
+}
+
+dawn_status dev_reserve(Ctx* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> lk(ctx->budget_mu);
+  if (ctx->used.load() + ctx->reserved.load() + bytes > ctx->budget)
+    return fail(DAWN_E_NO_MEMORY, "HBM budget exceeded: cannot set aside %zu bytes", bytes);
+  ctx->reserved += bytes;
+  return DAWN_OK;
+}
+
+void dev_unreserve(Ctx* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> lk(ctx->budget_mu);
+  ctx->reserved -= std::min<uint64_t>(bytes, ctx->reserved.load());
 }
 
 void dev_free(Ctx* ctx, void* p, size_t bytes) {

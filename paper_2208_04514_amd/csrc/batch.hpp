@@ -66,6 +66,7 @@ struct BatchWs {
   u64* planes[kMaxPlanes] = {};
   int nplanes = 0;              // allocated
   int planes_dirty = 0;         // planes that may hold bits from an earlier batch
+  size_t plane_reserve = 0;     // budget set aside for planes not yet allocated
   u64* touched[2] = {nullptr, nullptr};
   int32_t* cu[2] = {nullptr, nullptr};
   int32_t* ck[2] = {nullptr, nullptr};

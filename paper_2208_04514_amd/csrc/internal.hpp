@@ -124,8 +124,11 @@ struct SsspArgs {
 struct Ctx;
 struct GraphRec;
 
-// Device memory accounted against the context's budget.
-dawn_status dev_alloc(Ctx* ctx, void** p, size_t bytes);
+// Device memory accounted against the context's budget.  Budget can be set
+// aside with dev_reserve; an allocation `from_reserve` draws on it.
+dawn_status dev_alloc(Ctx* ctx, void** p, size_t bytes, bool from_reserve = false);
+dawn_status dev_reserve(Ctx* ctx, size_t bytes);
+void dev_unreserve(Ctx* ctx, size_t bytes);
 void dev_free(Ctx* ctx, void* p, size_t bytes);
 
 template <class T>
@@ -194,8 +197,10 @@ struct Ctx {
   int coop = 0;
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};
+  std::atomic<uint64_t> reserved{0};       // budget set aside (serving engines' level planes)
   std::atomic<long long> fail_after{-1};   // failure injection: allocations left before failing
   std::mutex mu;
+  std::mutex budget_mu;
   std::map<int32_t, std::shared_ptr<GraphRec>> graphs;
   int32_t next_graph = 0;
   Server* server = nullptr;

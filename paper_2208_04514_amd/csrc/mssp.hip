@@ -438,6 +438,7 @@ void batch_ws_destroy(BatchWs* w) {
   dev_free(ctx, w->lane, 0);
   dev_free(ctx, w->stage, 0);
   if (ctx) ctx->used -= w->bytes;
+  if (ctx && w->plane_reserve) dev_unreserve(ctx, w->plane_reserve);
   if (w->h_ctrl) hipHostFree(w->h_ctrl);
   if (w->ev0) hipEventDestroy(w->ev0);
   if (w->ev1) hipEventDestroy(w->ev1);
@@ -505,7 +506,9 @@ dawn_status batch_ensure_planes(BatchWs* w, int need, int W) {
   const size_t bytes = (size_t)w->n * (size_t)w->Wmax * 8;
   while (w->nplanes < need) {
     u64* p = nullptr;
-    DAWN_TRY(dev_alloc(w->ctx, (void**)&p, bytes));
+    const bool res = w->plane_reserve >= bytes;
+    DAWN_TRY(dev_alloc(w->ctx, (void**)&p, bytes, res));
+    if (res) w->plane_reserve -= bytes;
     w->bytes += bytes;
     DAWN_HIP(hipMemsetAsync(p, 0, bytes, w->stream));
     w->planes[w->nplanes++] = p;

@@ -152,6 +152,15 @@ static dawn_status engine_create(Server* S, const std::shared_ptr<GraphRec>& g, 
     engine_destroy_raw(e);
     return st;
   }
+  // set budget aside for every level plane the engine may need, so a running
+  // batch never stalls on memory held by queries waiting to join it
+  const size_t plane_bytes = (size_t)g->n * e->ws->Wmax * 8;
+  st = dev_reserve(S->ctx, plane_bytes * kMaxPlanes);
+  if (st != DAWN_OK) {
+    engine_destroy_raw(e);
+    return st;
+  }
+  e->ws->plane_reserve = plane_bytes * kMaxPlanes;
   e->owner.assign(e->capacity, nullptr);
   e->busy.assign(e->W, 0);
   e->act.assign(e->W, 0);
@@ -534,7 +543,7 @@ dawn_status serve_submit(Ctx* ctx, int32_t graph, const int32_t* sources, int32_
       return fail(DAWN_E_INVALID_ARG, "sources[%d] = %d outside [0, %d)", r, sources[r], g->n);
   // a query that can never fit the budget fails now
   const int W = (capacity + 63) / 64;
-  const uint64_t engine_bytes = (uint64_t)g->n * W * 8 * 4;   // vis, two nxt, one plane
+  const uint64_t engine_bytes = (uint64_t)g->n * W * 8 * (3 + kMaxPlanes);   // vis, nxt, planes
   const uint64_t stage = (flags & DAWN_DEVICE_OUT) ? 0 : (uint64_t)k * g->n * 4;
   if (engine_bytes + stage + g->bytes > ctx->budget)
     return fail(DAWN_E_NO_MEMORY, "query needs %llu bytes beyond the graph, budget is %llu",
