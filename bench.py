@@ -85,19 +85,22 @@ def run_plain(D, ctx, h, g, src, out, steps, warmup):
 
 def level_kernel_timing(D, ctx, h, src, out):
     """Per-launch time of the level-step kernel, measured with HIP events that
-    bracket each launch on the stream it runs on (library timing mode 1)."""
+    bracket each launch on the stream it runs on (library timing mode 1).
+    Returns (total ms, launches, levels per source)."""
     p = D.dawn_get_params(ctx, h)
     D.dawn_set_params(ctx, h, driver=2, timing=1)
     ms = 0.0
     launches = 0
+    levels = []
     try:
         for i, s in enumerate(src):
             _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
             ms += st["kernel_ms"]
             launches += st["launches"]
+            levels.append(st["levels"])
     finally:
         D.dawn_set_params(ctx, h, **p)
-    return ms, launches
+    return ms, launches, levels
 
 
 def component_edge_sums(g):
@@ -200,13 +203,12 @@ def roofline_only(D, ctx, params_json):
     p = json.loads(params_json) if params_json else {}
     if p:
         D.dawn_set_params(ctx, h, **p)
-    lk_ms, lk_launches = level_kernel_timing(D, ctx, h, src, out)
-    levels = []
-    for i, s in enumerate(src):
-        _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
-        levels.append(st["levels"])
+    lk_ms, lk_launches, levels = level_kernel_timing(D, ctx, h, src, out)
     alg = plain_alg_bytes(g, out.cpu().numpy(), levels)
-    a = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+    # counter calibration: 1 GiB written, then copied (read 1 GiB, write 1 GiB);
+    # the source is 4x the 256 MiB memory-side cache, so the copy reads HBM
+    a = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
+    a.fill_(1)
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
@@ -215,7 +217,8 @@ def roofline_only(D, ctx, params_json):
                       "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
                       "alg_bytes_per_launch": round(alg / lk_launches, 1),
                       "achieved_gbs": round(achieved, 2), "frac": round(achieved / HBM_PEAK_GBS, 5),
-                      "calibration_copy_bytes": 2 * a.numel() * 4, "params": p}), flush=True)
+                      "calibration_copy_read_bytes": a.numel() * 4,
+                      "calibration_copy_write_bytes": b.numel() * 4, "params": p}), flush=True)
 
 
 def main():
@@ -265,9 +268,9 @@ def main():
     ms_per_step = dt / args.steps * 1e3
 
     # roofline of the level-step kernel
-    lk_ms, lk_launches = level_kernel_timing(D, ctx, h, src, out)
+    lk_ms, lk_launches, lk_levels = level_kernel_timing(D, ctx, h, src, out)
     dist_rows = out.cpu().numpy()
-    alg = plain_alg_bytes(g, dist_rows, levels[: src.size])
+    alg = plain_alg_bytes(g, dist_rows, lk_levels)
     achieved = alg / (lk_ms / 1e3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -88,7 +88,8 @@ typedef struct dawn_run_stats {
 typedef struct dawn_params {
   int32_t driver;             /* 1 persistent cooperative kernel (grid barrier per level),
                                  2 one launch per level with a host read-back,
-                                 3 HIP graph of `graph_levels` level launches replayed until done */
+                                 3 `graph_levels` level launches queued per host read-back,
+                                 4 the same launches captured once in a HIP graph and replayed */
   int32_t direction;          /* 1 push only, 2 pull only, 3 switch by alpha/beta */
   int32_t block;              /* threads per workgroup: 256, 512 or 1024 */
   int32_t blocks_per_cu;      /* persistent grid: workgroups per compute unit */
@@ -96,7 +97,7 @@ typedef struct dawn_params {
   int32_t pull_lane_edges;    /* pull: in-edges one lane scans before its wave helps */
   float alpha;                /* switch push -> pull when frontier edges > unvisited edges / alpha */
   float beta;                 /* switch pull -> push when frontier nodes < n / beta */
-  int32_t graph_levels;       /* driver 3: level launches per HIP graph replay */
+  int32_t graph_levels;       /* drivers 3, 4: level launches per host read-back (rounded up to even) */
   int32_t small_n;            /* graphs with n <= small_n run as one workgroup per source */
   float batch_alpha;          /* batched: push when frontier edges * alpha < unsaturated in-edges */
   int32_t batch_lanes;        /* batched: sources per launch (64..4096, multiple of 64) */

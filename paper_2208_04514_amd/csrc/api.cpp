@@ -102,7 +102,7 @@ dawn_params default_params(const GraphRec& g) {
 }
 
 dawn_status check_params(const dawn_params& p) {
-  if (p.driver < 1 || p.driver > 3) return fail(DAWN_E_INVALID_ARG, "driver must be 1, 2 or 3");
+  if (p.driver < 1 || p.driver > 4) return fail(DAWN_E_INVALID_ARG, "driver must be 1, 2, 3 or 4");
   if (p.direction < 1 || p.direction > 3) return fail(DAWN_E_INVALID_ARG, "direction must be 1..3");
   if (p.block != 256 && p.block != 512 && p.block != 1024)
     return fail(DAWN_E_INVALID_ARG, "block must be 256, 512 or 1024");

@@ -173,12 +173,26 @@ static dawn_status build_csc(Ctx* ctx, int n, long long m, const int32_t* rp, co
   return DAWN_OK;
 }
 
+__global__ void mark_no_in(const int32_t* ip, int n, u64* noin) {
+  const int nw = (n + 63) / 64;
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+    u64 bits = 0;
+    for (int b = 0; b < 64 && w * 64 + b < n; ++b) {
+      const int v = w * 64 + b;
+      if (ip[v + 1] == ip[v]) bits |= 1ull << b;
+    }
+    noin[w] = bits;
+  }
+}
+
 static void free_graph_buffers(GraphRec* g) {
   dev_free(g->ctx, g->rp, ((size_t)g->n + 1) * 4);
   dev_free(g->ctx, g->col, (size_t)std::max(g->m, 1LL) * 4);
   dev_free(g->ctx, g->ip, ((size_t)g->n + 1) * 4);
   dev_free(g->ctx, g->isrc, (size_t)std::max(g->m, 1LL) * 4);
+  dev_free(g->ctx, g->noin, (((size_t)g->n + 63) / 64) * 8);
   g->rp = g->col = g->ip = g->isrc = nullptr;
+  g->noin = nullptr;
 }
 
 GraphRec::~GraphRec() {
@@ -196,7 +210,17 @@ static dawn_status alloc_graph_buffers(Ctx* ctx, GraphRec* g) {
   DAWN_TRY(dev_alloc_n(ctx, &g->col, mm));
   DAWN_TRY(dev_alloc_n(ctx, &g->ip, n1));
   DAWN_TRY(dev_alloc_n(ctx, &g->isrc, mm));
-  g->bytes = 2 * (n1 + mm) * 4;
+  DAWN_TRY(dev_alloc_n(ctx, &g->noin, ((size_t)g->n + 63) / 64));
+  g->bytes = 2 * (n1 + mm) * 4 + (((size_t)g->n + 63) / 64) * 8;
+  return DAWN_OK;
+}
+
+static dawn_status finish_noin(Ctx* ctx, GraphRec* g, hipStream_t s) {
+  const int nw = (g->n + 63) / 64;
+  hipLaunchKernelGGL(mark_no_in, dim3(grid_for(ctx, nw, 256)), dim3(256), 0, s, g->ip, g->n, g->noin);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(DAWN_E_DEVICE, "graph metadata: %s", hipGetErrorString(e));
   return DAWN_OK;
 }
 
@@ -230,6 +254,7 @@ dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_
   dawn_status st = DAWN_OK;
   if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "upload: %s", hipGetErrorString(e));
   if (st == DAWN_OK) st = build_csc(ctx, n, m, g->rp, g->col, g->ip, g->isrc, s);
+  if (st == DAWN_OK) st = finish_noin(ctx, g, s);
   hipStreamDestroy(s);
   return st;
 }
@@ -413,6 +438,7 @@ dawn_status graph_wcc(Ctx* ctx, GraphRec* g, hipStream_t s) {
     if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "wcc: %s", hipGetErrorString(e));
   }
   if (st == DAWN_OK) st = build_csc(ctx, s_wcc, sm, sub->rp, sub->col, sub->ip, sub->isrc, s);
+  if (st == DAWN_OK) st = finish_noin(ctx, sub.get(), s);
   std::vector<int32_t> h_nodes(s_wcc);
   if (st == DAWN_OK && s_wcc > 0) {
     e = hipMemcpyAsync(h_nodes.data(), nodes, (size_t)s_wcc * 4, hipMemcpyDeviceToHost, s);

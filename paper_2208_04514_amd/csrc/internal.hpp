@@ -74,7 +74,7 @@ struct LevelSlot {
 struct LevelState {
   int level;                  // last level executed (0 = seeded)
   int cur;                    // which visited bitmap is current (0/1)
-  int pull;                   // direction of the next level
+  int pull;                   // direction of the last level executed
   int done;                   // 0 running, 1 finished, 2 watchdog
   long long mu;               // out-degree sum of the still-unvisited nodes
   int last_nonempty;          // last level that found a node
@@ -85,10 +85,16 @@ struct LevelState {
   u64 reached;
 };
 
+// st[p]: the state after the level run by the last launch of parity p (the
+// per-level kernels alternate parities, so a launch reads st[p ^ 1] and
+// writes st[p] without racing its own readers).
 struct SsspCtrl {
   GridBarrier bar;
+  int32_t* dist;              // output rows and source: written by the host (one copy)
+  int source;                 //   before the init kernel, so launches and captured
+  int pad;                    //   graphs do not depend on them
   LevelSlot slot[3];
-  LevelState st;
+  LevelState st[2];
 };
 
 // Everything a single-source traversal kernel needs (passed by value).
@@ -100,6 +106,7 @@ struct SsspArgs {
   const int32_t* col;         // CSR targets (m)
   const int32_t* ip;          // CSC column offsets (n+1)
   const int32_t* isrc;        // CSC sources (m)
+  const u64* noin;            // bit per node with no in-edge (never reached unless the source)
   u64* vis0;
   u64* vis1;
   int32_t* qs0;               // small-degree queues (level parity 0/1): kStripes
@@ -109,8 +116,7 @@ struct SsspArgs {
   int32_t* ck0;               // ... and the chunk's index within the node's row
   int32_t* ck1;
   SsspCtrl* ctrl;
-  int32_t* dist;
-  int32_t source;
+  int32_t* dist;              // filled in by each kernel from ctrl->dist
   int32_t mode;               // 1 push, 2 pull, 3 switch
   float alpha, beta;
   int32_t big_degree;
@@ -154,8 +160,9 @@ struct SsspWs {
   size_t chunk_cap = 0;
   size_t bytes = 0;
   SsspCtrl* h_ctrl = nullptr;   // pinned read-back
-  // HIP graph driver cache
+  // HIP graph driver cache: init + levels, and levels alone for long runs
   hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec_more = nullptr;
   int gexec_levels = 0;
   int gexec_block = 0;
   SsspArgs gexec_args{};        // launch arguments baked into the captured graph
@@ -174,6 +181,7 @@ struct GraphRec {
   int32_t* col = nullptr;
   int32_t* ip = nullptr;
   int32_t* isrc = nullptr;
+  u64* noin = nullptr;                    // nodes with no in-edge, one bit each
   int32_t max_out_deg = 0;
   int32_t zero_out = 0;
   size_t bytes = 0;

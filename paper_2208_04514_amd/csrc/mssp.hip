@@ -345,43 +345,82 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
 }
 
 // ------------------------------------------------------------------ emit --
-// Write the distance rows of the lanes in emask: for each tile of 64 nodes one
-// workgroup, one wave per word; a lane holds node v0+lane's visited word and
-// level planes, then each emitted lane's row gets 64 consecutive int32 (one
-// 256-byte store).  With `clear` the emitted lanes' bits are removed.
+// Write the distance rows of the lanes in emask.  One workgroup per tile of
+// 64 nodes; the tile's visited words and level planes are read a chunk of
+// kEmitWords words at a time (each node's chunk is one contiguous 128-byte
+// line), transposed into LDS, and then each wave takes a word: a lane holds
+// node v0+lane's visited bits and planes for that word in registers and
+// rebuilds every emitted source's level, writing 64 consecutive int32 of the
+// source's row (one 256-byte store) per source.  With `clear` the emitted
+// lanes' bits are removed from vis and the planes (serving reuses the lanes).
+constexpr int kEmitWords = 16;
+
+template <int DMAX>
 __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, const u64* emask,
                                                           int clear) {
+  __shared__ u64 sx[kEmitWords][65];
+  __shared__ u64 sp[DMAX][kEmitWords][65];
+  const int tid = threadIdx.x;
   const int lane = lane_id();
-  const int wv = threadIdx.x / kWave;
+  const int wv = tid / kWave;
   const int W = a.W;
   const int ntiles = (a.n + 63) / 64;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int v = t * 64 + lane;
-    const bool valid = v < a.n;
-    for (int w = wv; w < W; w += kBatchBlock / kWave) {
-      u64 em = emask[w];
-      if (!em) continue;
-      const size_t idx = (size_t)v * W + w;
-      const u64 x = valid ? a.vis[idx] : 0ull;
-      u64 pl[kMaxPlanes];
+    const int v0 = t * 64;
+    const int nv = min(64, a.n - v0);
+    for (int wc0 = 0; wc0 < W; wc0 += kEmitWords) {
+      const int wcn = min(kEmitWords, W - wc0);
+      bool any = false;
+      for (int i = 0; i < wcn; ++i) any |= emask[wc0 + i] != 0;
+      if (!any) continue;
+      __syncthreads();
+      for (int e = tid; e < 64 * wcn; e += kBatchBlock) {
+        const int j = e / wcn, wl = e % wcn;
+        u64 x = 0;
+        u64 pv[DMAX];
 #pragma unroll
-      for (int b = 0; b < kMaxPlanes; ++b) pl[b] = (b < D && valid) ? a.planes[b][idx] : 0ull;
-      if (clear && valid) {
-        a.vis[idx] = x & ~em;
-        for (int b = 0; b < D; ++b) a.planes[b][idx] = pl[b] & ~em;
-      }
-      while (em) {
-        const int b = __ffsll((unsigned long long)em) - 1;
-        em &= em - 1;
-        int32_t* row = a.rows[w * 64 + b];
-        if (!row) continue;
-        int val = -1;
-        if ((x >> b) & 1ull) {
-          val = 0;
+        for (int d = 0; d < DMAX; ++d) pv[d] = 0;
+        if (j < nv) {
+          const size_t idx = (size_t)(v0 + j) * W + wc0 + wl;
+          const u64 em = emask[wc0 + wl];
+          x = a.vis[idx];
 #pragma unroll
-          for (int d = 0; d < kMaxPlanes; ++d) val |= (int)((pl[d] >> b) & 1ull) << d;
+          for (int d = 0; d < DMAX; ++d)
+            if (d < D) pv[d] = a.planes[d][idx];
+          if (clear && em) {
+            a.vis[idx] = x & ~em;
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d)
+              if (d < D) a.planes[d][idx] = pv[d] & ~em;
+          }
         }
-        if (valid) row[v] = val;
+        sx[wl][j] = x;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) sp[d][wl][j] = pv[d];
+      }
+      __syncthreads();
+      for (int wl = wv; wl < wcn; wl += kBatchBlock / kWave) {
+        const int w = wc0 + wl;
+        u64 em = emask[w];
+        if (!em) continue;
+        const u64 x = sx[wl][lane];
+        u64 pl[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) pl[d] = sp[d][wl][lane];
+        const int v = v0 + lane;
+        while (em) {
+          const int b = __ffsll((unsigned long long)em) - 1;
+          em &= em - 1;
+          int32_t* row = a.rows[w * 64 + b];
+          if (!row) continue;
+          int val = -1;
+          if ((x >> b) & 1ull) {
+            val = 0;
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) val |= (int)((pl[d] >> b) & 1ull) << d;
+          }
+          if (lane < nv) row[v] = val;
+        }
       }
     }
   }
@@ -615,8 +654,13 @@ dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, co
                               bool clear, hipStream_t s) {
   const int ntiles = (a.n + 63) / 64;
   const int grid = std::max(1, std::min(ntiles, ctx->num_cu * 8));
-  hipLaunchKernelGGL(batch_emit, dim3(grid), dim3(kBatchBlock), 0, s, a, nplanes_used, d_emask,
-                     clear ? 1 : 0);
+  const int D = nplanes_used;
+  if (D <= 4)
+    hipLaunchKernelGGL(batch_emit<4>, dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask, clear ? 1 : 0);
+  else if (D <= 8)
+    hipLaunchKernelGGL(batch_emit<8>, dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask, clear ? 1 : 0);
+  else
+    hipLaunchKernelGGL(batch_emit<16>, dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask, clear ? 1 : 0);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }

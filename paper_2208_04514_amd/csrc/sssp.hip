@@ -39,9 +39,12 @@
 // Drivers: (1) one persistent cooperative kernel with a software grid barrier
 // between levels, (2) one kernel per level with the counters read back by the
 // host, (3) a HIP graph of level kernels replayed until a device flag says done.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -213,33 +216,42 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
   }
 }
 
+// LDS the pull step needs per wave: a rank -> lane table and hit flags.
+struct PullScratch {
+  int rank_lane[kWave];
+  int hit[kWave];
+};
+
 template <int BLOCK>
 __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, Counters& c,
-                          WaveQueue& q) {
+                          WaveQueue& q, PullScratch* ps) {
   const int lane = lane_id();
   const int wpb = BLOCK / kWave;
   const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
   const unsigned nwaves = gridDim.x * wpb;
+  PullScratch& sc = ps[threadIdx.x / kWave];
+  sc.hit[lane] = 0;
   for (unsigned w = gw; w < (unsigned)a.nw; w += nwaves) {
     const u64 word = vin[w];
+    // nodes without in-edges can only be the source: treat them as settled
+    const u64 settled = word | a.noin[w];
     const int v = (int)(w * kWave) + lane;
     const int valid_n = min(kWave, a.n - (int)(w * kWave));
     const u64 full = valid_n >= kWave ? ~0ull : ((1ull << valid_n) - 1ull);
-    if ((word & full) == full) {
+    if ((settled & full) == full) {
       if (lane == 0) vout[w] = word;
       continue;
     }
     bool found = false;
-    bool rest = false;
-    int s = 0, e = 0, lim = 0;
-    if (lane < valid_n && !((word >> lane) & 1ull)) {
-      s = a.ip[v];
+    int cur = 0, e = 0;
+    const bool unvisited = lane < valid_n && !((settled >> lane) & 1ull);
+    if (unvisited) {
+      cur = a.ip[v];
       e = a.ip[v + 1];
-      lim = min(e, s + a.lane_edges);
-      int j = s;
-      // four in-neighbours per step keep four independent loads in flight
-      for (; j + 4 <= lim; j += 4) {
-        const int u0 = a.isrc[j], u1 = a.isrc[j + 1], u2 = a.isrc[j + 2], u3 = a.isrc[j + 3];
+      // the lane's own first in-edges, four loads in flight per step
+      const int lim = min(e, cur + a.lane_edges);
+      for (; cur + 4 <= lim; cur += 4) {
+        const int u0 = a.isrc[cur], u1 = a.isrc[cur + 1], u2 = a.isrc[cur + 2], u3 = a.isrc[cur + 3];
         const u64 b0 = vin[u0 >> 6] >> (u0 & 63), b1 = vin[u1 >> 6] >> (u1 & 63);
         const u64 b2 = vin[u2 >> 6] >> (u2 & 63), b3 = vin[u3 >> 6] >> (u3 & 63);
         c.edges += 4;
@@ -248,33 +260,42 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
           break;
         }
       }
-      for (; !found && j < lim; ++j) {
-        const int u = a.isrc[j];
+      for (; !found && cur < lim; ++cur) {
+        const int u = a.isrc[cur];
         c.edges += 1;
         if ((vin[u >> 6] >> (u & 63)) & 1ull) found = true;
       }
-      rest = !found && lim < e;
     }
-    // the wave finishes long in-lists together, 64 entries a step
-    u64 pending = __ballot(rest);
-    while (pending) {
-      const int j = __ffsll((unsigned long long)pending) - 1;
-      pending &= pending - 1;
-      const int b0 = __shfl(lim, j, kWave);
-      const int b1 = __shfl(e, j, kWave);
-      for (int b = b0; b < b1; b += kWave) {
-        const int idx = b + lane;
-        bool hit = false;
-        if (idx < b1) {
-          const int u = a.isrc[idx];
-          c.edges += 1;
-          hit = (vin[u >> 6] >> (u & 63)) & 1ull;
-        }
-        if (__ballot(hit)) {
-          if (lane == j) found = true;
-          break;
-        }
+    // lanes still searching share the wave: each round hands the 64 lanes out
+    // round-robin over the searching nodes, so every round checks 64 in-edges
+    // and a node leaves as soon as one of its edges hits
+    bool searching = unvisited && !found && cur < e;
+    u64 um = __ballot(searching);
+    while (um) {
+      const int cnt = __popcll(um);
+      const int rank = __popcll(um & lanes_below());
+      if (searching) sc.rank_lane[rank] = lane;
+      __builtin_amdgcn_wave_barrier();
+      const int owner = sc.rank_lane[lane % cnt];
+      const int off = lane / cnt;
+      const int oc = __shfl(cur, owner, kWave);
+      const int oe = __shfl(e, owner, kWave);
+      const int idx = oc + off;
+      if (idx < oe) {
+        const int u = a.isrc[idx];
+        c.edges += 1;
+        if ((vin[u >> 6] >> (u & 63)) & 1ull) sc.hit[owner] = 1;
       }
+      __builtin_amdgcn_wave_barrier();
+      if (searching) {
+        if (sc.hit[lane]) found = true;
+        cur += (kWave - rank + cnt - 1) / cnt;
+        searching = !found && cur < e;
+      }
+      __builtin_amdgcn_wave_barrier();
+      sc.hit[lane] = 0;
+      __builtin_amdgcn_wave_barrier();
+      um = __ballot(searching);
     }
     const u64 newbits = __ballot(found);
     if (lane == 0) vout[w] = word | newbits;
@@ -365,9 +386,7 @@ __device__ void decide(const SsspArgs& a, LevelState& st, const SlotSum& sl, boo
 // Seed the source (one thread; slots 1 and 2 are zeroed by the caller).
 template <int BLOCK>
 __device__ void seed(const SsspArgs& a) {
-  const int s = a.source;
-  a.dist[s] = 0;
-  a.vis0[s >> 6] |= 1ull << (s & 63);
+  const int s = a.ctrl->source;
   const int deg = a.rp[s + 1] - a.rp[s];
   LevelSlot* sl = &a.ctrl->slot[0];
   sl->nf[0] = 1;
@@ -383,7 +402,7 @@ __device__ void seed(const SsspArgs& a) {
     }
     sl->big_chunks = nch;
   }
-  LevelState& st = a.ctrl->st;
+  LevelState& st = a.ctrl->st[1];
   st.level = 0;
   st.cur = 0;
   st.pull = 0;
@@ -399,20 +418,26 @@ __device__ void seed(const SsspArgs& a) {
   if (a.lrec > 0) a.level_dir[0] = 0;
 }
 
+// dist = -1 except dist[s] = 0, visited = {s}, all counter slots zero.
 __device__ __forceinline__ void init_fill(const SsspArgs& a) {
+  const int s = a.ctrl->source;
   const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned nt = gridDim.x * blockDim.x;
-  for (unsigned i = tid; i < (unsigned)a.n; i += nt) a.dist[i] = -1;
-  for (unsigned w = tid; w < (unsigned)a.nw; w += nt) a.vis0[w] = 0;
+  for (unsigned i = tid; i < (unsigned)a.n; i += nt) a.dist[i] = (int)i == s ? 0 : -1;
+  for (unsigned w = tid; w < (unsigned)a.nw; w += nt)
+    a.vis0[w] = (int)w == (s >> 6) ? (1ull << (s & 63)) : 0ull;
   if (blockIdx.x == 0)
     for (int i = 0; i < 3; ++i) zero_slot(&a.ctrl->slot[i], threadIdx.x, blockDim.x);
 }
 
 // ------------------------------------------------------- persistent driver --
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a) {
+__global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
+  SsspArgs a = a0;
+  a.dist = a0.ctrl->dist;
   __shared__ int32_t qbuf[BLOCK / kWave][kWaveBuf];
   __shared__ unsigned pre[kStripes + 1];
+  __shared__ PullScratch ps[BLOCK / kWave];
   WaveQueue q{qbuf[threadIdx.x / kWave], 0};
   init_fill(a);
   if (!grid_sync(&a.ctrl->bar)) return;
@@ -433,7 +458,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a) {
     u64* vcur = st.cur ? a.vis1 : a.vis0;
     if (st.pull) {
       u64* vnext = st.cur ? a.vis0 : a.vis1;
-      pull_step<BLOCK>(a, L, vcur, vnext, c, q);
+      pull_step<BLOCK>(a, L, vcur, vnext, c, q, ps);
       st.cur ^= 1;
     } else {
       push_step<BLOCK>(a, L, vcur, c, q, pre);
@@ -442,70 +467,85 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a) {
     if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
     if (!grid_sync(&a.ctrl->bar)) return;
   }
-  if (leader) a.ctrl->st = st;
+  if (leader) a.ctrl->st[1] = st;
 }
 
 // ------------------------------------------------------ per-level drivers --
+// Initial state of one traversal (the source is read from the control block).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_init_fill(SsspArgs a) { init_fill(a); }
-
-template <int BLOCK>
-__global__ void sssp_seed(SsspArgs a) {
-  if (threadIdx.x == 0) {
-    seed<BLOCK>(a);
-    // choose level 1 from the seed's counters
-    LevelState st = a.ctrl->st;
-    SlotSum s0{1, (u64)(a.rp[a.source + 1] - a.rp[a.source]), 0};
-    decide(a, st, s0, true);
-    a.ctrl->st = st;
+__global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0) {
+  SsspArgs a = a0;
+  a.dist = a0.ctrl->dist;
+  init_fill(a);
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) seed<BLOCK>(a);
   }
 }
 
-// One level; the state was chosen by the decide kernel launched after the
-// previous level (kernel boundaries order the two, no fences needed).
+// One level per launch.  Launch i has parity p = i & 1: it reads the state
+// left by the previous launch (st[p ^ 1]) and the counters of that level, and
+// every workgroup takes the same decision for the next level (no separate
+// decide launch, no fences: the kernel boundary orders the two launches).
+// Workgroup 0 stores the new state in st[p].  Once the loop is done, later
+// launches only carry the final state forward.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a) {
+__global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
+  SsspArgs a = a0;
+  a.dist = a0.ctrl->dist;
   __shared__ int32_t qbuf[BLOCK / kWave][kWaveBuf];
   __shared__ unsigned pre[kStripes + 1];
+  __shared__ PullScratch ps[BLOCK / kWave];
+  __shared__ LevelState sst;
+  __shared__ int idle;
+  if (threadIdx.x == 0) {
+    LevelState st = a.ctrl->st[parity ^ 1];
+    if (!st.done) {
+      const LevelSlot* sl = &a.ctrl->slot[st.level % 3];
+      SlotSum sum{0, 0, 0};
+      unsigned nsmall = 0;
+      for (int i = 0; i < kStripes; ++i) {
+        sum.nf += sl->nf[i];
+        sum.mf += sl->mf[i];
+        sum.edges += sl->edges[i];
+        nsmall += sl->small_count[i];
+      }
+      decide(a, st, sum, blockIdx.x == 0);
+      // a push level with nothing for this workgroup lets it leave at once
+      const unsigned first_small = blockIdx.x * (BLOCK / kWave) * kWave;
+      idle = !st.done && !st.pull && first_small >= nsmall && blockIdx.x >= sl->big_chunks;
+    } else {
+      idle = 1;
+    }
+    sst = st;
+  }
+  __syncthreads();
+  const LevelState st = sst;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    LevelState out = st;
+    if (!st.done && st.pull) out.cur ^= 1;
+    a.ctrl->st[parity] = out;
+  }
+  if (st.done) return;
+  const int L = st.level;
+  if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
+  if (idle) return;
   WaveQueue q{qbuf[threadIdx.x / kWave], 0};
-  const LevelState st0 = a.ctrl->st;
-  if (st0.done) return;
-  const int L = st0.level;
   Counters c{0, 0, 0};
-  u64* vcur = st0.cur ? a.vis1 : a.vis0;
-  if (st0.pull) {
-    u64* vnext = st0.cur ? a.vis0 : a.vis1;
-    pull_step<BLOCK>(a, L, vcur, vnext, c, q);
+  u64* vcur = st.cur ? a.vis1 : a.vis0;
+  if (st.pull) {
+    u64* vnext = st.cur ? a.vis0 : a.vis1;
+    pull_step<BLOCK>(a, L, vcur, vnext, c, q, ps);
   } else {
     push_step<BLOCK>(a, L, vcur, c, q, pre);
   }
   finish_level<BLOCK>(a, L, c, q);
 }
 
-// Fold the level just run into the state and choose the next one.
-__global__ void sssp_decide(SsspArgs a) {
-  __shared__ SlotSum sum;
-  __shared__ int go;
-  const LevelState st0 = a.ctrl->st;
-  if (threadIdx.x == 0) {
-    go = !st0.done;
-    if (go) sum = sum_slot(&a.ctrl->slot[st0.level % 3]);
-  }
-  __syncthreads();
-  if (!go) return;
-  const int L = st0.level;
-  zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, blockDim.x);
-  if (threadIdx.x == 0) {
-    LevelState st = st0;
-    if (st.pull) st.cur ^= 1;
-    decide(a, st, sum, true);
-    a.ctrl->st = st;
-  }
-}
-
 // ------------------------------------------------------------------ host --
 SsspWs::~SsspWs() {
   if (gexec) hipGraphExecDestroy(gexec);
+  if (gexec_more) hipGraphExecDestroy(gexec_more);
   for (int i = 0; i < 2; ++i) {
     dev_free(ctx, vis[i], 0);
     dev_free(ctx, qs[i], 0);
@@ -573,6 +613,7 @@ static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
   a.col = g->col;
   a.ip = g->ip;
   a.isrc = g->isrc;
+  a.noin = g->noin;
   a.vis0 = w->vis[0];
   a.vis1 = w->vis[1];
   a.qs0 = w->qs[0];
@@ -582,8 +623,9 @@ static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
   a.ck0 = w->ck[0];
   a.ck1 = w->ck[1];
   a.ctrl = w->ctrl;
-  a.dist = dist;
-  a.source = source;
+  a.dist = nullptr;
+  (void)source;
+  (void)dist;
   a.mode = p.direction;
   a.alpha = p.alpha;
   a.beta = p.beta;
@@ -609,26 +651,41 @@ static dawn_status launch_persistent(Ctx* ctx, SsspWs* w, const SsspArgs& a, int
   return DAWN_OK;
 }
 
+static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStream_t)>& body) {
+  hipStream_t cs = nullptr;
+  DAWN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    body(cs);
+    e = hipStreamEndCapture(cs, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail(DAWN_E_DEVICE, "HIP graph build: %s", hipGetErrorString(e));
+  return DAWN_OK;
+}
+
 template <int BLOCK>
 static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, int driver,
-                              int graph_levels, int* launches, double* level_ms) {
+                              int graph_levels, int* launches, double* level_ms, int* final_parity) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
-  hipLaunchKernelGGL(sssp_init_fill<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
-  hipLaunchKernelGGL(sssp_seed<BLOCK>, dim3(1), dim3(64), 0, w->stream, a);
-  DAWN_HIP(hipGetLastError());
-  *launches = 2;
   const long long max_launch = (long long)a.n + 2;
   if (driver == 2) {
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+    DAWN_HIP(hipGetLastError());
+    *launches = 1;
     int level_launches = 0;
     for (long long it = 0; it <= max_launch; ++it) {
+      const int parity = (int)(it & 1);
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
-      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a);
+      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a, parity);
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
-      hipLaunchKernelGGL(sssp_decide, dim3(1), dim3(64), 0, w->stream, a);
       DAWN_HIP(hipGetLastError());
-      *launches += 2;
+      *launches += 1;
       ++level_launches;
-      DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st, &w->ctrl->st, sizeof(LevelState),
+      DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[parity], &w->ctrl->st[parity], sizeof(LevelState),
                               hipMemcpyDeviceToHost, w->stream));
       DAWN_HIP(hipStreamSynchronize(w->stream));
       if (level_ms) {
@@ -636,70 +693,87 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
         DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
         *level_ms += ms;
       }
-      if (w->h_ctrl->st.done) {
+      if (w->h_ctrl->st[parity].done) {
+        *final_parity = parity;
         if (level_ms) *launches = level_launches;
         return DAWN_OK;
       }
     }
     return fail(DAWN_E_DEVICE, "level loop did not terminate");
   }
-  // driver 3: HIP graph of `graph_levels` level launches, replayed until done
-  // level launches bake their arguments in: recapture when any of them changed
-  SsspArgs key = a;
-  key.source = 0;
+  graph_levels += graph_levels & 1;
+  if (driver == 3) {
+    // K level launches queued per host check of the final state
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+    *launches = 1;
+    for (long long it = 0; it * graph_levels <= max_launch; ++it) {
+      for (int i = 0; i < graph_levels; ++i)
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a, i & 1);
+      DAWN_HIP(hipGetLastError());
+      *launches += graph_levels;
+      DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[1], &w->ctrl->st[1], sizeof(LevelState),
+                              hipMemcpyDeviceToHost, w->stream));
+      DAWN_HIP(hipStreamSynchronize(w->stream));
+      if (w->h_ctrl->st[1].done) {
+        *final_parity = 1;
+        return DAWN_OK;
+      }
+    }
+    return fail(DAWN_E_DEVICE, "level loop did not terminate");
+  }
+  // driver 4: one HIP graph holds the init kernel and an even number of level
+  // launches (parities 0, 1, 0, 1, ...); a second graph of level launches
+  // alone continues a traversal that needs more levels
   if (w->gexec && (w->gexec_levels != graph_levels || w->gexec_block != BLOCK ||
-                   memcmp(&w->gexec_args, &key, sizeof(SsspArgs)) != 0)) {
+                   memcmp(&w->gexec_args, &a, sizeof(SsspArgs)) != 0)) {
     hipGraphExecDestroy(w->gexec);
     w->gexec = nullptr;
+    if (w->gexec_more) hipGraphExecDestroy(w->gexec_more);
+    w->gexec_more = nullptr;
   }
   if (!w->gexec) {
-    if (w->gexec) {
-      hipGraphExecDestroy(w->gexec);
-      w->gexec = nullptr;
-    }
-    hipStream_t cs = nullptr;
-    DAWN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      for (int i = 0; i < graph_levels; ++i) {
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a);
-        hipLaunchKernelGGL(sssp_decide, dim3(1), dim3(64), 0, cs, a);
-      }
-      e = hipStreamEndCapture(cs, &graph);
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&w->gexec, graph, nullptr, nullptr, 0);
-    if (graph) hipGraphDestroy(graph);
-    hipStreamDestroy(cs);
-    if (e != hipSuccess) return fail(DAWN_E_DEVICE, "HIP graph build: %s", hipGetErrorString(e));
+    DAWN_TRY(capture(&w->gexec, [&](hipStream_t cs) {
+      hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, cs, a);
+      for (int i = 0; i < graph_levels; ++i)
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a, i & 1);
+    }));
+    DAWN_TRY(capture(&w->gexec_more, [&](hipStream_t cs) {
+      for (int i = 0; i < graph_levels; ++i)
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a, i & 1);
+    }));
     w->gexec_levels = graph_levels;
     w->gexec_block = BLOCK;
-    w->gexec_args = key;
+    w->gexec_args = a;
   }
+  *launches = 0;
   for (long long it = 0; it * graph_levels <= max_launch; ++it) {
-    DAWN_HIP(hipGraphLaunch(w->gexec, w->stream));
-    *launches += 2 * graph_levels;
-    DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st, &w->ctrl->st, sizeof(LevelState),
+    DAWN_HIP(hipGraphLaunch(it == 0 ? w->gexec : w->gexec_more, w->stream));
+    *launches += graph_levels + (it == 0 ? 1 : 0);
+    DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[1], &w->ctrl->st[1], sizeof(LevelState),
                             hipMemcpyDeviceToHost, w->stream));
     DAWN_HIP(hipStreamSynchronize(w->stream));
-    if (w->h_ctrl->st.done) return DAWN_OK;
+    if (w->h_ctrl->st[1].done) {
+      *final_parity = 1;
+      return DAWN_OK;
+    }
   }
   return fail(DAWN_E_DEVICE, "level loop did not terminate");
 }
 
 template <int BLOCK>
 static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_params& p,
-                                 SsspArgs& a, int* launches, double* level_ms) {
+                                 SsspArgs& a, int* launches, double* level_ms, int* final_parity) {
   const bool single = g->n <= p.small_n;
   if (p.driver == 1 || single) {
     *launches = 1;
+    *final_parity = 1;
     return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, single);
   }
   int occ = 0;
   DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, 0));
   int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
   return run_levels<BLOCK>(ctx, w, a, per_cu * ctx->num_cu, p.driver, std::max(p.graph_levels, 1),
-                           launches, level_ms);
+                           launches, level_ms, final_parity);
 }
 
 dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source, int32_t* dist,
@@ -732,12 +806,18 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   const bool level_timing = p.timing == 1 && p.driver == 2 && g->n > p.small_n;
   double level_ms = 0.0;
   double* lm = level_timing ? &level_ms : nullptr;
+  int fp = 1;
+  const uint64_t t_setup = now_ns();
+  w->h_ctrl->dist = d_dist;
+  w->h_ctrl->source = source;
+  DAWN_HIP(hipMemcpyAsync(&w->ctrl->dist, &w->h_ctrl->dist, sizeof(int32_t*) + sizeof(int),
+                          hipMemcpyHostToDevice, w->stream));
   DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
-    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, &launches, lm); break;
-    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, &launches, lm); break;
-    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, &launches, lm); break;
+    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, &launches, lm, &fp); break;
+    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, &launches, lm, &fp); break;
+    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, &launches, lm, &fp); break;
   }
   if (!level_timing) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
@@ -745,21 +825,26 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     w->poisoned = true;
     return st;
   }
-  DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(SsspCtrl), hipMemcpyDeviceToHost,
-                          w->stream));
+  const uint64_t t_loop = now_ns();
+  // the per-level and graph drivers already read the final state back; the
+  // persistent driver's state (and its barrier's abort flag) is read here
+  const bool persistent = p.driver == 1 || g->n <= p.small_n;
   const int32_t cap = (stats && stats->frontier_cap > 0) ? std::min(stats->frontier_cap, w->lrec) : 0;
   std::vector<int32_t> lnf;
   std::vector<uint8_t> ldir;
+  if (persistent)
+    DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(SsspCtrl), hipMemcpyDeviceToHost,
+                            w->stream));
   if (cap > 0) {
     lnf.resize(cap);
     ldir.resize(cap);
     DAWN_HIP(hipMemcpyAsync(lnf.data(), w->level_nf, cap * 4, hipMemcpyDeviceToHost, w->stream));
     DAWN_HIP(hipMemcpyAsync(ldir.data(), w->level_dir, cap, hipMemcpyDeviceToHost, w->stream));
   }
-  DAWN_HIP(hipStreamSynchronize(w->stream));
-  const LevelState& rs = w->h_ctrl->st;
+  if (persistent || cap > 0) DAWN_HIP(hipStreamSynchronize(w->stream));
+  const LevelState& rs = w->h_ctrl->st[fp];
   if (rs.done != 1) w->poisoned = true;
-  if (w->h_ctrl->bar.abort) return fail(DAWN_E_DEVICE, "grid barrier timed out");
+  if (persistent && w->h_ctrl->bar.abort) return fail(DAWN_E_DEVICE, "grid barrier timed out");
   if (rs.done == 2) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
   if (rs.done != 1) return fail(DAWN_E_DEVICE, "level loop ended without finishing");
   if (!device_out) {
@@ -768,10 +853,12 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   }
   if (stats) {
     float ms = 0.f;
-    if (level_timing)
+    if (level_timing) {
       ms = (float)level_ms;
-    else
+    } else {
+      DAWN_HIP(hipEventSynchronize(w->ev1));
       DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    }
     stats->levels = rs.last_nonempty + 1;
     stats->push_levels = rs.push_levels;
     stats->pull_levels = rs.pull_levels;
@@ -786,6 +873,12 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     if (cap > 0 && stats->directions)
       for (int i = 0; i < nl; ++i) stats->directions[i] = ldir[i];
     stats->total_ms = (now_ns() - t0) / 1e6;
+  }
+  static const bool host_timing = getenv("DAWN_HOST_TIMING") != nullptr;
+  if (host_timing) {
+    const uint64_t t_end = now_ns();
+    fprintf(stderr, "[dawn_sssp] setup %.1f us, launch+loop %.1f us, tail %.1f us\n",
+            (t_setup - t0) / 1e3, (t_loop - t_setup) / 1e3, (t_end - t_loop) / 1e3);
   }
   return DAWN_OK;
 }

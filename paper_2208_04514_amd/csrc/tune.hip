@@ -153,8 +153,8 @@ dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, u
       return search({v});
     };
     if (st == DAWN_OK)
-      st = one(variants([](dawn_params& p, double v) { p.driver = (int)v; }, {2, 3}));
-    if (st == DAWN_OK && cur.driver == 3)
+      st = one(variants([](dawn_params& p, double v) { p.driver = (int)v; }, {2, 3, 4}));
+    if (st == DAWN_OK && cur.driver >= 3)
       st = one(variants([](dawn_params& p, double v) { p.graph_levels = (int)v; }, {4, 8, 16, 32}));
     if (st == DAWN_OK)
       st = one(variants([](dawn_params& p, double v) { p.big_degree = (int)v; },

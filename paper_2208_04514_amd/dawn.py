@@ -247,9 +247,9 @@ def dawn_sssp(ctx, graph: int, source: int, out=None, n: int | None = None,
     n = out.numel() if _is_torch_cuda(out) else out.size
     ptr, flags, _keep = _out_ptr(out, n)
     st = RunStats()
-    fs = np.zeros(max(frontier_cap, 1), np.int32)
-    dr = np.zeros(max(frontier_cap, 1), np.uint8)
     if frontier_cap > 0:
+        fs = np.zeros(frontier_cap, np.int32)
+        dr = np.zeros(frontier_cap, np.uint8)
         st.frontier_sizes = fs.ctypes.data_as(_i32p)
         st.directions = dr.ctypes.data_as(_u8p)
         st.frontier_cap = frontier_cap

@@ -48,6 +48,7 @@ VARIANTS = [
     dict(driver=1, direction=3), dict(driver=1, direction=1), dict(driver=1, direction=2),
     dict(driver=2, direction=3), dict(driver=2, direction=1), dict(driver=2, direction=2),
     dict(driver=3, direction=3, graph_levels=4), dict(driver=3, direction=1, graph_levels=16),
+    dict(driver=4, direction=3, graph_levels=6), dict(driver=4, direction=2, graph_levels=2),
     dict(driver=1, direction=3, block=512), dict(driver=1, direction=3, block=1024),
     dict(driver=1, direction=1, big_degree=64), dict(driver=2, direction=1, big_degree=64, block=1024),
     dict(driver=1, direction=2, pull_lane_edges=1), dict(driver=1, direction=3, alpha=1e6, beta=1e-3),
@@ -149,7 +150,7 @@ def test_edge_cases(ctx):
     g = gg.gen_edges(n, [(i, i + 1) for i in range(n - 1)])
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     try:
-        for driver in (1, 2, 3):
+        for driver in (1, 2, 3, 4):
             D.dawn_set_params(ctx, h, driver=driver, graph_levels=64)
             got, st = D.dawn_sssp(ctx, h, 5, frontier_cap=8)
             _check_row(g, 5, got, st)
@@ -222,7 +223,7 @@ def test_full_size(ctx, upload, name, count):
         _say(f"  source {s}: levels {st['levels']} push {st['push_levels']} "
              f"pull {st['pull_levels']} kernel {st['kernel_ms']:.3f} ms")
     # the other drivers on one source
-    for driver in (2, 3):
+    for driver in (2, 3, 4):
         D.dawn_set_params(ctx, h, driver=driver, graph_levels=32)
         got, st = D.dawn_sssp(ctx, h, int(src[0]))
         _check_row(g, src[0], got)
