@@ -38,12 +38,17 @@ struct BatchArgs {
   const int32_t* col;
   const int32_t* ip;
   const int32_t* isrc;
+  const int32_t* pcv;           // chunks of long in-lists: node
+  const int32_t* pck;           //                          chunk index
+  int32_t npc;
   u64* vis;                     // [n][W]
   u64* nxt[2];                  // [n][W] new bits per level parity
   u64* planes[kMaxPlanes];      // [n][W] bit b of each source's relative level
   int32_t nplanes;              // planes allocated (levels < 2^nplanes)
   u64* touched[2];              // one bit per node with new bits at a level of that
                                 //   parity: the frontier of the next level
+  u64* fmap[2];                 // [n] bit w set iff word w of the node's nxt row of
+                                //   that parity is nonzero (W <= 64)
   int32_t* cu[2];               // out-edge chunks of big-degree frontier nodes: node
   int32_t* ck[2];               //                                             chunk index
   BatchCtrl* ctrl;
@@ -68,6 +73,7 @@ struct BatchWs {
   int planes_dirty = 0;         // planes that may hold bits from an earlier batch
   size_t plane_reserve = 0;     // budget set aside for planes not yet allocated
   u64* touched[2] = {nullptr, nullptr};
+  u64* fmap[2] = {nullptr, nullptr};
   int32_t* cu[2] = {nullptr, nullptr};
   int32_t* ck[2] = {nullptr, nullptr};
   BatchCtrl* ctrl = nullptr;

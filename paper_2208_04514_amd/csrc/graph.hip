@@ -185,12 +185,29 @@ __global__ void mark_no_in(const int32_t* ip, int n, u64* noin) {
   }
 }
 
+__global__ void list_pull_chunks(const int32_t* ip, int n, unsigned* count, int32_t* pcv,
+                                 int32_t* pck) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int d = ip[v + 1] - ip[v];
+    if (d < kPullBig) continue;
+    const unsigned nch = (unsigned)((d + kPullChunk - 1) / kPullChunk);
+    const unsigned b = atomicAdd(count, nch);
+    for (unsigned k = 0; k < nch; ++k) {
+      pcv[b + k] = v;
+      pck[b + k] = (int32_t)k;
+    }
+  }
+}
+
 static void free_graph_buffers(GraphRec* g) {
   dev_free(g->ctx, g->rp, ((size_t)g->n + 1) * 4);
   dev_free(g->ctx, g->col, (size_t)std::max(g->m, 1LL) * 4);
   dev_free(g->ctx, g->ip, ((size_t)g->n + 1) * 4);
   dev_free(g->ctx, g->isrc, (size_t)std::max(g->m, 1LL) * 4);
   dev_free(g->ctx, g->noin, (((size_t)g->n + 63) / 64) * 8);
+  dev_free(g->ctx, g->pcv, g->pc_cap * 4);
+  dev_free(g->ctx, g->pck, g->pc_cap * 4);
+  g->pcv = g->pck = nullptr;
   g->rp = g->col = g->ip = g->isrc = nullptr;
   g->noin = nullptr;
 }
@@ -211,16 +228,35 @@ static dawn_status alloc_graph_buffers(Ctx* ctx, GraphRec* g) {
   DAWN_TRY(dev_alloc_n(ctx, &g->ip, n1));
   DAWN_TRY(dev_alloc_n(ctx, &g->isrc, mm));
   DAWN_TRY(dev_alloc_n(ctx, &g->noin, ((size_t)g->n + 63) / 64));
-  g->bytes = 2 * (n1 + mm) * 4 + (((size_t)g->n + 63) / 64) * 8;
+  // chunks: sum over in-lists of d >= kPullBig entries of ceil(d / kPullChunk)
+  g->pc_cap = (size_t)(g->m / kPullChunk) + (size_t)(g->m / kPullBig) + 1;
+  DAWN_TRY(dev_alloc_n(ctx, &g->pcv, g->pc_cap));
+  DAWN_TRY(dev_alloc_n(ctx, &g->pck, g->pc_cap));
+  g->bytes = 2 * (n1 + mm) * 4 + (((size_t)g->n + 63) / 64) * 8 + g->pc_cap * 8;
   return DAWN_OK;
 }
 
+// Per-graph metadata built from the CSC: the no-in-edge bitmap and the
+// chunk list of long in-lists.
 static dawn_status finish_noin(Ctx* ctx, GraphRec* g, hipStream_t s) {
   const int nw = (g->n + 63) / 64;
+  unsigned* count = nullptr;
+  DAWN_TRY(dev_alloc_n(ctx, &count, 1));
   hipLaunchKernelGGL(mark_no_in, dim3(grid_for(ctx, nw, 256)), dim3(256), 0, s, g->ip, g->n, g->noin);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(count, 0, sizeof(unsigned), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(list_pull_chunks, dim3(grid_for(ctx, g->n, 256)), dim3(256), 0, s, g->ip,
+                       g->n, count, g->pcv, g->pck);
+    e = hipGetLastError();
+  }
+  unsigned npc = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&npc, count, sizeof(unsigned), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(ctx, count, sizeof(unsigned));
   if (e != hipSuccess) return fail(DAWN_E_DEVICE, "graph metadata: %s", hipGetErrorString(e));
+  if (npc > g->pc_cap) return fail(DAWN_E_DEVICE, "pull chunk list overflow");
+  g->npc = (int32_t)npc;
   return DAWN_OK;
 }
 

@@ -60,6 +60,9 @@ struct GridBarrier {
 // takes more than a few hundred atomics per level; readers sum the stripes.
 constexpr int kStripes = 16;
 
+constexpr int kPullBig = 512;     // in-degree from which a batched pull splits the in-list
+constexpr int kPullChunk = 256;   // in-edges per chunk of a split in-list
+
 // Counters produced by one level step (ring of three, indexed level % 3).
 struct LevelSlot {
   unsigned int nf[kStripes];            // nodes found at this level
@@ -182,6 +185,12 @@ struct GraphRec {
   int32_t* ip = nullptr;
   int32_t* isrc = nullptr;
   u64* noin = nullptr;                    // nodes with no in-edge, one bit each
+  // in-lists of at least kPullBig entries cut into chunks of kPullChunk, so
+  // that a batched pull scans one long in-list with many waves: node, chunk
+  int32_t* pcv = nullptr;
+  int32_t* pck = nullptr;
+  int32_t npc = 0;
+  size_t pc_cap = 0;
   int32_t max_out_deg = 0;
   int32_t zero_out = 0;
   size_t bytes = 0;

@@ -45,7 +45,18 @@ constexpr int kChunkB = 64;       // out-edges per chunk of a big-degree node
 template <int P>
 __device__ __forceinline__ u64 group_mask(int lane) {
   if (P == 64) return ~0ull;
-  return ((1ull << P) - 1ull) << (lane & ~(P - 1));
+  return ((1ull << (P & 63)) - 1ull) << (lane & ~(P - 1));
+}
+
+// the low P bits
+template <int P>
+__device__ __forceinline__ u64 low_mask() {
+  return P == 64 ? ~0ull : (1ull << (P & 63)) - 1ull;
+}
+
+__device__ __forceinline__ u64 shfl64(u64 x, int src) {
+  unsigned lo = __shfl((unsigned)x, src, kWave), hi = __shfl((unsigned)(x >> 32), src, kWave);
+  return ((u64)hi << 32) | lo;
 }
 
 __device__ __forceinline__ u64 shfl_xor64(u64 x, int m) {
@@ -64,6 +75,73 @@ __device__ __forceinline__ void push_chunks(const BatchArgs& a, int L, int v, in
 }
 
 // ------------------------------------------------------------- expansion --
+// OR into acc the previous level's new bits of in-edges [s, e) that lie in
+// `need`, stopping once every lane of the group has all of its word's needed
+// bits (group-uniform call).  Returns the number of in-edges read.
+//
+// Per lane r, an unvisited v has an in-neighbour visited in r iff it has one
+// whose bit r is new at level L - 1, and the two give the same bits of
+// `need`: the scan reads the previous level's new rows, and only the words
+// that the frontier word map marks nonzero.
+template <int P>
+__device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, const u64* fm, int s,
+                                         int e, u64 need, int w, u64 gm, u64& acc) {
+  const size_t W = (size_t)a.W;
+  int j = s;
+  bool sat = false;
+  // eight (then four) in-neighbours per step keep independent loads in
+  // flight; a lane whose word is already covered issues no row loads
+  for (; j + 8 <= e; j += 8) {
+    int u[8];
+    u64 mk[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = a.isrc[j + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mk[q] = fm[u[q]];
+    if (acc != need) {
+      u64 r = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if ((mk[q] >> w) & 1ull) r |= front[(size_t)u[q] * W + w];
+      acc |= r & need;
+    }
+    if ((__ballot(acc != need) & gm) == 0) {
+      j += 8;
+      sat = true;
+      break;
+    }
+  }
+  for (; !sat && j + 4 <= e; j += 4) {
+    int u[4];
+    u64 mk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = a.isrc[j + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mk[q] = fm[u[q]];
+    if (acc != need) {
+      u64 r = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((mk[q] >> w) & 1ull) r |= front[(size_t)u[q] * W + w];
+      acc |= r & need;
+    }
+    if ((__ballot(acc != need) & gm) == 0) {
+      j += 4;
+      sat = true;
+      break;
+    }
+  }
+  for (; !sat && j < e; ++j) {
+    const int u = a.isrc[j];
+    if (acc != need && ((fm[u] >> w) & 1ull)) acc |= front[(size_t)u * W + w] & need;
+    if ((__ballot(acc != need) & gm) == 0) {
+      ++j;
+      break;
+    }
+  }
+  return j - s;
+}
+
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   const int lane = lane_id();
@@ -74,45 +152,53 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   const u64 gm = group_mask<P>(lane);
   const u64 actw = wok ? a.act[w] : 0ull;
   const size_t W = (size_t)a.W;
+  const u64* front = a.nxt[(L - 1) & 1];
+  const u64* fm = a.fmap[(L - 1) & 1];
   u64* nxt = a.nxt[L & 1];
   u64* T = a.touched[L & 1];
   u64 edges = 0;
   const unsigned gw = (blockIdx.x * kBatchBlock + threadIdx.x) / kWave;
   const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
+
+  // long in-lists: one chunk of kPullChunk in-edges per lane group, the
+  // chunks of a node OR their bits into its row
+  for (unsigned cb = gw * npw; cb < (unsigned)a.npc; cb += nwaves * npw) {
+    const unsigned c = cb + (unsigned)sub;
+    const bool has = c < (unsigned)a.npc;
+    int v = 0, s = 0, e = 0;
+    u64 need = 0;
+    if (has) {
+      v = a.pcv[c];
+      const int k = a.pck[c];
+      s = a.ip[v] + k * kPullChunk;
+      e = min(s + kPullChunk, a.ip[v + 1]);
+      if (wok) need = actw & ~a.vis[(size_t)v * W + w];
+    }
+    u64 acc = 0;
+    if ((__ballot(need != 0) & gm) != 0) {
+      const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gm, acc);
+      if (w == 0) edges += (u64)nr;
+    }
+    if (acc) atom_or(&nxt[(size_t)v * W + w], acc);
+    const bool any = (__ballot(acc != 0) & gm) != 0;
+    if (any && w == 0) atom_or(&T[v >> 6], 1ull << (v & 63));
+  }
+
   for (unsigned base = gw * npw; base < (unsigned)a.n; base += nwaves * npw) {
     const int v = (int)base + sub;
     const bool valid = v < a.n;
-    const u64 vw = (valid && wok) ? a.vis[(size_t)v * W + w] : ~0ull;
-    const u64 need = (valid && wok) ? (actw & ~vw) : 0ull;
-    const bool gneed = (__ballot(need != 0) & gm) != 0;
+    int s = 0, e = 0;
+    if (valid) {
+      s = a.ip[v];
+      e = a.ip[v + 1];
+    }
+    const bool mine = valid && e - s < kPullBig;     // long in-lists went by chunks
+    const u64 vw = (mine && wok) ? a.vis[(size_t)v * W + w] : ~0ull;
+    const u64 need = (mine && wok) ? (actw & ~vw) : 0ull;
     u64 acc = 0;
-    if (gneed) {
-      const int s = a.ip[v], e = a.ip[v + 1];
-      int j = s;
-      bool sat = false;
-      // four in-neighbours per step keep independent loads in flight; a lane
-      // whose word is already covered issues no further loads
-      for (; j + 4 <= e; j += 4) {
-        const int u0 = a.isrc[j], u1 = a.isrc[j + 1], u2 = a.isrc[j + 2], u3 = a.isrc[j + 3];
-        if (acc != need) {
-          acc |= (a.vis[(size_t)u0 * W + w] | a.vis[(size_t)u1 * W + w] |
-                  a.vis[(size_t)u2 * W + w] | a.vis[(size_t)u3 * W + w]) & need;
-        }
-        if ((__ballot(acc != need) & gm) == 0) {
-          j += 4;
-          sat = true;
-          break;
-        }
-      }
-      for (; !sat && j < e; ++j) {
-        const int u = a.isrc[j];
-        if (acc != need) acc |= a.vis[(size_t)u * W + w] & need;
-        if ((__ballot(acc != need) & gm) == 0) {
-          ++j;
-          break;
-        }
-      }
-      if (w == 0) edges += (u64)(j - s);
+    if ((__ballot(need != 0) & gm) != 0) {
+      const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gm, acc);
+      if (w == 0) edges += (u64)nr;
     }
     if (acc) nxt[(size_t)v * W + w] = acc;
     const bool any = (__ballot(acc != 0) & gm) != 0;
@@ -129,6 +215,8 @@ __device__ __forceinline__ void relax(const BatchArgs& a, u64* out, u64* T, int 
   u64 b = 0;
   if (f) {
     b = f & ~a.vis[(size_t)v * a.W + w];
+    // bits already staged for v this level need no atomic
+    if (b) b &= ~out[(size_t)v * a.W + w];
     if (b) atom_or(&out[(size_t)v * a.W + w], b);
   }
   const bool any = (__ballot(b != 0) & gm) != 0;
@@ -151,6 +239,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
   const int pl = (L - 1) & 1;
   const u64* F = a.touched[pl];
   const u64* front = a.nxt[pl];
+  const u64* fmp = a.fmap[pl];
   u64* out = a.nxt[L & 1];
   u64* T = a.touched[L & 1];
   u64 edges = 0;
@@ -173,10 +262,12 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
     }
     if (has && w == 0) edges += (u64)(e1 - e0);
     int e = e0;
-    for (; e + 2 <= e1; e += 2) {
-      const int v0 = a.col[e], v1 = a.col[e + 1];
+    for (; e + 4 <= e1; e += 4) {
+      const int v0 = a.col[e], v1 = a.col[e + 1], v2 = a.col[e + 2], v3 = a.col[e + 3];
       relax<P>(a, out, T, v0, f, w, gm);
       relax<P>(a, out, T, v1, f, w, gm);
+      relax<P>(a, out, T, v2, f, w, gm);
+      relax<P>(a, out, T, v3, f, w, gm);
     }
     for (; e < e1; ++e) relax<P>(a, out, T, a.col[e], f, w, gm);
   }
@@ -189,29 +280,40 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
     if (!fw) continue;
     const int u = (int)t * 64 + lane;
     int deg = 0, rs = 0;
+    u64 fmu = 0;
     if ((fw >> lane) & 1ull) {
       rs = a.rp[u];
       deg = a.rp[u + 1] - rs;
       if (deg >= kBigB) deg = 0;
+      fmu = fmp[u];
     }
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, kWave - 1, kWave);
     if (w == 0 && sub == 0) edges += (u64)total;
-    for (int eb = 0; eb < total; eb += npw) {
-      const int x = eb + sub;
-      const bool has = x < total;
-      const int j = wave_owner(incl, has ? x : total - 1);
-      const int inc_j = __shfl(incl, j, kWave);
-      const int deg_j = __shfl(deg, j, kWave);
-      const int rs_j = __shfl(rs, j, kWave);
-      const int uj = (int)t * 64 + j;
-      int v = 0;
-      u64 f = 0;
-      if (has) {
-        v = a.col[rs_j + (x - (inc_j - deg_j))];
-        if (wok) f = front[(size_t)uj * W + w];
+    // four edges per lane group and step keep independent loads in flight
+    for (int eb = 0; eb < total; eb += 4 * npw) {
+      int v[4];
+      u64 f[4];
+      u64 fmw[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int x = eb + q * npw + sub;
+        const bool has = x < total;
+        const int j = wave_owner(incl, has ? x : total - 1);
+        const int inc_j = __shfl(incl, j, kWave);
+        const int deg_j = __shfl(deg, j, kWave);
+        const int rs_j = __shfl(rs, j, kWave);
+        const int uj = (int)t * 64 + j;
+        fmw[q] = shfl64(fmu, j);
+        v[q] = 0;
+        f[q] = 0;
+        if (has) {
+          v[q] = a.col[rs_j + (x - (inc_j - deg_j))];
+          if (wok && ((fmw[q] >> w) & 1ull)) f[q] = front[(size_t)uj * W + w];
+        }
       }
-      relax<P>(a, out, T, v, f, w, gm);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) relax<P>(a, out, T, v[q], f[q], w, gm);
     }
   }
   edges = wave_sum(edges);
@@ -233,17 +335,17 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   const int wv = tid / kWave;
   const int W = a.W;
   const int D = a.nplanes;
-  if (tid < W) {
-    u64 mb[kMaxPlanes];
-    for (int b = 0; b < kMaxPlanes; ++b) mb[b] = 0;
-    for (int r = 0; r < 64; ++r) {
-      const int rel = L - a.base[tid * 64 + r];
-      for (int b = 0; b < D; ++b)
-        if ((rel >> b) & 1) mb[b] |= 1ull << r;
+  // one word per wave: lane r holds source (64 x + r)'s relative level, and a
+  // ballot per plane gives that plane's mask
+  for (int x = wv; x < W; x += kBatchBlock / kWave) {
+    const int rel = L - a.base[x * 64 + lane];
+#pragma unroll
+    for (int b = 0; b < kMaxPlanes; ++b) {
+      const u64 m = __ballot(b < D && ((rel >> b) & 1));
+      if (lane == 0) lmask[b][x] = m;
     }
-    for (int b = 0; b < kMaxPlanes; ++b) lmask[b][tid] = mb[b];
-    actb[tid] = 0;
   }
+  if (tid < 64) actb[tid] = 0;
   __syncthreads();
 
   const int cl = L & 1;
@@ -261,6 +363,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   if (L > 0) {
     u64* F = a.touched[(L - 1) & 1];
     u64* prev = a.nxt[(L - 1) & 1];
+    u64* pmap = a.fmap[(L - 1) & 1];
     for (unsigned t = gw; t < (unsigned)nwords; t += nwaves) {
       const u64 fw = F[t];
       if (!fw) continue;
@@ -269,7 +372,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
       __builtin_amdgcn_wave_barrier();
       for (int i0 = 0; i0 < cnt; i0 += npw) {
         const int i = i0 + sub;
-        if (i < cnt && wok) prev[(size_t)((int)t * 64 + rank_j[wv][i]) * W + w] = 0;
+        if (i < cnt && wok) {
+          const int v = (int)t * 64 + rank_j[wv][i];
+          prev[(size_t)v * W + w] = 0;
+          if (w == 0) pmap[v] = 0;
+        }
       }
       __builtin_amdgcn_wave_barrier();
       if (lane == 0) F[t] = 0;
@@ -277,6 +384,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   }
 
   u64* nxt = a.nxt[cl];
+  u64* fmap = a.fmap[cl];
   const u64* T = a.touched[cl];
   u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0;
   for (unsigned t = gw; t < (unsigned)nwords; t += nwaves) {
@@ -298,9 +406,13 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
       const int i = i0 + sub;
       const int j = rank_j[wv][i < cnt ? i : cnt - 1];
       const int dj = __shfl(deg, j, kWave);
+      u64 nb = 0;
+      if (i < cnt && wok) nb = nxt[(size_t)(v0 + j) * W + w];
+      // the group's nonzero words of node v0 + j: its frontier word map
+      const u64 nzb = __ballot(nb != 0);
+      if (i < cnt && w == 0) fmap[v0 + j] = (nzb >> ((sub * P) & 63)) & low_mask<P>();
       if (i < cnt && wok) {
         const size_t idx = (size_t)(v0 + j) * W + w;
-        const u64 nb = nxt[idx];
         if (nb) {
           a.vis[idx] |= nb;
           for (int b = 0; b < D; ++b) {
@@ -345,36 +457,41 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
 }
 
 // ------------------------------------------------------------------ emit --
-// Write the distance rows of the lanes in emask.  One workgroup per tile of
-// 64 nodes; the tile's visited words and level planes are read a chunk of
-// kEmitWords words at a time (each node's chunk is one contiguous 128-byte
-// line), transposed into LDS, and then each wave takes a word: a lane holds
-// node v0+lane's visited bits and planes for that word in registers and
-// rebuilds every emitted source's level, writing 64 consecutive int32 of the
-// source's row (one 256-byte store) per source.  With `clear` the emitted
+// Write the distance rows of the lanes in emask.  A workgroup takes a tile of
+// kEmitSub x 64 nodes; the tile's visited words and level planes are read
+// EW = 16 / DMAX words at a time (contiguous within each node's row) and
+// transposed into LDS.  Then, for each word of the chunk, wave q of the block
+// takes the emitted sources b with b % 4 == q: a lane holds nodes
+// v0 + 64 s + lane (s < kEmitSub) in registers, rebuilds the source's level
+// for them and writes kEmitSub consecutive 256-byte pieces of the source's
+// row (one contiguous run per row and tile).  With `clear` the emitted
 // lanes' bits are removed from vis and the planes (serving reuses the lanes).
-constexpr int kEmitWords = 16;
+constexpr int kEmitSub = 4;
+constexpr int kEmitTile = kEmitSub * 64;
 
 template <int DMAX>
 __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, const u64* emask,
                                                           int clear) {
-  __shared__ u64 sx[kEmitWords][65];
-  __shared__ u64 sp[DMAX][kEmitWords][65];
+  constexpr int EW = 16 / DMAX;
+  __shared__ u64 sx[EW][kEmitTile + 1];
+  __shared__ u64 sp[DMAX][EW][kEmitTile + 1];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int W = a.W;
-  const int ntiles = (a.n + 63) / 64;
+  const int ntiles = (a.n + kEmitTile - 1) / kEmitTile;
+  // sources b with b % 4 == wv belong to wave wv
+  const u64 wave_bits = 0x1111111111111111ull << wv;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int v0 = t * 64;
-    const int nv = min(64, a.n - v0);
-    for (int wc0 = 0; wc0 < W; wc0 += kEmitWords) {
-      const int wcn = min(kEmitWords, W - wc0);
+    const int v0 = t * kEmitTile;
+    const int nv = min(kEmitTile, a.n - v0);
+    for (int wc0 = 0; wc0 < W; wc0 += EW) {
+      const int wcn = min(EW, W - wc0);
       bool any = false;
       for (int i = 0; i < wcn; ++i) any |= emask[wc0 + i] != 0;
       if (!any) continue;
       __syncthreads();
-      for (int e = tid; e < 64 * wcn; e += kBatchBlock) {
+      for (int e = tid; e < kEmitTile * wcn; e += kBatchBlock) {
         const int j = e / wcn, wl = e % wcn;
         u64 x = 0;
         u64 pv[DMAX];
@@ -399,27 +516,40 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, co
         for (int d = 0; d < DMAX; ++d) sp[d][wl][j] = pv[d];
       }
       __syncthreads();
-      for (int wl = wv; wl < wcn; wl += kBatchBlock / kWave) {
+      for (int wl = 0; wl < wcn; ++wl) {
         const int w = wc0 + wl;
-        u64 em = emask[w];
+        u64 em = emask[w] & wave_bits;
         if (!em) continue;
-        const u64 x = sx[wl][lane];
-        u64 pl[DMAX];
+        u64 x[kEmitSub];
+        u64 pl[DMAX][kEmitSub];
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d) pl[d] = sp[d][wl][lane];
-        const int v = v0 + lane;
+        for (int q = 0; q < kEmitSub; ++q) {
+          x[q] = sx[wl][q * 64 + lane];
+#pragma unroll
+          for (int d = 0; d < DMAX; ++d) pl[d][q] = sp[d][wl][q * 64 + lane];
+        }
+        // lane b holds source (64 w + b)'s row pointer; each row is read from
+        // that lane instead of a memory load per row
+        const unsigned long long my_row = (unsigned long long)a.rows[w * 64 + lane];
         while (em) {
           const int b = __ffsll((unsigned long long)em) - 1;
           em &= em - 1;
-          int32_t* row = a.rows[w * 64 + b];
+          const unsigned lo = __shfl((unsigned)my_row, b, kWave);
+          const unsigned hi = __shfl((unsigned)(my_row >> 32), b, kWave);
+          int32_t* row = (int32_t*)(((unsigned long long)hi << 32) | lo);
           if (!row) continue;
-          int val = -1;
-          if ((x >> b) & 1ull) {
-            val = 0;
 #pragma unroll
-            for (int d = 0; d < DMAX; ++d) val |= (int)((pl[d] >> b) & 1ull) << d;
+          for (int q = 0; q < kEmitSub; ++q) {
+            int val = -1;
+            if ((x[q] >> b) & 1ull) {
+              val = 0;
+#pragma unroll
+              for (int d = 0; d < DMAX; ++d) val |= (int)((pl[d][q] >> b) & 1ull) << d;
+            }
+            const int j = q * 64 + lane;
+            // written once and not read again by the library: bypass the caches
+            if (j < nv) __builtin_nontemporal_store(val, &row[v0 + j]);
           }
-          if (lane < nv) row[v] = val;
         }
       }
     }
@@ -445,6 +575,7 @@ __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane,
     const size_t idx = (size_t)s * a.W + (l >> 6);
     const u64 bit = 1ull << (l & 63);
     atom_or(&a.nxt[L & 1][idx], bit);
+    atom_or(&a.fmap[L & 1][s], 1ull << (l >> 6));
     const u64 sbit = 1ull << (s & 63);
     const u64 old = atom_or(&a.touched[L & 1][s >> 6], sbit);
     if (live) {
@@ -465,6 +596,7 @@ void batch_ws_destroy(BatchWs* w) {
   for (int b = 0; b < kMaxPlanes; ++b) dev_free(ctx, w->planes[b], 0);
   for (int i = 0; i < 2; ++i) {
     dev_free(ctx, w->touched[i], 0);
+    dev_free(ctx, w->fmap[i], 0);
     dev_free(ctx, w->cu[i], 0);
     dev_free(ctx, w->ck[i], 0);
   }
@@ -509,6 +641,7 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   alloc((void**)&w->nxt[1], n * W * 8);
   for (int i = 0; i < 2; ++i) {
     alloc((void**)&w->touched[i], nw * 8 + 64);
+    alloc((void**)&w->fmap[i], n * 8);
     alloc((void**)&w->cu[i], chunk_cap * 4);
     alloc((void**)&w->ck[i], chunk_cap * 4);
   }
@@ -566,6 +699,9 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W) {
   a.col = g->col;
   a.ip = g->ip;
   a.isrc = g->isrc;
+  a.pcv = g->pcv;
+  a.pck = g->pck;
+  a.npc = g->npc;
   a.vis = w->vis;
   a.nxt[0] = w->nxt[0];
   a.nxt[1] = w->nxt[1];
@@ -573,6 +709,7 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W) {
   a.nplanes = w->nplanes;
   for (int i = 0; i < 2; ++i) {
     a.touched[i] = w->touched[i];
+    a.fmap[i] = w->fmap[i];
     a.cu[i] = w->cu[i];
     a.ck[i] = w->ck[i];
   }
@@ -652,7 +789,7 @@ dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t 
 
 dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
                               bool clear, hipStream_t s) {
-  const int ntiles = (a.n + 63) / 64;
+  const int ntiles = (a.n + kEmitTile - 1) / kEmitTile;
   const int grid = std::max(1, std::min(ntiles, ctx->num_cu * 8));
   const int D = nplanes_used;
   if (D <= 4)
@@ -726,12 +863,14 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
   DAWN_TRY(batch_launch_zero(ctx, w->nxt[1], nW, s));
   DAWN_TRY(batch_launch_zero(ctx, w->touched[0], ((size_t)g->n + 63) / 64, s));
   DAWN_TRY(batch_launch_zero(ctx, w->touched[1], ((size_t)g->n + 63) / 64, s));
+  DAWN_TRY(batch_launch_zero(ctx, w->fmap[0], (size_t)g->n, s));
+  DAWN_TRY(batch_launch_zero(ctx, w->fmap[1], (size_t)g->n, s));
   for (int b = 0; b < w->planes_dirty; ++b) DAWN_TRY(batch_launch_zero(ctx, w->planes[b], nW, s));
   w->planes_dirty = 0;
   BatchArgs a = batch_args(g, w, W);
   DAWN_TRY(batch_launch_seed(ctx, a, w->src, w->lane, k, 0, false, s));
   DAWN_TRY(batch_launch_merge(ctx, a, 0, s));
-  int launches = 7 + w->planes_dirty;
+  int launches = 9 + w->planes_dirty;
   int last_nonempty = 0;
   for (int L = 1;; ++L) {
     const int pl = (L - 1) & 1;

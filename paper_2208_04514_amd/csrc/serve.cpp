@@ -189,6 +189,8 @@ static dawn_status engine_create(Server* S, const std::shared_ptr<GraphRec>& g, 
   if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->nxt[1], nW, w->stream);
   if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->touched[0], ((size_t)g->n + 63) / 64, w->stream);
   if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->touched[1], ((size_t)g->n + 63) / 64, w->stream);
+  if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->fmap[0], (size_t)g->n, w->stream);
+  if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->fmap[1], (size_t)g->n, w->stream);
   if (z == DAWN_OK) {
     he = hipMemcpyAsync(w->base, e->h_base, (size_t)e->capacity * 4, hipMemcpyHostToDevice, w->stream);
     if (he == hipSuccess)
@@ -543,7 +545,8 @@ dawn_status serve_submit(Ctx* ctx, int32_t graph, const int32_t* sources, int32_
       return fail(DAWN_E_INVALID_ARG, "sources[%d] = %d outside [0, %d)", r, sources[r], g->n);
   // a query that can never fit the budget fails now
   const int W = (capacity + 63) / 64;
-  const uint64_t engine_bytes = (uint64_t)g->n * W * 8 * (3 + kMaxPlanes);   // vis, nxt, planes
+  // vis, nxt, planes and the two frontier word maps
+  const uint64_t engine_bytes = (uint64_t)g->n * W * 8 * (3 + kMaxPlanes) + (uint64_t)g->n * 16;
   const uint64_t stage = (flags & DAWN_DEVICE_OUT) ? 0 : (uint64_t)k * g->n * 4;
   if (engine_bytes + stage + g->bytes > ctx->budget)
     return fail(DAWN_E_NO_MEMORY, "query needs %llu bytes beyond the graph, budget is %llu",
