@@ -38,7 +38,7 @@
 namespace dawn {
 
 constexpr int kBatchBlock = 256;
-constexpr int kBigB = 256;        // out-degree from which a frontier node's edges are chunked
+constexpr int kBigB = 64;         // out-degree from which a frontier node's edges are chunked
 constexpr int kChunkB = 64;       // out-edges per chunk of a big-degree node
 
 // group of P lanes per node: lane w of the group handles word w
@@ -74,72 +74,85 @@ __device__ __forceinline__ void push_chunks(const BatchArgs& a, int L, int v, in
   }
 }
 
+// Append the out-edge chunks of node v (when big) to level L's chunk list,
+// one counter atomic per wave (wave-uniform call).
+__device__ __forceinline__ void push_chunks_wave(const BatchArgs& a, int L, int v, int deg,
+                                                 bool big) {
+  const int nch = big ? (deg + kChunkB - 1) / kChunkB : 0;
+  const int incl = wave_incl_scan(nch);
+  const int total = __shfl(incl, kWave - 1, kWave);
+  if (total == 0) return;
+  unsigned base = 0;
+  if (lane_id() == kWave - 1) base = atom_add(&a.ctrl->lv[L & 1].nchunks, (unsigned)total);
+  base = (unsigned)__shfl((int)base, kWave - 1, kWave);
+  const unsigned b0 = base + (unsigned)(incl - nch);
+  for (int k = 0; k < nch; ++k) {
+    a.cu[L & 1][b0 + k] = v;
+    a.ck[L & 1][b0 + k] = (int32_t)k;
+  }
+}
+
 // ------------------------------------------------------------- expansion --
+// Lane i of the group reads value x of group lane i (group-uniform call).
+template <int P>
+__device__ __forceinline__ int group_read(int x, int gb, int i) {
+  if (P == 64) return __builtin_amdgcn_readlane(x, i);
+  return __shfl(x, gb + i, kWave);
+}
+
+template <int P>
+__device__ __forceinline__ u64 group_read64(u64 x, int gb, int i) {
+  const unsigned lo = (unsigned)group_read<P>((int)(unsigned)x, gb, i);
+  const unsigned hi = (unsigned)group_read<P>((int)(unsigned)(x >> 32), gb, i);
+  return ((u64)hi << 32) | lo;
+}
+
 // OR into acc the previous level's new bits of in-edges [s, e) that lie in
 // `need`, stopping once every lane of the group has all of its word's needed
-// bits (group-uniform call).  Returns the number of in-edges read.
+// bits (group-uniform call; gb = the group's first lane).  Returns the number
+// of in-edges read.
 //
 // Per lane r, an unvisited v has an in-neighbour visited in r iff it has one
 // whose bit r is new at level L - 1, and the two give the same bits of
 // `need`: the scan reads the previous level's new rows, and only the words
-// that the frontier word map marks nonzero.
+// that the frontier word map marks nonzero.  The group reads P in-edges and
+// their map words at a time (lane i takes edge i), then walks the edges whose
+// source is on the frontier, each lane loading its own word of those rows.
 template <int P>
 __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, const u64* fm, int s,
-                                         int e, u64 need, int w, u64 gm, u64& acc) {
+                                         int e, u64 need, int w, int gb, u64 gm, u64& acc) {
   const size_t W = (size_t)a.W;
   int j = s;
-  bool sat = false;
-  // eight (then four) in-neighbours per step keep independent loads in
-  // flight; a lane whose word is already covered issues no row loads
-  for (; j + 8 <= e; j += 8) {
-    int u[8];
-    u64 mk[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) u[q] = a.isrc[j + q];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) mk[q] = fm[u[q]];
-    if (acc != need) {
-      u64 r = 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if ((mk[q] >> w) & 1ull) r |= front[(size_t)u[q] * W + w];
-      acc |= r & need;
+  while (j < e) {
+    int my_u = 0;
+    u64 my_m = 0;
+    if (j + w < e) {
+      my_u = a.isrc[j + w];
+      my_m = fm[my_u];
     }
-    if ((__ballot(acc != need) & gm) == 0) {
-      j += 8;
-      sat = true;
-      break;
+    j += P;
+    u64 hits = (__ballot(my_m != 0) & gm) >> gb;    // bit i: edge i's source is on the frontier
+    u64 r = 0;
+    while (hits) {
+      u64 val[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        val[q] = 0;
+        if (hits) {
+          const int i = __builtin_ctzll(hits);
+          hits &= hits - 1;
+          const int u = group_read<P>(my_u, gb, i);
+          const u64 m = group_read64<P>(my_m, gb, i);
+          if (((m >> w) & 1ull) && acc != need) val[q] = front[(size_t)u * W + w];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) r |= val[q];
     }
+    acc |= r & need;
+    if ((__ballot(acc != need) & gm) == 0) break;
   }
-  for (; !sat && j + 4 <= e; j += 4) {
-    int u[4];
-    u64 mk[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = a.isrc[j + q];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) mk[q] = fm[u[q]];
-    if (acc != need) {
-      u64 r = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if ((mk[q] >> w) & 1ull) r |= front[(size_t)u[q] * W + w];
-      acc |= r & need;
-    }
-    if ((__ballot(acc != need) & gm) == 0) {
-      j += 4;
-      sat = true;
-      break;
-    }
-  }
-  for (; !sat && j < e; ++j) {
-    const int u = a.isrc[j];
-    if (acc != need && ((fm[u] >> w) & 1ull)) acc |= front[(size_t)u * W + w] & need;
-    if ((__ballot(acc != need) & gm) == 0) {
-      ++j;
-      break;
-    }
-  }
-  return j - s;
+  return min(j, e) - s;
 }
 
 template <int P>
@@ -150,6 +163,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   const int sub = lane / P;
   const bool wok = w < a.W;
   const u64 gm = group_mask<P>(lane);
+  const int gb = P == 64 ? 0 : (lane & ~(P - 1));
   const u64 actw = wok ? a.act[w] : 0ull;
   const size_t W = (size_t)a.W;
   const u64* front = a.nxt[(L - 1) & 1];
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     }
     u64 acc = 0;
     if ((__ballot(need != 0) & gm) != 0) {
-      const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gm, acc);
+      const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gb, gm, acc);
       if (w == 0) edges += (u64)nr;
     }
     if (acc) atom_or(&nxt[(size_t)v * W + w], acc);
@@ -197,7 +211,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     const u64 need = (mine && wok) ? (actw & ~vw) : 0ull;
     u64 acc = 0;
     if ((__ballot(need != 0) & gm) != 0) {
-      const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gm, acc);
+      const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gb, gm, acc);
       if (w == 0) edges += (u64)nr;
     }
     if (acc) nxt[(size_t)v * W + w] = acc;
@@ -208,22 +222,35 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges[blockIdx.x % kStripes], edges);
 }
 
-// Push bits f of a frontier node along its edge to v (group-uniform call).
+// Push bits f[q] of frontier nodes along their edges to v[q], q < 4
+// (group-uniform call).  Every load of the four edges is issued before any
+// atomic: a stale read of `out` only costs a redundant atomic.
 template <int P>
-__device__ __forceinline__ void relax(const BatchArgs& a, u64* out, u64* T, int v, u64 f, int w,
-                                      u64 gm) {
-  u64 b = 0;
-  if (f) {
-    b = f & ~a.vis[(size_t)v * a.W + w];
-    // bits already staged for v this level need no atomic
-    if (b) b &= ~out[(size_t)v * a.W + w];
-    if (b) atom_or(&out[(size_t)v * a.W + w], b);
+__device__ __forceinline__ void relax4(const BatchArgs& a, u64* out, u64* T, const int* v,
+                                       const u64* f, int w, u64 gm) {
+  const size_t W = (size_t)a.W;
+  u64 b[4], o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) b[q] = f[q] ? f[q] & ~a.vis[(size_t)v[q] * W + w] : 0ull;
+  // bits already staged for v this level need no atomic
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = b[q] ? out[(size_t)v[q] * W + w] : 0ull;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    b[q] &= ~o[q];
+    if (b[q]) atom_or(&out[(size_t)v[q] * W + w], b[q]);
   }
-  const bool any = (__ballot(b != 0) & gm) != 0;
-  if (any && w == 0) {
-    u64* tw = &T[v >> 6];
-    const u64 bit = 1ull << (v & 63);
-    if (!(*tw & bit)) atom_or(tw, bit);
+  bool any[4];
+  u64 tv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    any[q] = (__ballot(b[q] != 0) & gm) != 0 && w == 0;
+    tv[q] = any[q] ? T[v[q] >> 6] : 0ull;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const u64 bit = 1ull << (v[q] & 63);
+    if (any[q] && !(tv[q] & bit)) atom_or(&T[v[q] >> 6], bit);
   }
 }
 
@@ -261,15 +288,18 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
       if (wok) f = front[(size_t)u * W + w];
     }
     if (has && w == 0) edges += (u64)(e1 - e0);
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const int v0 = a.col[e], v1 = a.col[e + 1], v2 = a.col[e + 2], v3 = a.col[e + 3];
-      relax<P>(a, out, T, v0, f, w, gm);
-      relax<P>(a, out, T, v1, f, w, gm);
-      relax<P>(a, out, T, v2, f, w, gm);
-      relax<P>(a, out, T, v3, f, w, gm);
+    // group-uniform steps of four edges (past e1: no bits)
+    for (int e = e0; e < e1; e += 4) {
+      int v[4];
+      u64 fq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool in = e + q < e1;
+        v[q] = in ? a.col[e + q] : 0;
+        fq[q] = in ? f : 0ull;
+      }
+      relax4<P>(a, out, T, v, fq, w, gm);
     }
-    for (; e < e1; ++e) relax<P>(a, out, T, a.col[e], f, w, gm);
   }
 
   // other frontier nodes, 64 per wave (one frontier word): the wave walks the
@@ -312,8 +342,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
           if (wok && ((fmw[q] >> w) & 1ull)) f[q] = front[(size_t)uj * W + w];
         }
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) relax<P>(a, out, T, v[q], f[q], w, gm);
+      relax4<P>(a, out, T, v, f, w, gm);
     }
   }
   edges = wave_sum(edges);
@@ -399,8 +428,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
       deg = a.rp[v0 + lane + 1] - a.rp[v0 + lane];
       nodes += 1;
       mf += (u64)deg;
-      if (deg >= kBigB) push_chunks(a, L, v0 + lane, deg);
     }
+    push_chunks_wave(a, L, v0 + lane, deg, mine && deg >= kBigB);
     __builtin_amdgcn_wave_barrier();
     for (int i0 = 0; i0 < cnt; i0 += npw) {
       const int i = i0 + sub;
