@@ -130,14 +130,38 @@ __global__ void count_in_degree(const int32_t* col, long long m, int32_t* cnt) {
     atomicAdd(&cnt[col[e]], 1);
 }
 
-__global__ void scatter_in_edges(const int32_t* rp, const int32_t* col, int n, long long m,
+// floor(log2(d)) for d >= 1
+__device__ __forceinline__ int degree_class(int d) { return 31 - __clz(d); }
+
+// Scatter the out-edges of the sources whose out-degree class is `cls` into
+// the in-lists.  Run for cls from the largest class down to 0, it leaves
+// every in-list ordered by decreasing source out-degree class (the order
+// within a class follows the atomics): a pull that stops at the first hit
+// then meets the high-degree in-neighbours, the likeliest to be reached,
+// first.  Each wave takes 64 sources and walks the matching ones' out-lists
+// with all of its lanes.
+__global__ void scatter_in_edges(const int32_t* rp, const int32_t* col, int n, int cls,
                                  const int32_t* ip, int32_t* fill, int32_t* isrc) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < m;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int u = row_of(rp, n, e);
-    const int v = col[e];
-    const int pos = atomicAdd(&fill[v], 1);
-    isrc[ip[v] + pos] = u;
+  const int lane = lane_id();
+  const int nwaves = gridDim.x * blockDim.x / kWave;
+  for (int b = (blockIdx.x * blockDim.x + threadIdx.x) / kWave * kWave; b < n; b += nwaves * kWave) {
+    const int u = b + lane;
+    int s = 0, d = 0;
+    if (u < n) {
+      s = rp[u];
+      d = rp[u + 1] - s;
+    }
+    u64 match = __ballot(d > 0 && degree_class(d) == cls);
+    while (match) {
+      const int j = __builtin_ctzll(match);
+      match &= match - 1;
+      const int sj = __shfl(s, j, kWave), dj = __shfl(d, j, kWave);
+      for (int e = lane; e < dj; e += kWave) {
+        const int v = col[sj + e];
+        const int pos = atomicAdd(&fill[v], 1);
+        isrc[ip[v] + pos] = b + j;
+      }
+    }
   }
 }
 
@@ -160,9 +184,10 @@ static dawn_status build_csc(Ctx* ctx, int n, long long m, const int32_t* rp, co
   if (e == hipSuccess) st = scan_exclusive(ctx, cnt, n, ip, s);
   if (e == hipSuccess && st == DAWN_OK && m > 0) {
     e = hipMemsetAsync(cnt, 0, ((size_t)n + 1) * 4, s);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(scatter_in_edges, dim3(grid_for(ctx, m, 256)), dim3(256), 0, s, rp, col,
-                         n, m, ip, cnt, isrc);
+    const int max_class = 30;
+    for (int cls = max_class; cls >= 0 && e == hipSuccess; --cls) {
+      hipLaunchKernelGGL(scatter_in_edges, dim3(grid_for(ctx, (long long)n, 256)), dim3(256), 0, s,
+                         rp, col, n, cls, ip, cnt, isrc);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

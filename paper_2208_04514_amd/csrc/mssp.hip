@@ -254,6 +254,43 @@ __device__ __forceinline__ void relax4(const BatchArgs& a, u64* out, u64* T, con
   }
 }
 
+// A frontier node with at most kSparseWords nonzero words is pushed one edge
+// per lane (over those words) instead of one word per lane.
+constexpr int kSparseWords = 4;
+
+// Relax edge (u -> v) over the nonzero words `fmu` of u's frontier row
+// (per lane; at most kSparseWords words).
+__device__ __forceinline__ void relax_edge_sparse(const BatchArgs& a, const u64* front, u64* out,
+                                                  u64* T, int u, int v, u64 fmu) {
+  const size_t W = (size_t)a.W;
+  int wk[kSparseWords];
+  u64 f[kSparseWords], b[kSparseWords], o[kSparseWords];
+#pragma unroll
+  for (int k = 0; k < kSparseWords; ++k) {
+    wk[k] = fmu ? __builtin_ctzll(fmu) : -1;
+    fmu &= fmu - 1;
+  }
+#pragma unroll
+  for (int k = 0; k < kSparseWords; ++k) f[k] = wk[k] >= 0 ? front[(size_t)u * W + wk[k]] : 0ull;
+#pragma unroll
+  for (int k = 0; k < kSparseWords; ++k) b[k] = f[k] ? f[k] & ~a.vis[(size_t)v * W + wk[k]] : 0ull;
+#pragma unroll
+  for (int k = 0; k < kSparseWords; ++k) o[k] = b[k] ? out[(size_t)v * W + wk[k]] : 0ull;
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < kSparseWords; ++k) {
+    b[k] &= ~o[k];
+    if (b[k]) {
+      atom_or(&out[(size_t)v * W + wk[k]], b[k]);
+      any = true;
+    }
+  }
+  if (any) {
+    const u64 bit = 1ull << (v & 63);
+    if (!(T[v >> 6] & bit)) atom_or(&T[v >> 6], bit);
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
   const int lane = lane_id();
@@ -278,16 +315,22 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
   for (unsigned cb = gw * npw; cb < nch; cb += nwaves * npw) {
     const unsigned c = cb + (unsigned)sub;
     const bool has = c < nch;
-    int e0 = 0, e1 = 0;
-    u64 f = 0;
+    int e0 = 0, e1 = 0, u = 0;
+    u64 f = 0, fmu = 0;
     if (has) {
-      const int u = a.cu[pl][c];
+      u = a.cu[pl][c];
       const int k = a.ck[pl][c];
       e0 = a.rp[u] + k * kChunkB;
       e1 = min(e0 + kChunkB, a.rp[u + 1]);
-      if (wok) f = front[(size_t)u * W + w];
+      fmu = fmp[u];
     }
     if (has && w == 0) edges += (u64)(e1 - e0);
+    if (__popcll(fmu) <= kSparseWords) {
+      // few nonzero words: lane w of the group takes edges e0 + w, e0 + w + P, ...
+      for (int e = e0 + w; e < e1; e += P) relax_edge_sparse(a, front, out, T, u, a.col[e], fmu);
+      continue;
+    }
+    if (wok && ((fmu >> w) & 1ull)) f = front[(size_t)u * W + w];
     // group-uniform steps of four edges (past e1: no bits)
     for (int e = e0; e < e1; e += 4) {
       int v[4];
@@ -309,17 +352,36 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
     const u64 fw = F[t];
     if (!fw) continue;
     const int u = (int)t * 64 + lane;
-    int deg = 0, rs = 0;
+    int deg = 0, rs = 0, sdeg = 0;
     u64 fmu = 0;
     if ((fw >> lane) & 1ull) {
       rs = a.rp[u];
       deg = a.rp[u + 1] - rs;
-      if (deg >= kBigB) deg = 0;
       fmu = fmp[u];
+      if (deg >= kBigB) deg = 0;
+      if (__popcll(fmu) <= kSparseWords) {
+        sdeg = deg;
+        deg = 0;
+      }
+    }
+    // sparse nodes: one edge per lane over the union of their out-lists
+    const int sincl = wave_incl_scan(sdeg);
+    const int stotal = __shfl(sincl, kWave - 1, kWave);
+    for (int eb = 0; eb < stotal; eb += kWave) {
+      const int x = eb + lane;
+      const bool has = x < stotal;
+      const int j = wave_owner(sincl, has ? x : stotal - 1);
+      const int inc_j = __shfl(sincl, j, kWave);
+      const int deg_j = __shfl(sdeg, j, kWave);
+      const int rs_j = __shfl(rs, j, kWave);
+      const u64 fm_j = shfl64(fmu, j);
+      if (has)
+        relax_edge_sparse(a, front, out, T, (int)t * 64 + j, a.col[rs_j + (x - (inc_j - deg_j))],
+                          fm_j);
     }
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, kWave - 1, kWave);
-    if (w == 0 && sub == 0) edges += (u64)total;
+    if (lane == 0) edges += (u64)(total + stotal);
     // four edges per lane group and step keep independent loads in flight
     for (int eb = 0; eb < total; eb += 4 * npw) {
       int v[4];
@@ -352,7 +414,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
 // ----------------------------------------------------------------- merge --
 // Fold the new bits of level L into vis and the level planes, list the
 // big-degree nodes' out-edge chunks for the next push, and clear the rows and
-// bitmap of the previous frontier.  One wave per 64-node word (grid-stride).
+// bitmap of the previous frontier.
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   __shared__ u64 lmask[kMaxPlanes][64];   // bit b of (L - base) for the lanes of each word
@@ -416,42 +478,69 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   u64* fmap = a.fmap[cl];
   const u64* T = a.touched[cl];
   u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0;
-  for (unsigned t = gw; t < (unsigned)nwords; t += nwaves) {
+  // a work unit is a quarter of a frontier word (ranks 16 s .. 16 s + 15 of
+  // its set bits), so that dense words spread over four waves; within a unit
+  // four nodes' rows are loaded before any of them is written back
+  const unsigned nunits = (unsigned)nwords * 4u;
+  for (unsigned ux = gw; ux < nunits; ux += nwaves) {
+    const unsigned t = ux >> 2;
     const u64 tw = T[t];
-    if (tw == 0) continue;
-    const int v0 = (int)t * 64;
-    const bool mine = (tw >> lane) & 1ull;
     const int cnt = __popcll(tw);
+    const int ib = (int)(ux & 3u) * 16, ie = min(ib + 16, cnt);
+    if (ib >= ie) continue;
+    const int v0 = (int)t * 64;
+    const bool bit = (tw >> lane) & 1ull;
+    const int rk = __popcll(tw & lanes_below());
+    const bool mine = bit && rk >= ib && rk < ie;
     int deg = 0;
+    if (bit) rank_j[wv][rk] = lane;
     if (mine) {
-      rank_j[wv][__popcll(tw & lanes_below())] = lane;
       deg = a.rp[v0 + lane + 1] - a.rp[v0 + lane];
       nodes += 1;
       mf += (u64)deg;
     }
     push_chunks_wave(a, L, v0 + lane, deg, mine && deg >= kBigB);
     __builtin_amdgcn_wave_barrier();
-    for (int i0 = 0; i0 < cnt; i0 += npw) {
-      const int i = i0 + sub;
-      const int j = rank_j[wv][i < cnt ? i : cnt - 1];
-      const int dj = __shfl(deg, j, kWave);
-      u64 nb = 0;
-      if (i < cnt && wok) nb = nxt[(size_t)(v0 + j) * W + w];
-      // the group's nonzero words of node v0 + j: its frontier word map
-      const u64 nzb = __ballot(nb != 0);
-      if (i < cnt && w == 0) fmap[v0 + j] = (nzb >> ((sub * P) & 63)) & low_mask<P>();
-      if (i < cnt && wok) {
-        const size_t idx = (size_t)(v0 + j) * W + w;
-        if (nb) {
-          a.vis[idx] |= nb;
-          for (int b = 0; b < D; ++b) {
-            const u64 m = lmask[b][w] & nb;
-            if (m) a.planes[b][idx] |= m;
-          }
-          const u64 pc = (u64)__popcll(nb);
+    for (int i0 = ib; i0 < ie; i0 += 4 * npw) {
+      int jq[4], dq[4];
+      bool okq[4];
+      u64 nb[4], vo[4];
+      size_t idx[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * npw + sub;
+        okq[q] = i < ie;
+        jq[q] = rank_j[wv][okq[q] ? i : ib];
+        dq[q] = __shfl(deg, jq[q], kWave);
+        idx[q] = (size_t)(v0 + jq[q]) * W + w;
+        nb[q] = (okq[q] && wok) ? nxt[idx[q]] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // the group's nonzero words of the node: its frontier word map
+        const u64 nzb = __ballot(nb[q] != 0);
+        if (okq[q] && w == 0) fmap[v0 + jq[q]] = (nzb >> ((sub * P) & 63)) & low_mask<P>();
+        vo[q] = nb[q] ? a.vis[idx[q]] : 0ull;
+      }
+      for (int b = 0; b < D; ++b) {
+        u64 mq[4], pv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          mq[q] = lmask[b][w] & nb[q];
+          pv[q] = mq[q] ? a.planes[b][idx[q]] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (mq[q]) a.planes[b][idx[q]] = pv[q] | mq[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (nb[q]) {
+          a.vis[idx[q]] = vo[q] | nb[q];
+          const u64 pc = (u64)__popcll(nb[q]);
           bits += pc;
-          se += pc * (u64)dj;
-          act_acc |= nb;
+          se += pc * (u64)dq[q];
+          act_acc |= nb[q];
         }
       }
     }
@@ -490,12 +579,12 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
 // kEmitSub x 64 nodes; the tile's visited words and level planes are read
 // EW = 16 / DMAX words at a time (contiguous within each node's row) and
 // transposed into LDS.  Then, for each word of the chunk, wave q of the block
-// takes the emitted sources b with b % 4 == q: a lane holds nodes
-// v0 + 64 s + lane (s < kEmitSub) in registers, rebuilds the source's level
-// for them and writes kEmitSub consecutive 256-byte pieces of the source's
-// row (one contiguous run per row and tile).  With `clear` the emitted
+// takes the emitted sources b with b % 4 == q: lane l holds nodes
+// v0 + 4 l .. v0 + 4 l + 3 in registers, rebuilds the source's level for them
+// and the wave writes the tile's 1 KiB run of the source's row.  With `clear` the emitted
 // lanes' bits are removed from vis and the planes (serving reuses the lanes).
-constexpr int kEmitSub = 4;
+constexpr int kEmitSub = 4;       // nodes per lane (a tile is 4 x 64 nodes)
+typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kEmitTile = kEmitSub * 64;
 
 template <int DMAX>
@@ -540,9 +629,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, co
               if (d < D) a.planes[d][idx] = pv[d] & ~em;
           }
         }
-        sx[wl][j] = x;
+        // node j sits at (j % 4) * 64 + j / 4: lane l then reads nodes 4 l .. 4 l + 3
+        const int pj = ((j & 3) << 6) | (j >> 2);
+        sx[wl][pj] = x;
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d) sp[d][wl][j] = pv[d];
+        for (int d = 0; d < DMAX; ++d) sp[d][wl][pj] = pv[d];
       }
       __syncthreads();
       for (int wl = 0; wl < wcn; ++wl) {
@@ -567,17 +658,27 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, co
           const unsigned hi = __shfl((unsigned)(my_row >> 32), b, kWave);
           int32_t* row = (int32_t*)(((unsigned long long)hi << 32) | lo);
           if (!row) continue;
+          int val[kEmitSub];
 #pragma unroll
           for (int q = 0; q < kEmitSub; ++q) {
-            int val = -1;
+            val[q] = -1;
             if ((x[q] >> b) & 1ull) {
-              val = 0;
+              val[q] = 0;
 #pragma unroll
-              for (int d = 0; d < DMAX; ++d) val |= (int)((pl[d][q] >> b) & 1ull) << d;
+              for (int d = 0; d < DMAX; ++d) val[q] |= (int)((pl[d][q] >> b) & 1ull) << d;
             }
-            const int j = q * 64 + lane;
-            // written once and not read again by the library: bypass the caches
-            if (j < nv) __builtin_nontemporal_store(val, &row[v0 + j]);
+          }
+          // written once and not read again by the library: bypass the caches.
+          // A full tile of a 16-byte aligned row goes out as one 1 KiB store.
+          if (nv == kEmitTile && ((uintptr_t)row & 15u) == 0) {
+            const v4i vv = {val[0], val[1], val[2], val[3]};
+            __builtin_nontemporal_store(vv, reinterpret_cast<v4i*>(row + v0) + lane);
+          } else {
+#pragma unroll
+            for (int q = 0; q < kEmitSub; ++q) {
+              const int j = 4 * lane + q;
+              if (j < nv) __builtin_nontemporal_store(val[q], &row[v0 + j]);
+            }
           }
         }
       }

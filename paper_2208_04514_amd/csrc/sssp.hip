@@ -112,12 +112,17 @@ __device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool
     q.cnt += __popcll(mask);
     if (q.cnt > kWaveBuf - kWave) wq_flush(a, L, q);
   }
-  if (found && deg >= a.big_degree) {
-    unsigned nch = (unsigned)((deg + BLOCK - 1) / BLOCK);
-    unsigned base = atom_add(&a.ctrl->slot[L % 3].big_chunks, nch);
+  // big-degree nodes: their chunks of BLOCK out-edges, with one atomic on the
+  // shared chunk counter per wave (a middle level finds tens of thousands)
+  const int nch = (found && deg >= a.big_degree) ? (deg + BLOCK - 1) / BLOCK : 0;
+  if (__ballot(nch > 0)) {
+    const int incl = wave_incl_scan(nch);
+    unsigned base = 0;
+    if (lane_id() == kWave - 1) base = atom_add(&a.ctrl->slot[L % 3].big_chunks, (unsigned)incl);
+    base = (unsigned)__shfl((int)base, kWave - 1, kWave) + (unsigned)(incl - nch);
     int32_t* cu = chunk_u(a, L);
     int32_t* ck = chunk_k(a, L);
-    for (unsigned k = 0; k < nch; ++k) {
+    for (int k = 0; k < nch; ++k) {
       cu[base + k] = v;
       ck[base + k] = (int32_t)k;
     }
