@@ -154,6 +154,7 @@ dawn_status dawn_create(int32_t device, uint64_t hbm_budget_bytes, dawn_ctx** ou
   ctx->device = device;
   ctx->num_cu = prop.multiProcessorCount;
   ctx->coop = prop.cooperativeLaunch;
+  ctx->lds_per_block = prop.sharedMemPerBlock;
   uint64_t budget = hbm_budget_bytes;
   if (budget == 0) {
     const char* env = getenv("DAWN_HBM_BUDGET");

@@ -8,16 +8,20 @@ namespace dawn {
 
 constexpr int kMaxPlanes = 16;    // relative levels up to 2^16 - 1 per source
 
+// One stripe (a whole cache line) of the counters of one level of a batch.
+struct alignas(kLine) BatchStripe {
+  u64 nodes;                    // nodes that received a new bit
+  u64 bits;                     // new (node, source) pairs
+  u64 se;                       // sum over new pairs of the node's out-degree
+  u64 mf;                       // sum of out-degrees of the nodes with a new bit
+  u64 edges;                    // adjacency entries read by the expansion
+};
+
 // Counters of one level of a batch (two slots, indexed level & 1), striped
-// over kStripes addresses like the single-source counters.
+// over kStripes lines like the single-source counters.
 struct BatchLevel {
-  u64 nodes[kStripes];          // nodes that received a new bit
-  u64 bits[kStripes];           // new (node, source) pairs
-  u64 se[kStripes];             // sum over new pairs of the node's out-degree
-  u64 mf[kStripes];             // sum of out-degrees of the nodes with a new bit
-  u64 edges[kStripes];          // adjacency entries read by the expansion
-  unsigned nchunks;             // entries of the big-degree out-edge chunk list
-  unsigned pad;
+  BatchStripe s[kStripes];
+  alignas(kLine) unsigned nchunks;   // entries of the big-degree out-edge chunk list
 };
 
 struct BatchLevelSum {

@@ -55,22 +55,29 @@ struct GridBarrier {
   unsigned int pad;
 };
 
-// Counters of one level step are striped over kStripes addresses (a
-// workgroup adds into stripe blockIdx % kStripes) so that no single address
+// Counters of one level step are striped over kStripes cache lines (a
+// workgroup adds into stripe blockIdx % kStripes) so that no single line
 // takes more than a few hundred atomics per level; readers sum the stripes.
+// The L2 performs atomics one cache line at a time, so every stripe owns a
+// whole 128-byte line.
 constexpr int kStripes = 16;
+constexpr int kLine = 128;
 
 constexpr int kPullBig = 512;     // in-degree from which a batched pull splits the in-list
 constexpr int kPullChunk = 256;   // in-edges per chunk of a split in-list
 
+// One stripe of a level step's counters.
+struct alignas(kLine) SlotStripe {
+  unsigned int nf;                      // nodes found at this level
+  unsigned int small_count;             // entries appended to this stripe's small-degree sub-queue
+  u64 mf;                               // sum of out-degrees of the nodes found
+  u64 edges;                            // adjacency entries examined
+};
+
 // Counters produced by one level step (ring of three, indexed level % 3).
 struct LevelSlot {
-  unsigned int nf[kStripes];            // nodes found at this level
-  unsigned int small_count[kStripes];   // entries appended to each small-degree sub-queue
-  u64 mf[kStripes];                     // sum of out-degrees of the nodes found
-  u64 edges[kStripes];                  // adjacency entries examined
-  unsigned int big_chunks;              // chunks appended to the big-degree queue
-  unsigned int pad;
+  SlotStripe s[kStripes];
+  alignas(kLine) unsigned int big_chunks;   // chunks appended to the big-degree queue
 };
 
 // Level-loop state shared by every workgroup of a traversal.
@@ -127,6 +134,8 @@ struct SsspArgs {
   int32_t* level_nf;          // per-level discovered counts (lrec entries)
   uint8_t* level_dir;
   int32_t lrec;
+  int32_t lds_words;          // pull levels copy the visited bitmap (this many words,
+                              //   = nw) into LDS; 0 = read it from global memory
 };
 
 // ----------------------------------------------------------- host objects --
@@ -212,6 +221,7 @@ struct Ctx {
   int device = 0;
   int num_cu = 0;
   int coop = 0;
+  size_t lds_per_block = 0;                // LDS bytes a workgroup may use
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};
   std::atomic<uint64_t> reserved{0};       // budget set aside (serving engines' level planes)

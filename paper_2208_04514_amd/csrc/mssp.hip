@@ -92,6 +92,20 @@ __device__ __forceinline__ void push_chunks_wave(const BatchArgs& a, int L, int 
   }
 }
 
+// Sum `edges` over the workgroup and add it to the level's stripe (every
+// thread of the workgroup must call it).
+__device__ __forceinline__ void block_add_edges(const BatchArgs& a, int L, u64 edges) {
+  __shared__ u64 part[kBatchBlock / kWave];
+  edges = wave_sum(edges);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = edges;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 x = 0;
+    for (int i = 0; i < kBatchBlock / kWave; ++i) x += part[i];
+    if (x) atom_add(&a.ctrl->lv[L & 1].s[blockIdx.x % kStripes].edges, x);
+  }
+}
+
 // ------------------------------------------------------------- expansion --
 // Lane i of the group reads value x of group lane i (group-uniform call).
 template <int P>
@@ -218,8 +232,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     const bool any = (__ballot(acc != 0) & gm) != 0;
     if (any && w == 0) atom_or(&T[v >> 6], 1ull << (v & 63));
   }
-  edges = wave_sum(edges);
-  if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges[blockIdx.x % kStripes], edges);
+  block_add_edges(a, L, edges);
 }
 
 // Push bits f[q] of frontier nodes along their edges to v[q], q < 4
@@ -407,8 +420,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
       relax4<P>(a, out, T, v, f, w, gm);
     }
   }
-  edges = wave_sum(edges);
-  if (lane == 0 && edges) atom_add(&a.ctrl->lv[L & 1].edges[blockIdx.x % kStripes], edges);
+  block_add_edges(a, L, edges);
 }
 
 // ----------------------------------------------------------------- merge --
@@ -568,8 +580,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
     u64 x = 0;
     for (int i = 0; i < kBatchBlock / kWave; ++i) x += red[tid][i];
     if (x) {
-      u64* dst = tid == 0 ? lv->bits : tid == 1 ? lv->se : tid == 2 ? lv->nodes : lv->mf;
-      atom_add(&dst[stripe], x);
+      BatchStripe& st = lv->s[stripe];
+      u64* dst = tid == 0 ? &st.bits : tid == 1 ? &st.se : tid == 2 ? &st.nodes : &st.mf;
+      atom_add(dst, x);
     }
   }
 }
@@ -854,11 +867,11 @@ BatchLevelSum batch_level_sum(const BatchLevel& l) {
   BatchLevelSum s;
   memset(&s, 0, sizeof(s));
   for (int i = 0; i < kStripes; ++i) {
-    s.nodes += l.nodes[i];
-    s.bits += l.bits[i];
-    s.se += l.se[i];
-    s.mf += l.mf[i];
-    s.edges += l.edges[i];
+    s.nodes += l.s[i].nodes;
+    s.bits += l.s[i].bits;
+    s.se += l.s[i].se;
+    s.mf += l.s[i].mf;
+    s.edges += l.s[i].edges;
   }
   s.nchunks = l.nchunks;
   return s;

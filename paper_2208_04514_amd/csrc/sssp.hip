@@ -64,6 +64,12 @@ constexpr int kWaveBuf = 256;
 struct WaveQueue {
   int32_t* buf;   // this wave's LDS staging area (kWaveBuf entries)
   int cnt;        // wave-uniform fill
+  // the workgroup's big-degree nodes found this level (LDS, BLOCK entries):
+  // node, chunk count; filled through big_n, listed once per workgroup at
+  // the end of the level
+  int32_t* big_v;
+  int32_t* big_c;
+  unsigned* big_n;
 };
 
 __device__ __forceinline__ int32_t* small_q(const SsspArgs& a, int level) {
@@ -82,7 +88,7 @@ __device__ __forceinline__ void wq_flush(const SsspArgs& a, int L, WaveQueue& q)
   const int stripe = blockIdx.x % kStripes;
   const int lane = lane_id();
   unsigned base = 0;
-  if (lane == 0) base = atom_add(&a.ctrl->slot[L % 3].small_count[stripe], (unsigned)q.cnt);
+  if (lane == 0) base = atom_add(&a.ctrl->slot[L % 3].s[stripe].small_count, (unsigned)q.cnt);
   base = __shfl(base, 0, kWave);
   int32_t* dst = small_q(a, L) + (size_t)stripe * (size_t)a.n + base;
   __builtin_amdgcn_wave_barrier();
@@ -112,20 +118,75 @@ __device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool
     q.cnt += __popcll(mask);
     if (q.cnt > kWaveBuf - kWave) wq_flush(a, L, q);
   }
-  // big-degree nodes: their chunks of BLOCK out-edges, with one atomic on the
-  // shared chunk counter per wave (a middle level finds tens of thousands)
+  // big-degree nodes (a middle level finds tens of thousands): staged in the
+  // workgroup's LDS list, whose chunks are listed with one atomic on the
+  // shared chunk counter per workgroup; past the list's end a wave lists its
+  // own with one atomic per wave
   const int nch = (found && deg >= a.big_degree) ? (deg + BLOCK - 1) / BLOCK : 0;
-  if (__ballot(nch > 0)) {
-    const int incl = wave_incl_scan(nch);
+  const u64 bm = __ballot(nch > 0);
+  if (bm) {
+    const int lead = __ffsll((unsigned long long)bm) - 1;
     unsigned base = 0;
-    if (lane_id() == kWave - 1) base = atom_add(&a.ctrl->slot[L % 3].big_chunks, (unsigned)incl);
-    base = (unsigned)__shfl((int)base, kWave - 1, kWave) + (unsigned)(incl - nch);
-    int32_t* cu = chunk_u(a, L);
-    int32_t* ck = chunk_k(a, L);
-    for (int k = 0; k < nch; ++k) {
-      cu[base + k] = v;
-      ck[base + k] = (int32_t)k;
+    if (lane_id() == lead) base = atomicAdd(q.big_n, (unsigned)__popcll(bm));
+    base = (unsigned)__shfl((int)base, lead, kWave);
+    const unsigned slot = base + (unsigned)__popcll(bm & lanes_below());
+    const bool staged = nch > 0 && slot < (unsigned)BLOCK;
+    if (staged) {
+      q.big_v[slot] = v;
+      q.big_c[slot] = nch;
     }
+    const int rest = staged ? 0 : nch;
+    if (__ballot(rest > 0)) {
+      const int incl = wave_incl_scan(rest);
+      unsigned gb = 0;
+      if (lane_id() == kWave - 1) gb = atom_add(&a.ctrl->slot[L % 3].big_chunks, (unsigned)incl);
+      gb = (unsigned)__shfl((int)gb, kWave - 1, kWave) + (unsigned)(incl - rest);
+      int32_t* cu = chunk_u(a, L);
+      int32_t* ck = chunk_k(a, L);
+      for (int k = 0; k < rest; ++k) {
+        cu[gb + k] = v;
+        ck[gb + k] = (int32_t)k;
+      }
+    }
+  }
+}
+
+// List the chunks of the workgroup's staged big-degree nodes (every thread
+// of the workgroup calls it; resets the staging list).
+template <int BLOCK>
+__device__ __forceinline__ void flush_big(const SsspArgs& a, int L, WaveQueue& q) {
+  __shared__ int wsum[BLOCK / kWave];
+  __shared__ unsigned gbase;
+  __syncthreads();
+  const unsigned nst = min(*q.big_n, (unsigned)BLOCK);
+  if (nst == 0) return;   // uniform: every thread read the same count
+  const int t = threadIdx.x;
+  const int lane = lane_id(), wv = t / kWave;
+  int v = 0, nch = 0;
+  if ((unsigned)t < nst) {
+    v = q.big_v[t];
+    nch = q.big_c[t];
+  }
+  const int incl = wave_incl_scan(nch);
+  if (lane == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  if (t == 0) {
+    unsigned tot = 0;
+    for (int i = 0; i < BLOCK / kWave; ++i) {
+      const unsigned x = (unsigned)wsum[i];
+      wsum[i] = (int)tot;
+      tot += x;
+    }
+    gbase = atom_add(&a.ctrl->slot[L % 3].big_chunks, tot);
+    *q.big_n = 0;
+  }
+  __syncthreads();
+  const unsigned b0 = gbase + (unsigned)wsum[wv] + (unsigned)(incl - nch);
+  int32_t* cu = chunk_u(a, L);
+  int32_t* ck = chunk_k(a, L);
+  for (int k = 0; k < nch; ++k) {
+    cu[b0 + k] = v;
+    ck[b0 + k] = (int32_t)k;
   }
 }
 
@@ -153,7 +214,7 @@ __device__ __forceinline__ void stripe_prefix(const LevelSlot* in, unsigned* pre
     unsigned acc = 0;
     for (int s = 0; s < kStripes; ++s) {
       pre[s] = acc;
-      acc += ld_relaxed(&in->small_count[s]);
+      acc += ld_relaxed(&in->s[s].small_count);
     }
     pre[kStripes] = acc;
   }
@@ -227,6 +288,8 @@ struct PullScratch {
   int hit[kWave];
 };
 
+// `vin` is the visited bitmap of the previous level, read from LDS when the
+// level kernel staged a copy there.
 template <int BLOCK>
 __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, Counters& c,
                           WaveQueue& q, PullScratch* ps) {
@@ -313,13 +376,14 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
 template <int BLOCK>
 __device__ __forceinline__ void finish_level(const SsspArgs& a, int L, Counters& c, WaveQueue& q) {
   wq_flush(a, L, q);
+  flush_big<BLOCK>(a, L, q);
   block_sum3<BLOCK>(c.nf, c.mf, c.edges);
   if (threadIdx.x == 0) {
     LevelSlot* out = &a.ctrl->slot[L % 3];
     const int stripe = blockIdx.x % kStripes;
-    if (c.nf) atom_add(&out->nf[stripe], c.nf);
-    if (c.mf) atom_add(&out->mf[stripe], c.mf);
-    if (c.edges) atom_add(&out->edges[stripe], c.edges);
+    if (c.nf) atom_add(&out->s[stripe].nf, c.nf);
+    if (c.mf) atom_add(&out->s[stripe].mf, c.mf);
+    if (c.edges) atom_add(&out->s[stripe].edges, c.edges);
   }
   c.nf = 0;
   c.mf = 0;
@@ -335,9 +399,9 @@ struct SlotSum {
 __device__ __forceinline__ SlotSum sum_slot(const LevelSlot* s) {
   SlotSum r{0, 0, 0};
   for (int i = 0; i < kStripes; ++i) {
-    r.nf += ld_relaxed(&s->nf[i]);
-    r.mf += ld_relaxed(&s->mf[i]);
-    r.edges += ld_relaxed(&s->edges[i]);
+    r.nf += ld_relaxed(&s->s[i].nf);
+    r.mf += ld_relaxed(&s->s[i].mf);
+    r.edges += ld_relaxed(&s->s[i].edges);
   }
   return r;
 }
@@ -394,11 +458,11 @@ __device__ void seed(const SsspArgs& a) {
   const int s = a.ctrl->source;
   const int deg = a.rp[s + 1] - a.rp[s];
   LevelSlot* sl = &a.ctrl->slot[0];
-  sl->nf[0] = 1;
-  sl->mf[0] = (u64)deg;
+  sl->s[0].nf = 1;
+  sl->s[0].mf = (u64)deg;
   if (deg > 0 && deg < a.big_degree) {
     a.qs0[0] = s;
-    sl->small_count[0] = 1;
+    sl->s[0].small_count = 1;
   } else if (deg >= a.big_degree) {
     unsigned nch = (unsigned)((deg + BLOCK - 1) / BLOCK);
     for (unsigned k = 0; k < nch; ++k) {
@@ -443,7 +507,10 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
   __shared__ int32_t qbuf[BLOCK / kWave][kWaveBuf];
   __shared__ unsigned pre[kStripes + 1];
   __shared__ PullScratch ps[BLOCK / kWave];
-  WaveQueue q{qbuf[threadIdx.x / kWave], 0};
+  __shared__ int32_t big_v[BLOCK], big_c[BLOCK];
+  __shared__ unsigned big_n;
+  if (threadIdx.x == 0) big_n = 0;
+  WaveQueue q{qbuf[threadIdx.x / kWave], 0, big_v, big_c, &big_n};
   init_fill(a);
   if (!grid_sync(&a.ctrl->bar)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) seed<BLOCK>(a);
@@ -503,17 +570,20 @@ __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
   __shared__ PullScratch ps[BLOCK / kWave];
   __shared__ LevelState sst;
   __shared__ int idle;
+  __shared__ int32_t big_v[BLOCK], big_c[BLOCK];
+  __shared__ unsigned big_n;
   if (threadIdx.x == 0) {
+    big_n = 0;
     LevelState st = a.ctrl->st[parity ^ 1];
     if (!st.done) {
       const LevelSlot* sl = &a.ctrl->slot[st.level % 3];
       SlotSum sum{0, 0, 0};
       unsigned nsmall = 0;
       for (int i = 0; i < kStripes; ++i) {
-        sum.nf += sl->nf[i];
-        sum.mf += sl->mf[i];
-        sum.edges += sl->edges[i];
-        nsmall += sl->small_count[i];
+        sum.nf += sl->s[i].nf;
+        sum.mf += sl->s[i].mf;
+        sum.edges += sl->s[i].edges;
+        nsmall += sl->s[i].small_count;
       }
       decide(a, st, sum, blockIdx.x == 0);
       // a push level with nothing for this workgroup lets it leave at once
@@ -535,12 +605,20 @@ __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
   const int L = st.level;
   if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
   if (idle) return;
-  WaveQueue q{qbuf[threadIdx.x / kWave], 0};
+  WaveQueue q{qbuf[threadIdx.x / kWave], 0, big_v, big_c, &big_n};
   Counters c{0, 0, 0};
   u64* vcur = st.cur ? a.vis1 : a.vis0;
   if (st.pull) {
     u64* vnext = st.cur ? a.vis0 : a.vis1;
-    pull_step<BLOCK>(a, L, vcur, vnext, c, q, ps);
+    const u64* look = vcur;
+    if (a.lds_words) {
+      // every in-edge check of the sweep reads the bitmap: copy it to LDS
+      extern __shared__ u64 lds_vis[];
+      for (int i = threadIdx.x; i < a.lds_words; i += BLOCK) lds_vis[i] = vcur[i];
+      __syncthreads();
+      look = lds_vis;
+    }
+    pull_step<BLOCK>(a, L, look, vnext, c, q, ps);
   } else {
     push_step<BLOCK>(a, L, vcur, c, q, pre);
   }
@@ -673,8 +751,9 @@ static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStre
 }
 
 template <int BLOCK>
-static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, int driver,
-                              int graph_levels, int* launches, double* level_ms, int* final_parity) {
+static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, size_t shmem,
+                              int driver, int graph_levels, int* launches, double* level_ms,
+                              int* final_parity) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
   const long long max_launch = (long long)a.n + 2;
   if (driver == 2) {
@@ -685,7 +764,7 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
     for (long long it = 0; it <= max_launch; ++it) {
       const int parity = (int)(it & 1);
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
-      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a, parity);
+      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, a, parity);
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
       DAWN_HIP(hipGetLastError());
       *launches += 1;
@@ -713,7 +792,7 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
     *launches = 1;
     for (long long it = 0; it * graph_levels <= max_launch; ++it) {
       for (int i = 0; i < graph_levels; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, w->stream, a, i & 1);
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, a, i & 1);
       DAWN_HIP(hipGetLastError());
       *launches += graph_levels;
       DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[1], &w->ctrl->st[1], sizeof(LevelState),
@@ -740,11 +819,11 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
     DAWN_TRY(capture(&w->gexec, [&](hipStream_t cs) {
       hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, cs, a);
       for (int i = 0; i < graph_levels; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a, i & 1);
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
     }));
     DAWN_TRY(capture(&w->gexec_more, [&](hipStream_t cs) {
       for (int i = 0; i < graph_levels; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), 0, cs, a, i & 1);
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
     }));
     w->gexec_levels = graph_levels;
     w->gexec_block = BLOCK;
@@ -774,11 +853,23 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
     *final_parity = 1;
     return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, single);
   }
+  // the visited bitmap goes to LDS for pull levels when it fits next to the
+  // kernel's own LDS
+  hipFuncAttributes fa;
+  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
+  const size_t bitmap = (size_t)a.nw * 8;
+  size_t shmem = 0;
+  if (fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
+    shmem = bitmap;
+    a.lds_words = a.nw;
+    DAWN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sssp_level<BLOCK>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  }
   int occ = 0;
-  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, 0));
+  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, shmem));
   int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
-  return run_levels<BLOCK>(ctx, w, a, per_cu * ctx->num_cu, p.driver, std::max(p.graph_levels, 1),
-                           launches, level_ms, final_parity);
+  return run_levels<BLOCK>(ctx, w, a, per_cu * ctx->num_cu, shmem, p.driver,
+                           std::max(p.graph_levels, 1), launches, level_ms, final_parity);
 }
 
 dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source, int32_t* dist,
