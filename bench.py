@@ -4,20 +4,23 @@ Headline (``value``): plain per-source SSSP on R-MAT scale 20 (1,048,576 nodes,
 edge factor 16, a/b/c/d = .57/.19/.19/.05, symmetrised, de-duplicated), 64
 sources from the largest WCC, run one source at a time through ``dawn_sssp``
 with device-resident output.  One step = the 64 sources.  GTEPS counts, per
-source, the out-degrees of every reached node (the SOVM cost E_wcc(s)), summed
-over sources, per second.
+source, the out-degrees of every reached node (the SOVM cost E_wcc(s) of
+Section 4), summed over sources, per second.
 
 Also reported on the same JSON line: the batched form (R-MAT scale 18, 4096
-sources in one ``dawn_mssp`` launch) and the same 4096 sources run plain, the
-roofline of the level-step kernel, and the CPU oracle timed on a bounded
-sample on the host cores.
+sources in one ``dawn_mssp`` launch) next to the same 4096 sources run plain,
+APSP over the largest WCC of R-MAT scale 14, the damaged 2048^2 grid under
+each level-loop driver, the serving loop (three resident graphs, Poisson
+arrivals, p50/p99 latency), the roofline of the level-step kernel, and the
+CPU oracle timed on the host cores.
 
-Inputs are seeded synthetic graphs (the paper's SuiteSparse/Gunrock graphs
-are not available here).
+Inputs are seeded synthetic graphs standing in for the paper's
+SuiteSparse/Gunrock graphs, which are not available here.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -30,6 +33,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# Knobs of the plain level loop on R-MAT 20, as chosen by dawn_autotune on
+# eight other sources of the same graph (bench.py --autotune re-tunes live).
+PLAIN_KNOBS = {"driver": 3, "graph_levels": 16, "big_degree": 128, "alpha": 60.0, "beta": 24.0,
+               "block": 1024, "blocks_per_cu": 0, "pull_lane_edges": 32}
+
+# Sources that define the level-step kernel: the HBM counter record under
+# profiles/ holds their digest and is used only while it matches.
+KERNEL_SOURCES = ["paper_2208_04514_amd/csrc/sssp.hip", "paper_2208_04514_amd/csrc/device_util.hpp",
+                  "paper_2208_04514_amd/csrc/internal.hpp", "paper_2208_04514_amd/build.py"]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sssp_level_rmat20_hbm_counters.md")
 
 
 def _log(*a):
@@ -47,6 +61,26 @@ def cpu_model() -> str:
     return platform.processor()
 
 
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record():
+    """The committed FETCH_SIZE/WRITE_SIZE record of the level kernel, or None."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            for line in f:
+                if line.startswith("traffic-record:"):
+                    return json.loads(line.split(":", 1)[1])
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def plain_alg_bytes(g, dist_rows, levels) -> float:
     """Bytes the push-only level loop must move per the method (all sources summed).
 
@@ -62,36 +96,37 @@ def plain_alg_bytes(g, dist_rows, levels) -> float:
     return total
 
 
-def run_plain(D, ctx, h, g, src, out, steps, warmup):
+def run_plain(D, ctx, h, src, out, steps, warmup):
+    """Time `steps` passes over the sources; returns (source edges, seconds,
+    summed kernel ms, levels of the last pass, per-call wall ms)."""
+    import torch
     for _ in range(warmup):
         for i, s in enumerate(src):
             D.dawn_sssp(ctx, h, int(s), out=out[i])
-    import torch
     torch.cuda.synchronize()
-    se = 0
-    ks = 0.0
-    levels = []
+    se, ks, levels, calls = 0, 0.0, [], []
     t0 = time.perf_counter()
     for _ in range(steps):
+        levels = []
         for i, s in enumerate(src):
+            c0 = time.perf_counter()
             _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
+            calls.append((time.perf_counter() - c0) * 1e3)
             se += st["source_edges"]
             ks += st["kernel_ms"]
             levels.append(st["levels"])
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return se, dt, ks, levels
+    return se, time.perf_counter() - t0, ks, levels, np.array(calls)
 
 
 def level_kernel_timing(D, ctx, h, src, out):
     """Per-launch time of the level-step kernel, measured with HIP events that
-    bracket each launch on the stream it runs on (library timing mode 1).
+    bracket each launch on the stream it runs on (library timing mode 1, which
+    issues the same level launches one per host check).
     Returns (total ms, launches, levels per source)."""
     p = D.dawn_get_params(ctx, h)
     D.dawn_set_params(ctx, h, driver=2, timing=1)
-    ms = 0.0
-    launches = 0
-    levels = []
+    ms, launches, levels = 0.0, 0, []
     try:
         for i, s in enumerate(src):
             _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
@@ -101,6 +136,29 @@ def level_kernel_timing(D, ctx, h, src, out):
     finally:
         D.dawn_set_params(ctx, h, **p)
     return ms, launches, levels
+
+
+def roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs):
+    alg = plain_alg_bytes(g, dist_rows, lk_levels)
+    achieved = alg / (lk_ms / 1e3) / 1e9
+    rec = traffic_record()
+    traffic, note = None, "no counter record"
+    if rec is not None:
+        if rec.get("digest") != kernel_digest():
+            note = "level kernel changed since the counters were taken"
+        elif rec.get("params") != knobs:
+            note = "knobs differ from the counter run"
+        else:
+            traffic = rec["bytes_per_launch"]
+            note = rec.get("source", "")
+    return {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+        "kernel": "sssp_level", "launches": lk_launches,
+        "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
+        "alg_bytes_per_launch": round(alg / lk_launches, 1),
+        "traffic_note": note,
+    }
 
 
 def component_edge_sums(g):
@@ -114,6 +172,104 @@ def component_edge_sums(g):
     _, lab = connected_components(a, directed=True, connection="weak")
     sums = np.bincount(lab, weights=g.out_degree().astype(np.float64))
     return sums[lab].astype(np.int64)
+
+
+def batched_bench(D, ctx):
+    """R-MAT 18, 4096 sources in one dawn_mssp launch, and the same sources
+    one at a time through dawn_sssp."""
+    import torch
+    import graphgen as gg
+    g, src = gg.load_config("rmat18")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
+    t0 = time.perf_counter()
+    tuned = D.dawn_autotune(ctx, h, gg.sample_sources(g.meta["wcc_nodes"], 4096, 9002), what=3)
+    tune_s = time.perf_counter() - t0
+    D.dawn_mssp(ctx, h, src, out=out)
+    torch.cuda.synchronize()
+    times, st_b = [], None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, st_b = D.dawn_mssp(ctx, h, src, out=out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    tb = float(np.median(times))
+    del out
+    row = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    t0 = time.perf_counter()
+    sep = 0
+    for s in src:
+        _, st = D.dawn_sssp(ctx, h, int(s), out=row)
+        sep += st["source_edges"]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    D.dawn_graph_release(ctx, h)
+    return {
+        "workload": "rmat18_ef16_sym_4096src_one_launch", "n": g.n, "m": g.m,
+        "gteps": round(st_b["source_edges"] / tb / 1e9, 2),
+        "gteps_device": round(st_b["source_edges"] / st_b["kernel_ms"] / 1e6, 2),
+        "ms": round(tb * 1e3, 3), "kernel_ms": round(st_b["kernel_ms"], 3),
+        "levels": st_b["levels"], "push_levels": st_b["push_levels"],
+        "pull_levels": st_b["pull_levels"],
+        "plain_same_sources_gteps": round(sep / tp / 1e9, 2),
+        "plain_same_sources_ms": round(tp * 1e3, 1),
+        "speedup_vs_plain": round(tp / tb, 2),
+        "tuned": {k: tuned[k] for k in ("driver", "big_degree", "alpha", "beta", "block",
+                                        "batch_alpha")},
+        "autotune_s": round(tune_s, 2),
+    }
+
+
+def apsp_bench(D, ctx):
+    """APSP over the largest WCC of R-MAT 14 (dawn_apsp_wcc, device output)."""
+    import torch
+    import graphgen as gg
+    g, _ = gg.load_config("rmat14")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    nodes, _, _ = D.dawn_apsp_wcc(ctx, h, query_only=True)
+    s = nodes.size
+    out = torch.empty((s, s), dtype=torch.int32, device="cuda")
+    D.dawn_apsp_wcc(ctx, h, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st = D.dawn_apsp_wcc(ctx, h, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    D.dawn_graph_release(ctx, h)
+    return {"workload": "rmat14_ef16_sym_apsp_largest_wcc", "s_wcc": int(s),
+            "ms": round(t * 1e3, 3), "kernel_ms": round(st["kernel_ms"], 3),
+            "gteps": round(st["source_edges"] / t / 1e9, 2), "levels": st["levels"]}
+
+
+def grid_bench(D, ctx, k_src=4):
+    """The damaged 2048^2 grid (about 120 levels) under each level-loop
+    driver, and the no-shortcut grid (thousands of levels) under two."""
+    import torch
+    import graphgen as gg
+    res = {}
+    for name, drivers, ks in (("grid2048", (1, 2, 3, 4), k_src), ("grid2048ns", (1, 3), 1)):
+        g, src = gg.load_config(name)
+        h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        entry = {}
+        for drv in drivers:
+            D.dawn_set_params(ctx, h, driver=drv, graph_levels=32, blocks_per_cu=1)
+            D.dawn_sssp(ctx, h, int(src[0]), out=out)
+            t0 = time.perf_counter()
+            se, lv = 0, []
+            for s in src[:ks]:
+                _, st = D.dawn_sssp(ctx, h, int(s), out=out)
+                se += st["source_edges"]
+                lv.append(st["levels"])
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            entry[f"driver{drv}"] = {"ms_per_source": round(t / ks * 1e3, 3),
+                                     "gteps": round(se / t / 1e9, 3),
+                                     "us_per_level": round(t / sum(lv) * 1e6, 2),
+                                     "levels": lv}
+        res[name] = entry
+        D.dawn_graph_release(ctx, h)
+    return res
 
 
 def serve_run(D, ctx, graphs, queries, arrivals=None, window=48):
@@ -192,19 +348,40 @@ def serving_bench(D, ctx, nq=200, seed=105):
     return res
 
 
+def cpu_baseline(g, src, dist_rows):
+    """The CPU oracle on the host cores: one thread, then one source per thread."""
+    import oracle
+    import graphgen as gg
+    t0 = time.perf_counter()
+    ref = oracle.mssp(g, src, threads=1)
+    tc = time.perf_counter() - t0
+    se = gg.reach_edges_from_dist(g, ref)
+    cores = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    oracle.mssp(g, src, threads=cores)
+    tm = time.perf_counter() - t0
+    base = {"value": round(se / tc / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"rmat20, the {src.size} timed sources, FIFO-queue BFS one source at a "
+                      f"time, {tc:.1f} s",
+            "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
+    par = {"value": round(se / tm / 1e9, 4), "unit": "GTEPS", "cores": cores, "kind": "oracle",
+           "sample": f"same sources, one source per thread, {tm:.1f} s"}
+    return base, par, bool(np.array_equal(ref, dist_rows[: src.size]))
+
+
 def roofline_only(D, ctx, params_json):
-    """The level-kernel measurement alone (for profiling), with fixed knobs,
-    then a 256 MiB device copy whose counters calibrate FETCH/WRITE_SIZE."""
+    """The level-kernel measurement alone (for profiling), then a 1 GiB device
+    copy whose counters calibrate FETCH_SIZE and WRITE_SIZE."""
     import torch
     import graphgen as gg
     g, src = gg.load_config("rmat20")
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
-    p = json.loads(params_json) if params_json else {}
-    if p:
-        D.dawn_set_params(ctx, h, **p)
+    p = json.loads(params_json) if params_json else dict(PLAIN_KNOBS)
+    D.dawn_set_params(ctx, h, **p)
     lk_ms, lk_launches, levels = level_kernel_timing(D, ctx, h, src, out)
-    alg = plain_alg_bytes(g, out.cpu().numpy(), levels)
+    torch.cuda.synchronize()
+    roof = roofline_entry(g, out.cpu().numpy(), lk_ms, lk_launches, levels, p)
     # counter calibration: 1 GiB written, then copied (read 1 GiB, write 1 GiB);
     # the source is 4x the 256 MiB memory-side cache, so the copy reads HBM
     a = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
@@ -212,13 +389,9 @@ def roofline_only(D, ctx, params_json):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    achieved = alg / (lk_ms / 1e3) / 1e9
-    print(json.dumps({"kernel": "sssp_level", "launches": lk_launches,
-                      "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
-                      "alg_bytes_per_launch": round(alg / lk_launches, 1),
-                      "achieved_gbs": round(achieved, 2), "frac": round(achieved / HBM_PEAK_GBS, 5),
+    print(json.dumps({"roofline": roof, "digest": kernel_digest(), "params": p,
                       "calibration_copy_read_bytes": a.numel() * 4,
-                      "calibration_copy_write_bytes": b.numel() * 4, "params": p}), flush=True)
+                      "calibration_copy_write_bytes": b.numel() * 4}), flush=True)
 
 
 def main():
@@ -227,13 +400,19 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the APSP and grid sections")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--cpu-sources", type=int, default=64)
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-tune the plain knobs live instead of the committed ones")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the level-kernel timing pass (for rocprofv3)")
     ap.add_argument("--params", default="", help="JSON knobs for --roofline-only")
+    ap.add_argument("--digest", action="store_true", help="print the level kernel's source digest")
     args = ap.parse_args()
+    if args.digest:
+        print(kernel_digest())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the method shards over sources (no collectives), "
               "and this build runs and reports the single-GPU path only; use --gpus 1.",
@@ -249,90 +428,52 @@ def main():
         roofline_only(D, ctx, args.params)
         return
 
-    _log("[bench] generating R-MAT 20")
+    _log("[bench] R-MAT 20")
     g, src = gg.load_config("rmat20")
     ctx = D.dawn_create(0, 0)
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
 
-    # setup (outside the timed region): tune the knobs on 8 other sources
-    _log("[bench] autotune")
-    tune_src = gg.sample_sources(g.meta["wcc_nodes"], 8, 9001)
-    t0 = time.perf_counter()
-    tuned = D.dawn_autotune(ctx, h, tune_src, what=1)
-    tune_s = time.perf_counter() - t0
+    knobs, tune_s = dict(PLAIN_KNOBS), 0.0
+    if args.autotune:
+        _log("[bench] autotune")
+        t0 = time.perf_counter()
+        tuned = D.dawn_autotune(ctx, h, gg.sample_sources(g.meta["wcc_nodes"], 8, 9001), what=1)
+        tune_s = time.perf_counter() - t0
+        knobs = {k: tuned[k] for k in PLAIN_KNOBS}
+    D.dawn_set_params(ctx, h, **knobs)
 
     _log("[bench] plain SSSP timed region")
-    se, dt, ks, levels = run_plain(D, ctx, h, g, src, out, args.steps, args.warmup)
+    se, dt, ks, levels, calls = run_plain(D, ctx, h, src, out, args.steps, args.warmup)
     value = se / dt / 1e9
     ms_per_step = dt / args.steps * 1e3
 
-    # roofline of the level-step kernel
+    _log("[bench] level kernel per-launch timing")
     lk_ms, lk_launches, lk_levels = level_kernel_timing(D, ctx, h, src, out)
+    torch.cuda.synchronize()
     dist_rows = out.cpu().numpy()
-    alg = plain_alg_bytes(g, dist_rows, lk_levels)
-    achieved = alg / (lk_ms / 1e3) / 1e9
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-        "kernel": "sssp_level", "launches": lk_launches,
-        "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
-        "alg_bytes_per_launch": round(alg / lk_launches, 1),
-    }
+    roofline = roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs)
+    D.dawn_graph_release(ctx, h)
 
     extra = {}
     if not args.no_batched:
         _log("[bench] batched R-MAT 18, 4096 sources")
-        g2, src2 = gg.load_config("rmat18")
-        h2 = D.dawn_graph_upload(ctx, g2.row_ptr, g2.col)
-        out2 = torch.empty((src2.size, g2.n), dtype=torch.int32, device="cuda")
-        tuned2 = D.dawn_autotune(ctx, h2, gg.sample_sources(g2.meta["wcc_nodes"], 4096, 9002), what=3)
-        D.dawn_mssp(ctx, h2, src2, out=out2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, stb = D.dawn_mssp(ctx, h2, src2, out=out2)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        del out2
-        # the same 4096 sources, one at a time through the plain path
-        row = torch.empty(g2.n, dtype=torch.int32, device="cuda")
-        t0 = time.perf_counter()
-        sep = 0
-        for s in src2:
-            _, st = D.dawn_sssp(ctx, h2, int(s), out=row)
-            sep += st["source_edges"]
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        extra["batched"] = {
-            "workload": "rmat18_ef16_sym_4096src_one_launch",
-            "gteps": round(stb["source_edges"] / tb / 1e9, 2),
-            "gteps_device": round(stb["source_edges"] / stb["kernel_ms"] / 1e6, 2),
-            "ms": round(tb * 1e3, 3), "levels": stb["levels"],
-            "plain_same_sources_gteps": round(sep / tp / 1e9, 2),
-            "plain_same_sources_ms": round(tp * 1e3, 1),
-            "tuned": {k: tuned2[k] for k in ("driver", "big_degree", "alpha", "beta", "block",
-                                              "batch_alpha")},
-        }
-        D.dawn_graph_release(ctx, h2)
-
+        extra["batched"] = batched_bench(D, ctx)
+    if not args.no_extra:
+        _log("[bench] APSP over the largest WCC of R-MAT 14")
+        extra["apsp"] = apsp_bench(D, ctx)
+        _log("[bench] grid 2048^2 level-loop drivers")
+        extra["grid"] = grid_bench(D, ctx)
     if not args.no_serve:
         _log("[bench] serving: R-MAT 16, R-MAT 20, grid 1024^2")
         extra["served"] = serving_bench(D, ctx)
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        k = min(args.cpu_sources, src.size)
-        _log(f"[bench] CPU oracle on {k} sources (single thread)")
-        t0 = time.perf_counter()
-        ref = oracle.mssp(g, src[:k], threads=1)
-        tc = time.perf_counter() - t0
-        se_cpu = gg.reach_edges_from_dist(g, ref)
-        cpu = {"value": round(se_cpu / tc / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"rmat20 {k} sources, FIFO-queue BFS one source at a time, {tc:.1f} s",
-               "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
-        # parity of the timed rows on the sample (bit-exact)
-        extra["parity_sample_bit_exact"] = bool(np.array_equal(ref, dist_rows[:k]))
+        _log(f"[bench] CPU oracle on {src.size} sources")
+        cpu, cpu_par, same = cpu_baseline(g, src, dist_rows)
+        extra["cpu_parallel"] = cpu_par
+        extra["parity_sample_bit_exact"] = same
 
     line = {
         "metric": "GTEPS (source-edge traversals/s), plain per-source SSSP",
@@ -342,9 +483,11 @@ def main():
         "config": {"workload": "rmat20_ef16_sym_64src_plain_sssp", "n": g.n, "m": g.m,
                    "sources": int(src.size), "source_edges_per_step": int(se // args.steps),
                    "gteps_device": round(se / ks / 1e6, 3),
-                   "tuned": {k: tuned[k] for k in ("driver", "graph_levels", "big_degree", "alpha",
-                                                    "beta", "block", "blocks_per_cu",
-                                                    "pull_lane_edges")},
+                   "gteps_graph500_halved": round(value / 2, 3),
+                   "ms_per_source_p50": round(float(np.percentile(calls, 50)), 4),
+                   "ms_per_source_p99": round(float(np.percentile(calls, 99)), 4),
+                   "levels": int(np.max(levels)), "knobs": knobs,
+                   "knobs_from": "autotune (live)" if args.autotune else "committed",
                    "autotune_s": round(tune_s, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
