@@ -64,16 +64,6 @@ __device__ __forceinline__ u64 shfl_xor64(u64 x, int m) {
   return ((u64)hi << 32) | lo;
 }
 
-// Append the out-edge chunks of big-degree node v to level L's chunk list.
-__device__ __forceinline__ void push_chunks(const BatchArgs& a, int L, int v, int deg) {
-  const unsigned nch = (unsigned)((deg + kChunkB - 1) / kChunkB);
-  const unsigned cb = atom_add(&a.ctrl->lv[L & 1].nchunks, nch);
-  for (unsigned k = 0; k < nch; ++k) {
-    a.cu[L & 1][cb + k] = v;
-    a.ck[L & 1][cb + k] = (int32_t)k;
-  }
-}
-
 // Append the out-edge chunks of node v (when big) to level L's chunk list,
 // one counter atomic per wave (wave-uniform call).
 __device__ __forceinline__ void push_chunks_wave(const BatchArgs& a, int L, int v, int deg,
@@ -103,6 +93,80 @@ __device__ __forceinline__ void block_add_edges(const BatchArgs& a, int L, u64 e
     u64 x = 0;
     for (int i = 0; i < kBatchBlock / kWave; ++i) x += part[i];
     if (x) atom_add(&a.ctrl->lv[L & 1].s[blockIdx.x % kStripes].edges, x);
+  }
+}
+
+// Big-degree nodes found by a workgroup are staged in LDS and their chunks
+// listed with one counter atomic per workgroup (the L2 performs atomics on
+// one line at a time, and a dense level has thousands of such nodes).
+constexpr int kChunkStage = 1024;
+
+struct ChunkStage {
+  int32_t v[kChunkStage];
+  int32_t c[kChunkStage];
+  unsigned n;
+};
+
+// Stage node v (when big) with its chunk count; past the stage's end the
+// wave lists its own (wave-uniform call).
+__device__ __forceinline__ void stage_chunks_wave(const BatchArgs& a, int L, ChunkStage& cs, int v,
+                                                  int deg, bool big) {
+  const int nch = big ? (deg + kChunkB - 1) / kChunkB : 0;
+  const u64 bm = __ballot(nch > 0);
+  if (!bm) return;
+  const int lead = __ffsll((unsigned long long)bm) - 1;
+  unsigned base = 0;
+  if (lane_id() == lead) base = atomicAdd(&cs.n, (unsigned)__popcll(bm));
+  base = (unsigned)__shfl((int)base, lead, kWave);
+  const unsigned slot = base + (unsigned)__popcll(bm & lanes_below());
+  const bool staged = nch > 0 && slot < (unsigned)kChunkStage;
+  if (staged) {
+    cs.v[slot] = v;
+    cs.c[slot] = nch;
+  }
+  push_chunks_wave(a, L, v, deg, nch > 0 && !staged);
+}
+
+// List the staged nodes' chunks (every thread of the workgroup calls it,
+// after a barrier that follows the last staging).
+__device__ __forceinline__ void flush_chunk_stage(const BatchArgs& a, int L, ChunkStage& cs) {
+  constexpr int PER = kChunkStage / kBatchBlock;
+  __shared__ int wtot[kBatchBlock / kWave];
+  __shared__ unsigned gbase;
+  const unsigned nst = min(cs.n, (unsigned)kChunkStage);
+  if (nst == 0) return;   // uniform
+  const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
+  int mine = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const unsigned i = (unsigned)(t * PER + q);
+    if (i < nst) mine += cs.c[i];
+  }
+  const int incl = wave_incl_scan(mine);
+  if (lane == kWave - 1) wtot[wv] = incl;
+  __syncthreads();
+  if (t == 0) {
+    unsigned tot = 0;
+    for (int i = 0; i < kBatchBlock / kWave; ++i) {
+      const unsigned x = (unsigned)wtot[i];
+      wtot[i] = (int)tot;
+      tot += x;
+    }
+    gbase = atom_add(&a.ctrl->lv[L & 1].nchunks, tot);
+  }
+  __syncthreads();
+  unsigned b = gbase + (unsigned)wtot[wv] + (unsigned)(incl - mine);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const unsigned i = (unsigned)(t * PER + q);
+    if (i < nst) {
+      const int v = cs.v[i], nch = cs.c[i];
+      for (int k = 0; k < nch; ++k) {
+        a.cu[L & 1][b + k] = v;
+        a.ck[L & 1][b + k] = (int32_t)k;
+      }
+      b += (unsigned)nch;
+    }
   }
 }
 
@@ -433,7 +497,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   __shared__ u64 actb[64];
   __shared__ int rank_j[kBatchBlock / kWave][kWave];
   __shared__ u64 red[4][kBatchBlock / kWave];
+  __shared__ ChunkStage cstage;
   const int tid = threadIdx.x;
+  if (tid == 0) cstage.n = 0;
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int W = a.W;
@@ -511,7 +577,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
       nodes += 1;
       mf += (u64)deg;
     }
-    push_chunks_wave(a, L, v0 + lane, deg, mine && deg >= kBigB);
+    stage_chunks_wave(a, L, cstage, v0 + lane, deg, mine && deg >= kBigB);
     __builtin_amdgcn_wave_barrier();
     for (int i0 = ib; i0 < ie; i0 += 4 * npw) {
       int jq[4], dq[4];
@@ -572,6 +638,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
     red[3][wv] = mf;
   }
   __syncthreads();
+  flush_chunk_stage(a, L, cstage);
   if (tid < W && actb[tid]) {
     u64* gp = &a.ctrl->laneact[cl][tid];
     if (actb[tid] & ~ld_relaxed(gp)) atom_or(gp, actb[tid]);
@@ -712,20 +779,28 @@ __global__ __launch_bounds__(kBatchBlock) void batch_zero(u64* p, size_t count) 
 // merge's part: the visited bit and the big-degree chunks.
 __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane, int k, int L,
                            int live) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    const int s = src[i];
-    const int l = lane[i];
-    const size_t idx = (size_t)s * a.W + (l >> 6);
-    const u64 bit = 1ull << (l & 63);
-    atom_or(&a.nxt[L & 1][idx], bit);
-    atom_or(&a.fmap[L & 1][s], 1ull << (l >> 6));
-    const u64 sbit = 1ull << (s & 63);
-    const u64 old = atom_or(&a.touched[L & 1][s >> 6], sbit);
-    if (live) {
-      atom_or(&a.vis[idx], bit);
-      const int deg = a.rp[s + 1] - a.rp[s];
-      if (!(old & sbit) && deg >= kBigB) push_chunks(a, L, s, deg);
+  // whole waves walk the sources so that chunk listing is wave-aggregated
+  const int stride = gridDim.x * blockDim.x;
+  for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); i0 < k; i0 += stride) {
+    const int i = i0 + lane_id();
+    int s = 0, deg = 0;
+    bool first = false;
+    if (i < k) {
+      s = src[i];
+      const int l = lane[i];
+      const size_t idx = (size_t)s * a.W + (l >> 6);
+      const u64 bit = 1ull << (l & 63);
+      atom_or(&a.nxt[L & 1][idx], bit);
+      atom_or(&a.fmap[L & 1][s], 1ull << (l >> 6));
+      const u64 sbit = 1ull << (s & 63);
+      const u64 old = atom_or(&a.touched[L & 1][s >> 6], sbit);
+      if (live) {
+        atom_or(&a.vis[idx], bit);
+        deg = a.rp[s + 1] - a.rp[s];
+        first = !(old & sbit);
+      }
     }
+    push_chunks_wave(a, L, s, deg, first && deg >= kBigB);
   }
 }
 
