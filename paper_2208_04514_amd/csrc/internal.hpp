@@ -202,6 +202,9 @@ struct GraphRec {
   size_t pc_cap = 0;
   int32_t max_out_deg = 0;
   int32_t zero_out = 0;
+  // level launches the recent traversals needed (the direct-launch driver
+  // queues about this many before its first host check)
+  std::atomic<int> launch_hint{0};
   size_t bytes = 0;
   dawn_params params{};
   std::mutex mu;                          // guards the pools and the WCC cache

@@ -751,9 +751,9 @@ static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStre
 }
 
 template <int BLOCK>
-static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, size_t shmem,
-                              int driver, int graph_levels, int* launches, double* level_ms,
-                              int* final_parity) {
+static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& a, int grid,
+                              size_t shmem, int driver, int graph_levels, int* launches,
+                              double* level_ms, int* final_parity) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
   const long long max_launch = (long long)a.n + 2;
   if (driver == 2) {
@@ -787,21 +787,34 @@ static dawn_status run_levels(Ctx* ctx, SsspWs* w, const SsspArgs& a, int grid, 
   }
   graph_levels += graph_levels & 1;
   if (driver == 3) {
-    // K level launches queued per host check of the final state
+    // K level launches queued per host check of the final state.  The first
+    // batch covers what the graph's recent traversals needed (one more than
+    // their level count, for the launch that sees the end), so a typical
+    // traversal costs one host check and few launches past its end; a
+    // launch after the end only carries the final state along.
     hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
     *launches = 1;
-    for (long long it = 0; it * graph_levels <= max_launch; ++it) {
-      for (int i = 0; i < graph_levels; ++i)
+    const int hint = g->launch_hint.load(std::memory_order_relaxed);
+    int batch = hint > 0 ? std::min(hint + 1, graph_levels * 4) : graph_levels;
+    batch += batch & 1;
+    long long queued = 0;
+    while (queued <= max_launch) {
+      for (int i = 0; i < batch; ++i)
         hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, a, i & 1);
       DAWN_HIP(hipGetLastError());
-      *launches += graph_levels;
+      *launches += batch;
+      queued += batch;
       DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[1], &w->ctrl->st[1], sizeof(LevelState),
                               hipMemcpyDeviceToHost, w->stream));
       DAWN_HIP(hipStreamSynchronize(w->stream));
       if (w->h_ctrl->st[1].done) {
+        // launches this traversal needed: levels 1 .. last_nonempty + 1, then the end
+        const int need = w->h_ctrl->st[1].last_nonempty + 2;
+        g->launch_hint.store(std::max(need, hint - 1), std::memory_order_relaxed);
         *final_parity = 1;
         return DAWN_OK;
       }
+      batch = graph_levels;
     }
     return fail(DAWN_E_DEVICE, "level loop did not terminate");
   }
@@ -868,7 +881,7 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
   int occ = 0;
   DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, shmem));
   int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
-  return run_levels<BLOCK>(ctx, w, a, per_cu * ctx->num_cu, shmem, p.driver,
+  return run_levels<BLOCK>(ctx, g, w, a, per_cu * ctx->num_cu, shmem, p.driver,
                            std::max(p.graph_levels, 1), launches, level_ms, final_parity);
 }
 
