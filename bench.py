@@ -278,7 +278,7 @@ def serve_run(D, ctx, graphs, queries, arrivals=None, window=48):
     import torch
     t0 = time.perf_counter()
     inflight = {}
-    lat, se, ks = [], 0, 0
+    lat, gis, se, ks = [], [], 0, 0
     i = 0
     while i < len(queries) or inflight:
         now = time.perf_counter() - t0
@@ -289,21 +289,29 @@ def serve_run(D, ctx, graphs, queries, arrivals=None, window=48):
             h, g, esum = graphs[gi]
             out = torch.empty((srcs.size, g.n), dtype=torch.int32, device="cuda")
             t = D.dawn_serve_submit(ctx, h, srcs, out)
-            inflight[t] = (out, int(esum[srcs].sum()), srcs.size)
+            inflight[t] = (out, int(esum[srcs].sum()), srcs.size, gi)
             i += 1
         progressed = False
         for t in list(inflight):
             st, q = D.dawn_serve_poll(ctx, t)
             if st == D.DAWN_OK:
-                out, e, k = inflight.pop(t)
+                out, e, k, gi = inflight.pop(t)
                 lat.append((q["done_ns"] - q["submit_ns"]) / 1e6)
+                gis.append(gi)
                 se += e
                 ks += k
                 progressed = True
         if not progressed:
             time.sleep(0.0002)
     dt = time.perf_counter() - t0
-    return dt, np.array(lat), se, ks
+    return dt, np.array(lat), se, ks, np.array(gis)
+
+
+def _per_graph(names, lat, gis):
+    return {name: {"queries": int((gis == i).sum()),
+                   "p50_ms": round(float(np.percentile(lat[gis == i], 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat[gis == i], 99)), 3)}
+            for i, name in enumerate(names) if (gis == i).any()}
 
 
 def serving_bench(D, ctx, nq=200, seed=105):
@@ -312,7 +320,8 @@ def serving_bench(D, ctx, nq=200, seed=105):
     and 0.9 of the saturated query rate."""
     import graphgen as gg
     graphs = []
-    for name in ("rmat16", "rmat20", "grid1024"):
+    names = ("rmat16", "rmat20", "grid1024")
+    for name in names:
         g, _ = gg.load_config(name)
         h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
         graphs.append((h, g, component_edge_sums(g)))
@@ -326,21 +335,23 @@ def serving_bench(D, ctx, nq=200, seed=105):
         queries.append((gi, rng.choice(pool, size=k, replace=False).astype(np.int32)))
     warm = queries[:20]
     serve_run(D, ctx, graphs, warm)
-    dt, lat, se, ks = serve_run(D, ctx, graphs, queries)
+    dt, lat, se, ks, gis = serve_run(D, ctx, graphs, queries)
     cap_qps = len(queries) / dt
-    res = {"graphs": ["rmat16", "rmat20", "grid1024"], "queries": nq,
+    res = {"graphs": list(names), "queries": nq,
            "mean_k": round(float(np.mean([q[1].size for q in queries])), 1),
            "saturated": {"qps": round(cap_qps, 1), "sources_per_s": round(ks / dt, 1),
                          "gteps": round(se / dt / 1e9, 2),
                          "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)), 3)}}
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "per_graph": _per_graph(names, lat, gis)}}
     for frac in (0.5, 0.9):
         lam = frac * cap_qps
         arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
-        dt, lat, se, ks = serve_run(D, ctx, graphs, queries, arrivals=arr)
+        dt, lat, se, ks, gis = serve_run(D, ctx, graphs, queries, arrivals=arr)
         res[f"load_{frac}"] = {"offered_qps": round(lam, 1), "gteps": round(se / dt / 1e9, 2),
                                "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                               "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+                               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                               "per_graph": _per_graph(names, lat, gis)}
     used, budget = D.dawn_memory(ctx)
     res["hbm_used_gb"] = round(used / 1e9, 2)
     for h, _, _ in graphs:

@@ -99,7 +99,8 @@ typedef struct dawn_params {
   float beta;                 /* switch pull -> push when frontier nodes < n / beta */
   int32_t graph_levels;       /* drivers 3, 4: level launches per host read-back (rounded up to even) */
   int32_t small_n;            /* graphs with n <= small_n run as one workgroup per source */
-  float batch_alpha;          /* batched: push when frontier edges * alpha < unsaturated in-edges */
+  float batch_alpha;          /* batched: pull when (sum over frontier nodes of out-degree x
+                                 nonzero 64-lane words) * batch_alpha >= n x words, else push */
   int32_t batch_lanes;        /* batched: sources per launch (64..4096, multiple of 64) */
   int32_t timing;             /* 1: kernel_ms/launches of dawn_sssp cover only the level-step
                                  kernels, each bracketed by HIP events (driver 2 only);

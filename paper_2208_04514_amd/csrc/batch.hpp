@@ -15,6 +15,7 @@ struct alignas(kLine) BatchStripe {
   u64 se;                       // sum over new pairs of the node's out-degree
   u64 mf;                       // sum of out-degrees of the nodes with a new bit
   u64 edges;                    // adjacency entries read by the expansion
+  u64 mfw;                      // sum over nodes with a new bit of out-degree x nonzero words
 };
 
 // Counters of one level of a batch (two slots, indexed level & 1), striped
@@ -25,18 +26,28 @@ struct BatchLevel {
 };
 
 struct BatchLevelSum {
-  u64 nodes, bits, se, mf, edges;
+  u64 nodes, bits, se, mf, edges, mfw;
   unsigned nchunks;
 };
 
 struct BatchCtrl {
   BatchLevel lv[2];
-  u64 laneact[2][64];           // OR of the new bits of each word, per level
+  // OR of the new bits of each word, per level parity, striped like the
+  // counters (a workgroup ORs into stripe blockIdx % kStripes)
+  u64 laneact[2][kStripes][64];
 };
+
+// Lanes of word w that found new bits at a level of parity `par`.
+inline u64 lane_activity(const BatchCtrl& c, int par, int w) {
+  u64 x = 0;
+  for (int i = 0; i < kStripes; ++i) x |= c.laneact[par][i][w];
+  return x;
+}
 
 struct BatchArgs {
   int32_t n;
-  int32_t W;                    // 64-bit words per node row (sources / 64, rounded up)
+  int32_t W;                    // 64-bit words processed per node (lanes in use / 64, rounded up)
+  int32_t Ws;                   // row stride in words (>= W)
   long long m;
   const int32_t* rp;
   const int32_t* col;
@@ -90,6 +101,7 @@ struct BatchWs {
   int32_t* stage = nullptr;     // device rows for host-destination calls
   size_t stage_ints = 0;
   BatchCtrl* h_ctrl = nullptr;
+  u64* h_act = nullptr;         // pinned [64]: active lanes for the next level
 };
 
 struct BatchTotals {
@@ -101,7 +113,9 @@ struct BatchTotals {
 dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage_ints,
                             BatchWs** out);
 dawn_status batch_ensure_planes(BatchWs* w, int need, int W);
-BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W);
+// Ws = row stride (the batch's width); W = words the kernels process (<= Ws;
+// 0 = Ws).
+BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W = 0);
 BatchLevelSum batch_level_sum(const BatchLevel& l);
 dawn_status batch_launch_expand(Ctx* ctx, const BatchArgs& a, bool pull, int L, hipStream_t s);
 dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t s);
@@ -110,6 +124,6 @@ dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, co
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
 dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src,
                               const int32_t* d_lane, int k, int L, bool live, hipStream_t s);
-bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, long long m);
+bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, int n, int W);
 
 }  // namespace dawn

@@ -199,7 +199,7 @@ __device__ __forceinline__ u64 group_read64(u64 x, int gb, int i) {
 template <int P>
 __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, const u64* fm, int s,
                                          int e, u64 need, int w, int gb, u64 gm, u64& acc) {
-  const size_t W = (size_t)a.W;
+  const size_t W = (size_t)a.Ws;
   int j = s;
   while (j < e) {
     int my_u = 0;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   const u64 gm = group_mask<P>(lane);
   const int gb = P == 64 ? 0 : (lane & ~(P - 1));
   const u64 actw = wok ? a.act[w] : 0ull;
-  const size_t W = (size_t)a.W;
+  const size_t W = (size_t)a.Ws;
   const u64* front = a.nxt[(L - 1) & 1];
   const u64* fm = a.fmap[(L - 1) & 1];
   u64* nxt = a.nxt[L & 1];
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
 template <int P>
 __device__ __forceinline__ void relax4(const BatchArgs& a, u64* out, u64* T, const int* v,
                                        const u64* f, int w, u64 gm) {
-  const size_t W = (size_t)a.W;
+  const size_t W = (size_t)a.Ws;
   u64 b[4], o[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) b[q] = f[q] ? f[q] & ~a.vis[(size_t)v[q] * W + w] : 0ull;
@@ -339,7 +339,7 @@ constexpr int kSparseWords = 4;
 // (per lane; at most kSparseWords words).
 __device__ __forceinline__ void relax_edge_sparse(const BatchArgs& a, const u64* front, u64* out,
                                                   u64* T, int u, int v, u64 fmu) {
-  const size_t W = (size_t)a.W;
+  const size_t W = (size_t)a.Ws;
   int wk[kSparseWords];
   u64 f[kSparseWords], b[kSparseWords], o[kSparseWords];
 #pragma unroll
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
   const int sub = lane / P;
   const bool wok = w < a.W;
   const u64 gm = group_mask<P>(lane);
-  const size_t W = (size_t)a.W;
+  const size_t W = (size_t)a.Ws;
   const int pl = (L - 1) & 1;
   const u64* F = a.touched[pl];
   const u64* front = a.nxt[pl];
@@ -496,13 +496,14 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   __shared__ u64 lmask[kMaxPlanes][64];   // bit b of (L - base) for the lanes of each word
   __shared__ u64 actb[64];
   __shared__ int rank_j[kBatchBlock / kWave][kWave];
-  __shared__ u64 red[4][kBatchBlock / kWave];
+  __shared__ u64 red[5][kBatchBlock / kWave];
   __shared__ ChunkStage cstage;
   const int tid = threadIdx.x;
   if (tid == 0) cstage.n = 0;
   const int lane = lane_id();
   const int wv = tid / kWave;
-  const int W = a.W;
+  const int W = a.W;                  // words processed
+  const size_t Ws = (size_t)a.Ws;     // row stride
   const int D = a.nplanes;
   // one word per wave: lane r holds source (64 x + r)'s relative level, and a
   // ballot per plane gives that plane's mask
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
         const int i = i0 + sub;
         if (i < cnt && wok) {
           const int v = (int)t * 64 + rank_j[wv][i];
-          prev[(size_t)v * W + w] = 0;
+          prev[(size_t)v * Ws + w] = 0;
           if (w == 0) pmap[v] = 0;
         }
       }
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   u64* nxt = a.nxt[cl];
   u64* fmap = a.fmap[cl];
   const u64* T = a.touched[cl];
-  u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0;
+  u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0, mfw = 0;
   // a work unit is a quarter of a frontier word (ranks 16 s .. 16 s + 15 of
   // its set bits), so that dense words spread over four waves; within a unit
   // four nodes' rows are loaded before any of them is written back
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
     for (int i0 = ib; i0 < ie; i0 += 4 * npw) {
       int jq[4], dq[4];
       bool okq[4];
-      u64 nb[4], vo[4];
+      u64 nb[4];
       size_t idx[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -590,31 +591,33 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
         okq[q] = i < ie;
         jq[q] = rank_j[wv][okq[q] ? i : ib];
         dq[q] = __shfl(deg, jq[q], kWave);
-        idx[q] = (size_t)(v0 + jq[q]) * W + w;
+        idx[q] = (size_t)(v0 + jq[q]) * Ws + w;
         nb[q] = (okq[q] && wok) ? nxt[idx[q]] : 0ull;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         // the group's nonzero words of the node: its frontier word map
         const u64 nzb = __ballot(nb[q] != 0);
-        if (okq[q] && w == 0) fmap[v0 + jq[q]] = (nzb >> ((sub * P) & 63)) & low_mask<P>();
-        vo[q] = nb[q] ? a.vis[idx[q]] : 0ull;
+        const u64 fm = (nzb >> ((sub * P) & 63)) & low_mask<P>();
+        if (okq[q] && w == 0) {
+          fmap[v0 + jq[q]] = fm;
+          mfw += (u64)__popcll(fm) * (u64)dq[q];
+        }
       }
+      // vis and the planes take their bits with atomic ORs that return
+      // nothing: no (node, word) is touched twice in a level, and the wave
+      // never waits for a read-modify-write round trip per plane
       for (int b = 0; b < D; ++b) {
-        u64 mq[4], pv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          mq[q] = lmask[b][w] & nb[q];
-          pv[q] = mq[q] ? a.planes[b][idx[q]] : 0ull;
+          const u64 mq = lmask[b][w] & nb[q];
+          if (mq) atom_or(&a.planes[b][idx[q]], mq);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (mq[q]) a.planes[b][idx[q]] = pv[q] | mq[q];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (nb[q]) {
-          a.vis[idx[q]] = vo[q] | nb[q];
+          atom_or(&a.vis[idx[q]], nb[q]);
           const u64 pc = (u64)__popcll(nb[q]);
           bits += pc;
           se += pc * (u64)dq[q];
@@ -631,24 +634,27 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   se = wave_sum(se);
   nodes = wave_sum(nodes);
   mf = wave_sum(mf);
+  mfw = wave_sum(mfw);
   if (lane == 0) {
     red[0][wv] = bits;
     red[1][wv] = se;
     red[2][wv] = nodes;
     red[3][wv] = mf;
+    red[4][wv] = mfw;
   }
   __syncthreads();
   flush_chunk_stage(a, L, cstage);
   if (tid < W && actb[tid]) {
-    u64* gp = &a.ctrl->laneact[cl][tid];
+    u64* gp = &a.ctrl->laneact[cl][stripe][tid];
     if (actb[tid] & ~ld_relaxed(gp)) atom_or(gp, actb[tid]);
   }
-  if (tid < 4) {
+  if (tid < 5) {
     u64 x = 0;
     for (int i = 0; i < kBatchBlock / kWave; ++i) x += red[tid][i];
     if (x) {
       BatchStripe& st = lv->s[stripe];
-      u64* dst = tid == 0 ? &st.bits : tid == 1 ? &st.se : tid == 2 ? &st.nodes : &st.mf;
+      u64* dst = tid == 0 ? &st.bits : tid == 1 ? &st.se : tid == 2 ? &st.nodes
+               : tid == 3 ? &st.mf : &st.mfw;
       atom_add(dst, x);
     }
   }
@@ -677,6 +683,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, co
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int W = a.W;
+  const size_t Ws = (size_t)a.Ws;
   const int ntiles = (a.n + kEmitTile - 1) / kEmitTile;
   // sources b with b % 4 == wv belong to wave wv
   const u64 wave_bits = 0x1111111111111111ull << wv;
@@ -696,7 +703,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, co
 #pragma unroll
         for (int d = 0; d < DMAX; ++d) pv[d] = 0;
         if (j < nv) {
-          const size_t idx = (size_t)(v0 + j) * W + wc0 + wl;
+          const size_t idx = (size_t)(v0 + j) * Ws + wc0 + wl;
           const u64 em = emask[wc0 + wl];
           x = a.vis[idx];
 #pragma unroll
@@ -788,7 +795,7 @@ __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane,
     if (i < k) {
       s = src[i];
       const int l = lane[i];
-      const size_t idx = (size_t)s * a.W + (l >> 6);
+      const size_t idx = (size_t)s * a.Ws + (l >> 6);
       const u64 bit = 1ull << (l & 63);
       atom_or(&a.nxt[L & 1][idx], bit);
       atom_or(&a.fmap[L & 1][s], 1ull << (l >> 6));
@@ -829,6 +836,7 @@ void batch_ws_destroy(BatchWs* w) {
   if (ctx) ctx->used -= w->bytes;
   if (ctx && w->plane_reserve) dev_unreserve(ctx, w->plane_reserve);
   if (w->h_ctrl) hipHostFree(w->h_ctrl);
+  if (w->h_act) hipHostFree(w->h_act);
   if (w->ev0) hipEventDestroy(w->ev0);
   if (w->ev1) hipEventDestroy(w->ev1);
   if (w->stream && w->own_stream) hipStreamDestroy(w->stream);
@@ -877,6 +885,7 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
     return s;
   }
   hipError_t e = hipHostMalloc((void**)&w->h_ctrl, sizeof(BatchCtrl), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&w->h_act, 64 * 8, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
   w->own_stream = true;
   if (e == hipSuccess) e = hipEventCreate(&w->ev0);
@@ -907,11 +916,12 @@ dawn_status batch_ensure_planes(BatchWs* w, int need, int W) {
   return DAWN_OK;
 }
 
-BatchArgs batch_args(const GraphRec* g, BatchWs* w, int W) {
+BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W) {
   BatchArgs a;
   memset(&a, 0, sizeof(a));
   a.n = g->n;
-  a.W = W;
+  a.Ws = Ws;
+  a.W = W > 0 ? std::min(W, Ws) : Ws;
   a.m = g->m;
   a.rp = g->rp;
   a.col = g->col;
@@ -947,6 +957,7 @@ BatchLevelSum batch_level_sum(const BatchLevel& l) {
     s.se += l.s[i].se;
     s.mf += l.s[i].mf;
     s.edges += l.s[i].edges;
+    s.mfw += l.s[i].mfw;
   }
   s.nchunks = l.nchunks;
   return s;
@@ -1039,10 +1050,12 @@ dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src
 }
 
 // Choose push or pull for the next level from the counters of the last one.
-bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, long long m) {
+// A push touches, per frontier node, its out-edges times its nonzero words;
+// a pull reads every node's W visited words (and scans in-lists).
+bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, int n, int W) {
   if (p.direction == 1) return false;
   if (p.direction == 2) return true;
-  return (double)last.mf * (double)p.batch_alpha >= (double)m;
+  return (double)last.mfw * (double)p.batch_alpha >= (double)n * (double)W;
 }
 
 static int bit_length(int x) {
@@ -1100,7 +1113,10 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
     tot->source_edges += prev.se;
     if (prev.bits) last_nonempty = L - 1;
     bool any = false;
-    for (int i = 0; i < W; ++i) any |= w->h_ctrl->laneact[pl][i] != 0;
+    for (int i = 0; i < W; ++i) {
+      w->h_act[i] = lane_activity(*w->h_ctrl, pl, i);
+      any |= w->h_act[i] != 0;
+    }
     if (!any) break;
     if (L > g->n + 1) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
     const int need = bit_length(L);
@@ -1110,10 +1126,10 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
     }
     w->planes_dirty = std::max(w->planes_dirty, need);
     // active lanes and a clean slot for this level
-    DAWN_HIP(hipMemcpyAsync(w->act, w->h_ctrl->laneact[pl], (size_t)W * 8, hipMemcpyHostToDevice, s));
+    DAWN_HIP(hipMemcpyAsync(w->act, w->h_act, (size_t)W * 8, hipMemcpyHostToDevice, s));
     DAWN_HIP(hipMemsetAsync(&w->ctrl->lv[L & 1], 0, sizeof(BatchLevel), s));
-    DAWN_HIP(hipMemsetAsync(&w->ctrl->laneact[L & 1][0], 0, 64 * 8, s));
-    const bool pull = batch_choose_pull(p, prev, g->m);
+    DAWN_HIP(hipMemsetAsync(&w->ctrl->laneact[L & 1], 0, sizeof(w->ctrl->laneact[0]), s));
+    const bool pull = batch_choose_pull(p, prev, g->n, W);
     DAWN_TRY(batch_launch_expand(ctx, a, pull, L, s));
     DAWN_TRY(batch_launch_merge(ctx, a, L, s));
     launches += 2;

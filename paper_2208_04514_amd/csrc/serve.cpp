@@ -272,7 +272,15 @@ static dawn_status launch_level(Server* S, Engine* e) {
   hipStream_t s = w->stream;
   const GraphRec* g = e->g.get();
   const int L = e->L;
-  BatchArgs a = batch_args(g, w, e->W);
+  // the kernels walk only the words up to the highest busy lane (admission
+  // fills the lowest free lanes first)
+  int Wa = 1;
+  for (int i = e->W - 1; i >= 0; --i)
+    if (e->busy[i]) {
+      Wa = i + 1;
+      break;
+    }
+  BatchArgs a = batch_args(g, w, e->W, Wa);
   if (e->nseed > 0) {
     const int k = e->nseed;
     DAWN_HIP(hipMemcpyAsync(w->src, e->h_src, (size_t)k * 4, hipMemcpyHostToDevice, s));
@@ -287,18 +295,18 @@ static dawn_status launch_level(Server* S, Engine* e) {
   const int need = bit_length(L + 1 - min_base);
   if (need > w->nplanes) {
     DAWN_TRY(batch_ensure_planes(w, need, e->W));
-    a = batch_args(g, w, e->W);
+    a = batch_args(g, w, e->W, Wa);
   }
   for (int i = 0; i < e->W; ++i) e->h_act[i] = e->act[i];
   DAWN_HIP(hipMemcpyAsync(w->act, e->h_act, (size_t)e->W * 8, hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemsetAsync(&w->ctrl->lv[(L + 1) & 1], 0, sizeof(BatchLevel), s));
-  DAWN_HIP(hipMemsetAsync(&w->ctrl->laneact[(L + 1) & 1][0], 0, 64 * 8, s));
+  DAWN_HIP(hipMemsetAsync(&w->ctrl->laneact[(L + 1) & 1], 0, sizeof(w->ctrl->laneact[0]), s));
   dawn_params p;
   {
     std::lock_guard<std::mutex> lk(e->g->mu);
     p = e->g->params;
   }
-  const bool pull = e->have_last ? batch_choose_pull(p, e->last, g->m) : false;
+  const bool pull = e->have_last ? batch_choose_pull(p, e->last, g->n, Wa) : false;
   DAWN_TRY(batch_launch_expand(S->ctx, a, pull, L + 1, s));
   DAWN_TRY(batch_launch_merge(S->ctx, a, L + 1, s));
   DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, s));
@@ -316,7 +324,7 @@ static dawn_status level_done(Server* S, Engine* e) {
   e->have_last = true;
   std::vector<Query*> done;
   for (int wd = 0; wd < e->W; ++wd) {
-    const u64 still = w->h_ctrl->laneact[L & 1][wd];
+    const u64 still = lane_activity(*w->h_ctrl, L & 1, wd);
     u64 fin = e->busy[wd] & e->act[wd] & ~still;
     e->act[wd] = still & e->busy[wd];
     while (fin) {
@@ -337,7 +345,13 @@ static dawn_status level_done(Server* S, Engine* e) {
   }
   hipStream_t s = w->stream;
   DAWN_HIP(hipMemcpyAsync(w->emask, e->h_em, (size_t)e->W * 8, hipMemcpyHostToDevice, s));
-  BatchArgs a = batch_args(e->g.get(), w, e->W);
+  int We = 1;
+  for (int i = e->W - 1; i >= 0; --i)
+    if (e->h_em[i]) {
+      We = i + 1;
+      break;
+    }
+  BatchArgs a = batch_args(e->g.get(), w, e->W, We);
   DAWN_TRY(batch_launch_emit(S->ctx, a, w->nplanes, w->emask, true, s));
   for (Query* q : done) {
     hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
