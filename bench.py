@@ -380,6 +380,41 @@ def cpu_baseline(g, src, dist_rows):
     return base, par, bool(np.array_equal(ref, dist_rows[: src.size]))
 
 
+def host_dawn_bench(g, src, threads=(1, 2, 4, 8, 16), per=4):
+    """The host CPU DAWN (SOVM on CPU threads) on R-MAT 20: one source at a
+    time with N threads sharing each level, and the thread efficiency of the
+    paper's scalability section, eta_N = T_1 / (T_N x N); then 64 sources
+    spread one per thread."""
+    from paper_2208_04514_amd import dawn_host as H
+    hg = H.HostGraph(g.row_ptr, g.col)
+    cores = os.cpu_count() or 1
+    res, t1 = {}, None
+    row = np.empty(g.n, np.int32)
+    for nt in threads:
+        if nt > cores:
+            continue
+        H.dawn_host_sssp(hg, int(src[0]), nt, out=row)
+        t0 = time.perf_counter()
+        se = 0
+        for s in src[:per]:
+            _, st = H.dawn_host_sssp(hg, int(s), nt, out=row)
+            se += st["source_edges"]
+        t = (time.perf_counter() - t0) / per
+        t1 = t if nt == 1 else t1
+        res[str(nt)] = {"ms_per_source": round(t * 1e3, 2), "gteps": round(se / per / t / 1e9, 4),
+                        "efficiency": round(t1 / (t * nt), 4) if t1 else None}
+    nt = min(16, cores)
+    t0 = time.perf_counter()
+    _, st = H.dawn_host_mssp(hg, src, nt)
+    t = time.perf_counter() - t0
+    hg.close()
+    return {"workload": f"rmat20, {per} sources per thread count (one at a time); "
+                        f"{src.size} sources one per thread", "per_source": res,
+            "sources_parallel": {"threads": nt, "ms": round(t * 1e3, 1),
+                                 "gteps": round(st["source_edges"] / t / 1e9, 4)},
+            "host_cores": cores, "cpu_model": cpu_model()}
+
+
 def roofline_only(D, ctx, params_json):
     """The level-kernel measurement alone (for profiling), then a 1 GiB device
     copy whose counters calibrate FETCH_SIZE and WRITE_SIZE."""
@@ -485,6 +520,8 @@ def main():
         cpu, cpu_par, same = cpu_baseline(g, src, dist_rows)
         extra["cpu_parallel"] = cpu_par
         extra["parity_sample_bit_exact"] = same
+        _log("[bench] host CPU DAWN (SOVM on CPU threads)")
+        extra["host_dawn"] = host_dawn_bench(g, src)
 
     line = {
         "metric": "GTEPS (source-edge traversals/s), plain per-source SSSP",
