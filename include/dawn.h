@@ -53,6 +53,11 @@ typedef int32_t dawn_status;
 
 /* ----------------------------------------------------------------- flags -- */
 #define DAWN_DEVICE_OUT 0x1u    /* distance output is device memory */
+#define DAWN_SHARED_CSC 0x2u    /* graph upload: the graph is symmetric, so its CSR also
+                                   serves as its in-lists (no transpose is kept: 4(n+1+m)
+                                   bytes less on the device).  Checked at upload (a
+                                   non-symmetric graph gives BAD_GRAPH).  Pull steps then
+                                   scan in-lists in CSR order. */
 
 /* ----------------------------------------------------------------- types -- */
 typedef struct dawn_ctx dawn_ctx;
@@ -149,8 +154,9 @@ dawn_status dawn_memory(dawn_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_by
  * build its in-lists (CSC: the transpose, which pull steps scan as BOVM does in
  * Section 3.2) and its out-degree metadata.  The CSR is validated first.
  * row_ptr: n+1 int32, col: m int32 (m = row_ptr[n] <= INT32_MAX), host memory.
- * *graph_out receives a handle >= 0.  flags: must be 0.
- * Errors: INVALID_ARG, BAD_GRAPH, NO_MEMORY, DEVICE. */
+ * *graph_out receives a handle >= 0.  flags: 0 or DAWN_SHARED_CSC (the
+ * memory-frugal resident form of a symmetric graph).
+ * Errors: INVALID_ARG (other flags), BAD_GRAPH, NO_MEMORY, DEVICE. */
 dawn_status dawn_graph_upload(dawn_ctx *ctx, int32_t n, int64_t m,
                               const int32_t *row_ptr, const int32_t *col,
                               uint32_t flags, int32_t *graph_out);

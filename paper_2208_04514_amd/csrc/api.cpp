@@ -204,12 +204,13 @@ dawn_status dawn_graph_upload(dawn_ctx* c, int32_t n, int64_t m, const int32_t* 
   if (n <= 0) return fail(DAWN_E_INVALID_ARG, "n must be positive (got %d)", n);
   if (m < 0 || m > 0x7fffffffLL) return fail(DAWN_E_INVALID_ARG, "m must be in [0, INT32_MAX]");
   if (!row_ptr || (m > 0 && !col) || !graph_out) return fail(DAWN_E_INVALID_ARG, "null pointer");
-  if (flags != 0) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~DAWN_SHARED_CSC) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
   Ctx* ctx = C(c);
   DAWN_HIP(hipSetDevice(ctx->device));
   auto g = std::make_shared<GraphRec>();
   g->n = n;
   g->m = m;
+  g->shared_csc = (flags & DAWN_SHARED_CSC) != 0;
   dawn_status st = graph_build(ctx, g.get(), row_ptr, col);
   if (st != DAWN_OK) return st;
   g->params = default_params(*g);

@@ -227,8 +227,10 @@ __global__ void list_pull_chunks(const int32_t* ip, int n, unsigned* count, int3
 static void free_graph_buffers(GraphRec* g) {
   dev_free(g->ctx, g->rp, ((size_t)g->n + 1) * 4);
   dev_free(g->ctx, g->col, (size_t)std::max(g->m, 1LL) * 4);
-  dev_free(g->ctx, g->ip, ((size_t)g->n + 1) * 4);
-  dev_free(g->ctx, g->isrc, (size_t)std::max(g->m, 1LL) * 4);
+  if (!g->shared_csc) {
+    dev_free(g->ctx, g->ip, ((size_t)g->n + 1) * 4);
+    dev_free(g->ctx, g->isrc, (size_t)std::max(g->m, 1LL) * 4);
+  }
   dev_free(g->ctx, g->noin, (((size_t)g->n + 63) / 64) * 8);
   dev_free(g->ctx, g->pcv, g->pc_cap * 4);
   dev_free(g->ctx, g->pck, g->pc_cap * 4);
@@ -250,14 +252,20 @@ static dawn_status alloc_graph_buffers(Ctx* ctx, GraphRec* g) {
   const size_t n1 = (size_t)g->n + 1, mm = (size_t)std::max(g->m, 1LL);
   DAWN_TRY(dev_alloc_n(ctx, &g->rp, n1));
   DAWN_TRY(dev_alloc_n(ctx, &g->col, mm));
-  DAWN_TRY(dev_alloc_n(ctx, &g->ip, n1));
-  DAWN_TRY(dev_alloc_n(ctx, &g->isrc, mm));
+  if (g->shared_csc) {
+    g->ip = g->rp;
+    g->isrc = g->col;
+  } else {
+    DAWN_TRY(dev_alloc_n(ctx, &g->ip, n1));
+    DAWN_TRY(dev_alloc_n(ctx, &g->isrc, mm));
+  }
   DAWN_TRY(dev_alloc_n(ctx, &g->noin, ((size_t)g->n + 63) / 64));
   // chunks: sum over in-lists of d >= kPullBig entries of ceil(d / kPullChunk)
   g->pc_cap = (size_t)(g->m / kPullChunk) + (size_t)(g->m / kPullBig) + 1;
   DAWN_TRY(dev_alloc_n(ctx, &g->pcv, g->pc_cap));
   DAWN_TRY(dev_alloc_n(ctx, &g->pck, g->pc_cap));
-  g->bytes = 2 * (n1 + mm) * 4 + (((size_t)g->n + 63) / 64) * 8 + g->pc_cap * 8;
+  g->bytes = (g->shared_csc ? 1 : 2) * (n1 + mm) * 4 + (((size_t)g->n + 63) / 64) * 8 +
+             g->pc_cap * 8;
   return DAWN_OK;
 }
 
@@ -285,6 +293,37 @@ static dawn_status finish_noin(Ctx* ctx, GraphRec* g, hipStream_t s) {
   return DAWN_OK;
 }
 
+// Symmetry check for DAWN_SHARED_CSC: the edge multiset equals its reverse
+// iff, for a hash h of ordered pairs, the sums of h(u, v) and of h(v, u)
+// over the edges agree (two independent 64-bit mixes; a non-symmetric graph
+// passes with probability ~2^-128), and every node's out-degree equals its
+// in-degree.
+static u64 mix64(u64 x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+static bool is_symmetric(int n, long long m, const int32_t* rp, const int32_t* col) {
+  std::vector<int32_t> indeg((size_t)n, 0);
+  u64 f1 = 0, r1 = 0, f2 = 0, r2 = 0;
+  for (int u = 0; u < n; ++u)
+    for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+      const u64 v = (u64)col[e];
+      indeg[(size_t)v] += 1;
+      const u64 a = ((u64)u << 32) | v, b = (v << 32) | (u64)u;
+      f1 += mix64(a);
+      r1 += mix64(b);
+      f2 += mix64(a ^ 0x5851f42d4c957f2dull);
+      r2 += mix64(b ^ 0x5851f42d4c957f2dull);
+    }
+  (void)m;
+  for (int u = 0; u < n; ++u)
+    if (indeg[(size_t)u] != rp[u + 1] - rp[u]) return false;
+  return f1 == r1 && f2 == r2;
+}
+
 dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_t* h_col) {
   const int n = g->n;
   const long long m = g->m;
@@ -302,6 +341,8 @@ dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_
   for (long long e = 0; e < m; ++e)
     if (h_col[e] < 0 || h_col[e] >= n)
       return fail(DAWN_E_BAD_GRAPH, "col[%lld] = %d outside [0, %d)", e, h_col[e], n);
+  if (g->shared_csc && !is_symmetric(n, m, h_rp, h_col))
+    return fail(DAWN_E_BAD_GRAPH, "DAWN_SHARED_CSC: the graph is not symmetric");
   g->max_out_deg = maxdeg;
   g->zero_out = zero;
   g->ctx = ctx;
@@ -314,7 +355,7 @@ dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dawn_status st = DAWN_OK;
   if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "upload: %s", hipGetErrorString(e));
-  if (st == DAWN_OK) st = build_csc(ctx, n, m, g->rp, g->col, g->ip, g->isrc, s);
+  if (st == DAWN_OK && !g->shared_csc) st = build_csc(ctx, n, m, g->rp, g->col, g->ip, g->isrc, s);
   if (st == DAWN_OK) st = finish_noin(ctx, g, s);
   hipStreamDestroy(s);
   return st;
@@ -473,6 +514,7 @@ dawn_status graph_wcc(Ctx* ctx, GraphRec* g, hipStream_t s) {
   sub->ctx = ctx;
   sub->n = s_wcc;
   sub->params = g->params;
+  sub->shared_csc = g->shared_csc;   // an induced subgraph of a symmetric graph is symmetric
   int32_t* srp = nullptr;
   if ((st = dev_alloc_n(ctx, &srp, (size_t)s_wcc + 1)) != DAWN_OK) {
     cleanup();
@@ -498,7 +540,8 @@ dawn_status graph_wcc(Ctx* ctx, GraphRec* g, hipStream_t s) {
     e = hipGetLastError();
     if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "wcc: %s", hipGetErrorString(e));
   }
-  if (st == DAWN_OK) st = build_csc(ctx, s_wcc, sm, sub->rp, sub->col, sub->ip, sub->isrc, s);
+  if (st == DAWN_OK && !sub->shared_csc)
+    st = build_csc(ctx, s_wcc, sm, sub->rp, sub->col, sub->ip, sub->isrc, s);
   if (st == DAWN_OK) st = finish_noin(ctx, sub.get(), s);
   std::vector<int32_t> h_nodes(s_wcc);
   if (st == DAWN_OK && s_wcc > 0) {

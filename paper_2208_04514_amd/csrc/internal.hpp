@@ -194,6 +194,7 @@ struct GraphRec {
   int32_t* ip = nullptr;
   int32_t* isrc = nullptr;
   u64* noin = nullptr;                    // nodes with no in-edge, one bit each
+  bool shared_csc = false;                // symmetric graph: ip/isrc alias rp/col
   // in-lists of at least kPullBig entries cut into chunks of kPullChunk, so
   // that a batched pull scans one long in-list with many waves: node, chunk
   int32_t* pcv = nullptr;

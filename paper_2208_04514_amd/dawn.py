@@ -25,6 +25,7 @@ DAWN_E_DEVICE = -4
 DAWN_E_NOT_FOUND = -5
 DAWN_E_BUSY = -6
 DAWN_DEVICE_OUT = 0x1
+DAWN_SHARED_CSC = 0x2
 
 STATUS_NAMES = {
     0: "DAWN_OK", 1: "DAWN_PENDING", -1: "DAWN_E_INVALID_ARG", -2: "DAWN_E_BAD_GRAPH",
