@@ -241,6 +241,35 @@ def apsp_bench(D, ctx):
             "gteps": round(st["source_edges"] / t / 1e9, 2), "levels": st["levels"]}
 
 
+def small_component_bench(D, ctx):
+    """Sources in small components (512 components of 16..2048 nodes): one
+    workgroup per source (small_n = 2048) vs the general level loop
+    (small_n = 0)."""
+    import torch
+    import graphgen as gg
+    g, src = gg.load_config("islands")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    res = {"workload": f"islands: 512 symmetric components of 16..2048 nodes (n={g.n}, m={g.m}), "
+                       f"{src.size} sources"}
+    rows = {}
+    for label, sn in (("one_workgroup", 2048), ("level_loop", 0)):
+        D.dawn_set_params(ctx, h, small_n=sn)
+        D.dawn_sssp(ctx, h, int(src[0]), out=out)
+        t0 = time.perf_counter()
+        se = 0
+        for s in src:
+            _, st = D.dawn_sssp(ctx, h, int(s), out=out)
+            se += st["source_edges"]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[label] = {"us_per_source": round(t / src.size * 1e6, 1), "gteps": round(se / t / 1e9, 4)}
+        rows[label] = out.cpu().numpy().copy()
+    res["same_last_row"] = bool(np.array_equal(rows["one_workgroup"], rows["level_loop"]))
+    D.dawn_graph_release(ctx, h)
+    return res
+
+
 def grid_bench(D, ctx, k_src=4):
     """The damaged 2048^2 grid (about 120 levels) under each level-loop
     driver, and the no-shortcut grid (thousands of levels) under two."""
@@ -522,6 +551,8 @@ def main():
         extra["apsp"] = apsp_bench(D, ctx)
         _log("[bench] grid 2048^2 level-loop drivers")
         extra["grid"] = grid_bench(D, ctx)
+        _log("[bench] small components")
+        extra["small_components"] = small_component_bench(D, ctx)
     if not args.no_serve:
         _log("[bench] serving: R-MAT 16, R-MAT 20, grid 1024^2")
         extra["served"] = serving_bench(D, ctx)

@@ -25,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "Graph", "to_csr", "gen_uniform", "gen_rmat", "gen_grid", "gen_edges",
-    "largest_wcc_nodes", "sample_sources", "CONFIGS", "load_config",
+    "gen_islands", "largest_wcc_nodes", "sample_sources", "CONFIGS", "load_config",
     "reach_edges_from_dist",
 ]
 
@@ -191,6 +191,32 @@ def gen_grid(k: int, seed: int, delete_frac=0.05, shortcut_frac=0.001) -> Graph:
 # Source selection
 # ---------------------------------------------------------------------------
 
+def gen_islands(count: int, min_size: int, max_size: int, degree: int, seed: int) -> Graph:
+    """Disjoint union of ``count`` small symmetric random graphs.
+
+    Component sizes are log-uniform in [min_size, max_size]; each component
+    has a path through its nodes (so it is connected) plus ``degree / 2 *
+    size`` uniform pairs, symmetrised, without self-loops or repeats; node
+    ids are then relabelled by one seeded permutation.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(np.log(min_size), np.log(max_size + 1), size=count)))
+    sizes = sizes.astype(np.int64)
+    src, dst, base = [], [], 0
+    for sz in sizes:
+        chain = np.arange(sz - 1, dtype=np.int64)
+        extra = rng.integers(0, sz, size=(int(degree // 2 * sz), 2), dtype=np.int64)
+        src += [chain + base, extra[:, 0] + base]
+        dst += [chain + 1 + base, extra[:, 1] + base]
+        base += int(sz)
+    n = base
+    perm = rng.permutation(n).astype(np.int64)
+    u = perm[np.concatenate(src)]
+    v = perm[np.concatenate(dst)]
+    rp, col = to_csr(n, u, v, symmetrize=True)
+    return Graph(n, rp, col, f"islands-{count}", {"seed": seed, "kind": "islands"})
+
+
 def largest_wcc_nodes(g: Graph) -> np.ndarray:
     """Ascending node ids of the largest weakly connected component.
 
@@ -259,6 +285,9 @@ CONFIGS = {
                    from_wcc=True),
     "grid1024": dict(kind="grid", k=1024, seed=7, src_seed=107, k_src=0,
                      from_wcc=True, delete=0.05, shortcut=0.001),
+    # many small components (log-uniform 16 .. 2048 nodes), 64 sources over all nodes
+    "islands": dict(kind="islands", count=512, min_size=16, max_size=2048, degree=8, seed=10,
+                    src_seed=110, k=64, from_wcc=False),
     # reduced-size variants for quick tests
     "rmat12": dict(kind="rmat", scale=12, ef=16, seed=8, src_seed=108, k=64,
                    from_wcc=True),
@@ -287,6 +316,9 @@ def _build(cfg: dict) -> Graph:
         return gen_rmat(cfg["scale"], cfg["ef"], cfg["seed"])
     if kind == "grid":
         return gen_grid(cfg["k"], cfg["seed"], cfg["delete"], cfg["shortcut"])
+    if kind == "islands":
+        return gen_islands(cfg["count"], cfg["min_size"], cfg["max_size"], cfg["degree"],
+                           cfg["seed"])
     raise ValueError(kind)
 
 

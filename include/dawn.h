@@ -103,7 +103,9 @@ typedef struct dawn_params {
   float alpha;                /* switch push -> pull when frontier edges > unvisited edges / alpha */
   float beta;                 /* switch pull -> push when frontier nodes < n / beta */
   int32_t graph_levels;       /* drivers 3, 4: level launches per host read-back (rounded up to even) */
-  int32_t small_n;            /* graphs with n <= small_n run as one workgroup per source */
+  int32_t small_n;            /* a source whose weakly connected component has
+                                 <= min(small_n, 2048) nodes is traversed by one workgroup
+                                 (0 = never; not when direction forces pull) */
   float batch_alpha;          /* batched: pull when (sum over frontier nodes of out-degree x
                                  nonzero 64-lane words) * batch_alpha >= n x words, else push */
   int32_t batch_lanes;        /* batched: sources per launch (64..4096, multiple of 64) */

@@ -139,6 +139,7 @@ constexpr unsigned long long kBarrierTimeoutTicks = 1000000000ull;   // 10 s
 __device__ __forceinline__ bool grid_sync(GridBarrier* bar) {
   __shared__ int ok;
   __syncthreads();
+  if (gridDim.x == 1) return true;   // one workgroup: the workgroup barrier is enough
   if (threadIdx.x == 0) {
     ok = 1;
     const unsigned nb = gridDim.x;

@@ -324,6 +324,8 @@ static bool is_symmetric(int n, long long m, const int32_t* rp, const int32_t* c
   return f1 == r1 && f2 == r2;
 }
 
+static dawn_status graph_components(Ctx* ctx, GraphRec* g, hipStream_t s);
+
 dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_t* h_col) {
   const int n = g->n;
   const long long m = g->m;
@@ -357,6 +359,7 @@ dawn_status graph_build(Ctx* ctx, GraphRec* g, const int32_t* h_rp, const int32_
   if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "upload: %s", hipGetErrorString(e));
   if (st == DAWN_OK && !g->shared_csc) st = build_csc(ctx, n, m, g->rp, g->col, g->ip, g->isrc, s);
   if (st == DAWN_OK) st = finish_noin(ctx, g, s);
+  if (st == DAWN_OK) st = graph_components(ctx, g, s);
   hipStreamDestroy(s);
   return st;
 }
@@ -417,6 +420,49 @@ __global__ void uf_label(int* parent, int n, int32_t* sizes) {
     if (lane == 0) atomicAdd(&sizes[r0], (int)__popcll(same));
     if (valid && r != r0) atomicAdd(&sizes[r], 1);
   }
+}
+
+__global__ void comp_size_of(const int* label, const int32_t* sizes, int n, int32_t* out) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    out[v] = sizes[label[v]];
+}
+
+// Size of every node's weakly connected component (union-find over the
+// edges taken undirected), kept on the host: a source in a small component
+// is traversed by one workgroup.
+static dawn_status graph_components(Ctx* ctx, GraphRec* g, hipStream_t s) {
+  const int n = g->n;
+  int* parent = nullptr;
+  int32_t *sizes = nullptr, *per = nullptr;
+  dawn_status st = DAWN_OK;
+  if ((st = dev_alloc_n(ctx, &parent, n)) || (st = dev_alloc_n(ctx, &sizes, n)) ||
+      (st = dev_alloc_n(ctx, &per, n))) {
+    dev_free(ctx, parent, (size_t)n * 4);
+    dev_free(ctx, sizes, (size_t)n * 4);
+    dev_free(ctx, per, (size_t)n * 4);
+    return st;
+  }
+  const int gb = grid_for(ctx, n, 256);
+  hipError_t e = hipMemsetAsync(sizes, 0, (size_t)n * 4, s);
+  hipLaunchKernelGGL(uf_init, dim3(gb), dim3(256), 0, s, parent, n);
+  if (g->m > 0)
+    hipLaunchKernelGGL(uf_hook, dim3(grid_for(ctx, g->m, 256)), dim3(256), 0, s, g->rp, g->col, n,
+                       g->m, parent);
+  hipLaunchKernelGGL(uf_label, dim3(gb), dim3(256), 0, s, parent, n, sizes);
+  hipLaunchKernelGGL(comp_size_of, dim3(gb), dim3(256), 0, s, parent, sizes, n, per);
+  if (e == hipSuccess) e = hipGetLastError();
+  g->comp_size.resize((size_t)n);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->comp_size.data(), per, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(ctx, parent, (size_t)n * 4);
+  dev_free(ctx, sizes, (size_t)n * 4);
+  dev_free(ctx, per, (size_t)n * 4);
+  if (e != hipSuccess) {
+    g->comp_size.clear();
+    return fail(DAWN_E_DEVICE, "components: %s", hipGetErrorString(e));
+  }
+  return DAWN_OK;
 }
 
 __global__ void uf_best(const int32_t* sizes, int n, u64* best) {

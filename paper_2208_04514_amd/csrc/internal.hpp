@@ -195,6 +195,8 @@ struct GraphRec {
   int32_t* isrc = nullptr;
   u64* noin = nullptr;                    // nodes with no in-edge, one bit each
   bool shared_csc = false;                // symmetric graph: ip/isrc alias rp/col
+  std::vector<int32_t> comp_size;         // host copy: nodes in each node's weakly
+                                          //   connected component
   // in-lists of at least kPullBig entries cut into chunks of kPullChunk, so
   // that a batched pull scans one long in-list with many waves: node, chunk
   int32_t* pcv = nullptr;

@@ -542,6 +542,149 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
   if (leader) a.ctrl->st[1] = st;
 }
 
+// ------------------------------------------------- one-workgroup traversal --
+// A source whose weakly connected component has at most kCompMax nodes reaches
+// at most that many: one workgroup runs its whole push level loop after the
+// grid-wide init kernel (dist = -1, visited = {source}).  The frontier lives
+// in LDS; a level's new nodes are deduplicated in an LDS hash set (so a node
+// found through several edges is claimed once without a global atomic per
+// edge), then marked visited and given their distance.
+constexpr int kCompMax = 2048;
+constexpr int kCompHash = 4096;    // power of two >= 2 x kCompMax: probing always ends
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sssp_component(SsspArgs a0) {
+  SsspArgs a = a0;
+  a.dist = a0.ctrl->dist;
+  // frontier and next: node, row start, out-degree
+  __shared__ int32_t qa[kCompMax], qb[kCompMax], ra[kCompMax], rb[kCompMax], da[kCompMax],
+      db[kCompMax];
+  __shared__ int32_t hset[kCompHash];
+  __shared__ unsigned nnew;
+  __shared__ u64 wsum[2][BLOCK / kWave];
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  constexpr int NW = BLOCK / kWave;
+  const int src = a0.ctrl->source;
+  int32_t *cur = qa, *nxt = qb, *cur_r = ra, *nxt_r = rb, *cur_d = da, *nxt_d = db;
+  if (tid == 0) {
+    qa[0] = src;
+    ra[0] = a.rp[src];
+    da[0] = a.rp[src + 1] - ra[0];
+  }
+  unsigned fsize = 1;
+  u64 edges_total = 0, source_edges = (u64)(a.rp[src + 1] - a.rp[src]), reached = 1;
+  int L = 0, last = 0, expansions = 0;
+  for (;;) {
+    for (int i = tid; i < kCompHash; i += BLOCK) hset[i] = -1;
+    if (tid == 0) nnew = 0;
+    __syncthreads();
+    ++L;
+    ++expansions;
+    // expand: each wave takes 64 frontier nodes and walks the union of their
+    // out-lists 64 edges a step (a lane finds its edge's node by binary
+    // search over the wave's degree prefix sums)
+    u64 my_edges = 0;
+    for (unsigned b = (unsigned)wv * kWave; b < fsize; b += NW * kWave) {
+      const unsigned i = b + (unsigned)lane;
+      int rs = 0, deg = 0;
+      if (i < fsize) {
+        rs = cur_r[i];
+        deg = cur_d[i];
+      }
+      const int incl = wave_incl_scan(deg);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      if (lane == 0) my_edges += (u64)total;
+      for (int eb = 0; eb < total; eb += kWave) {
+        const int x = eb + lane;
+        const bool has = x < total;
+        const int j = wave_owner(incl, has ? x : total - 1);
+        const int inc_j = __shfl(incl, j, kWave);
+        const int deg_j = __shfl(deg, j, kWave);
+        const int rs_j = __shfl(rs, j, kWave);
+        if (!has) continue;
+        const int v = a.col[rs_j + (x - (inc_j - deg_j))];
+        if ((ld_relaxed(&a.vis0[v >> 6]) >> (v & 63)) & 1ull) continue;
+        unsigned h = ((unsigned)v * 2654435761u) & (kCompHash - 1);
+        for (;;) {
+          const int old = atomicCAS(&hset[h], -1, v);
+          if (old == -1) {
+            nxt[atomicAdd(&nnew, 1u)] = v;
+            break;
+          }
+          if (old == v) break;
+          h = (h + 1) & (kCompHash - 1);
+        }
+      }
+    }
+    __syncthreads();
+    const unsigned found = nnew;
+    // mark the new nodes: distance, visited bit, out-degree sum
+    u64 my_mf = 0;
+    for (unsigned i = (unsigned)tid; i < found; i += BLOCK) {
+      const int v = nxt[i];
+      a.dist[v] = L;
+      atom_or(&a.vis0[v >> 6], 1ull << (v & 63));
+      const int rs = a.rp[v], d = a.rp[v + 1] - rs;
+      nxt_r[i] = rs;
+      nxt_d[i] = d;
+      my_mf += (u64)d;
+    }
+    my_edges = wave_sum(my_edges);
+    my_mf = wave_sum(my_mf);
+    if (lane == 0) {
+      wsum[0][wv] = my_edges;
+      wsum[1][wv] = my_mf;
+    }
+    __syncthreads();
+    u64 le = 0, lm = 0;
+    for (int i = 0; i < NW; ++i) {
+      le += wsum[0][i];
+      lm += wsum[1][i];
+    }
+    edges_total += le;
+    if (tid == 0 && L < a.lrec) {
+      a.level_nf[L] = (int32_t)found;
+      a.level_dir[L] = 1;
+    }
+    if (found == 0) break;
+    last = L;
+    source_edges += lm;
+    reached += found;
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    t = cur_r;
+    cur_r = nxt_r;
+    nxt_r = t;
+    t = cur_d;
+    cur_d = nxt_d;
+    nxt_d = t;
+    fsize = found;
+    if (lm == 0) break;   // the new nodes have no out-edge: nothing left to expand
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (a.lrec > 0) {
+      a.level_nf[0] = 1;
+      a.level_dir[0] = 0;
+    }
+    LevelState st;
+    st.level = last;
+    st.cur = 0;
+    st.pull = 0;
+    st.done = 1;
+    st.mu = 0;
+    st.last_nonempty = last;
+    st.push_levels = expansions;
+    st.pull_levels = 0;
+    st.prev_nf = 0;
+    st.edges_total = edges_total;
+    st.source_edges = source_edges;
+    st.reached = reached;
+    a.ctrl->st[1] = st;
+  }
+}
+
 // ------------------------------------------------------ per-level drivers --
 // Initial state of one traversal (the source is read from the control block).
 template <int BLOCK>
@@ -726,7 +869,14 @@ static dawn_status launch_persistent(Ctx* ctx, SsspWs* w, const SsspArgs& a, int
   DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_persistent<BLOCK>, BLOCK, 0));
   if (occ < 1) return fail(DAWN_E_DEVICE, "persistent kernel cannot be resident");
   int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ;
-  int grid = single ? 1 : per_cu * ctx->num_cu;
+  if (single) {
+    // one workgroup: its barriers are workgroup barriers, so a plain launch
+    // does (a cooperative launch costs tens of microseconds more here)
+    hipLaunchKernelGGL(sssp_persistent<BLOCK>, dim3(1), dim3(BLOCK), 0, w->stream, a);
+    DAWN_HIP(hipGetLastError());
+    return DAWN_OK;
+  }
+  int grid = per_cu * ctx->num_cu;
   SsspArgs args = a;
   void* kargs[] = {&args};
   DAWN_HIP(hipLaunchCooperativeKernel((const void*)sssp_persistent<BLOCK>, dim3(grid),
@@ -857,14 +1007,31 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
   return fail(DAWN_E_DEVICE, "level loop did not terminate");
 }
 
+// A source whose weakly connected component has at most small_n nodes (it
+// reaches no more) is traversed by one workgroup (sssp_component) after the
+// grid-wide init kernel.  Forced pull keeps the general path.
+static bool small_component(const GraphRec* g, const dawn_params& p, int32_t source) {
+  return p.small_n > 0 && p.direction != 2 && !g->comp_size.empty() &&
+         g->comp_size[(size_t)source] <= std::min(p.small_n, kCompMax);
+}
+
 template <int BLOCK>
 static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_params& p,
-                                 SsspArgs& a, int* launches, double* level_ms, int* final_parity) {
-  const bool single = g->n <= p.small_n;
-  if (p.driver == 1 || single) {
+                                 SsspArgs& a, int32_t source, int* launches, double* level_ms,
+                                 int* final_parity) {
+  if (small_component(g, p, source)) {
+    const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+    hipLaunchKernelGGL(sssp_component<BLOCK>, dim3(1), dim3(BLOCK), 0, w->stream, a);
+    DAWN_HIP(hipGetLastError());
+    *launches = 2;
+    *final_parity = 1;
+    return DAWN_OK;
+  }
+  if (p.driver == 1) {
     *launches = 1;
     *final_parity = 1;
-    return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, single);
+    return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, false);
   }
   // the visited bitmap goes to LDS for pull levels when it fits next to the
   // kernel's own LDS
@@ -912,7 +1079,8 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   SsspArgs a;
   fill_args(a, g, w.get(), p, source, d_dist);
   int launches = 0;
-  const bool level_timing = p.timing == 1 && p.driver == 2 && g->n > p.small_n;
+  const bool small = small_component(g, p, source);
+  const bool level_timing = p.timing == 1 && p.driver == 2 && !small;
   double level_ms = 0.0;
   double* lm = level_timing ? &level_ms : nullptr;
   int fp = 1;
@@ -924,9 +1092,9 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
-    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, &launches, lm, &fp); break;
-    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, &launches, lm, &fp); break;
-    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, &launches, lm, &fp); break;
+    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, source, &launches, lm, &fp); break;
+    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, &launches, lm, &fp); break;
+    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, &launches, lm, &fp); break;
   }
   if (!level_timing) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
@@ -937,7 +1105,7 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   const uint64_t t_loop = now_ns();
   // the per-level and graph drivers already read the final state back; the
   // persistent driver's state (and its barrier's abort flag) is read here
-  const bool persistent = p.driver == 1 || g->n <= p.small_n;
+  const bool persistent = p.driver == 1 || small;
   const int32_t cap = (stats && stats->frontier_cap > 0) ? std::min(stats->frontier_cap, w->lrec) : 0;
   std::vector<int32_t> lnf;
   std::vector<uint8_t> ldir;

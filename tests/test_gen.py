@@ -109,3 +109,19 @@ def test_config_small_workloads():
     g, src = gg.load_config("rmat12", use_cache=False)
     wcc = g.meta["wcc_nodes"]
     assert np.isin(src, wcc).all() and src.size == 64
+
+
+def test_islands_components():
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    g = gg.gen_islands(40, 4, 300, 6, seed=3)
+    a = csr_matrix((np.ones(g.m, dtype=np.int8), g.col, g.row_ptr), shape=(g.n, g.n))
+    nc, lab = connected_components(a, directed=False)
+    assert nc == 40
+    sizes = np.bincount(lab)
+    assert sizes.min() >= 4 and sizes.max() <= 300
+    # symmetric, loop-free
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    assert not (src == g.col).any()
+    fwd = set(zip(src.tolist(), g.col.tolist()))
+    assert all((v, u) in fwd for u, v in fwd)

@@ -228,3 +228,38 @@ def test_full_size(ctx, upload, name, count):
         got, st = D.dawn_sssp(ctx, h, int(src[0]))
         _check_row(g, src[0], got)
     D.dawn_set_params(ctx, h, driver=1)
+
+
+def test_small_components_one_workgroup(ctx):
+    """Sources in weakly connected components of <= small_n nodes run as one
+    workgroup (two launches); results equal the oracle's, and forcing pull or
+    small_n = 0 takes the general level loop with the same rows."""
+    rng = np.random.default_rng(21)
+    edges, base, comps = [], 0, []
+    for size in [1, 2, 3, 17, 64, 200, 1000, 2048, 2049, 5000]:
+        local = rng.integers(0, size, size=(3 * size, 2)) if size > 1 else np.zeros((0, 2), np.int64)
+        chain = [(i, i + 1) for i in range(size - 1)]          # keep it weakly connected
+        e = np.concatenate([local, np.array(chain, np.int64).reshape(-1, 2)]) + base
+        edges.append(e)
+        comps.append((base, size))
+        base += size
+    g = gg.gen_edges(base, np.concatenate(edges), symmetrize=False, drop_self=False, dedupe=True)
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    try:
+        D.dawn_set_params(ctx, h, small_n=2048, direction=3)
+        for b, size in comps:
+            for s in sorted({b, b + size // 2, b + size - 1}):
+                got, st = D.dawn_sssp(ctx, h, s, frontier_cap=64)
+                _check_row(g, s, got, st)
+                if size <= 2048:
+                    assert st["launches"] == 2, (size, st["launches"])
+                else:
+                    assert st["launches"] > 2
+        for kw in (dict(small_n=0, direction=3), dict(small_n=2048, direction=2),
+                   dict(small_n=2048, direction=1, driver=2)):
+            D.dawn_set_params(ctx, h, **kw)
+            for b, size in comps[:7]:
+                got, st = D.dawn_sssp(ctx, h, b, frontier_cap=64)
+                _check_row(g, b, got, st)
+    finally:
+        D.dawn_graph_release(ctx, h)
