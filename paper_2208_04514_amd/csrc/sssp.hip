@@ -97,16 +97,14 @@ __device__ __forceinline__ void wq_flush(const SsspArgs& a, int L, WaveQueue& q)
   q.cnt = 0;
 }
 
-// Record node v (claimed at level L by the calling lane when `found`) in the
-// distance vector and in the next frontier.  Must be reached by the whole wave.
+// Record node v (claimed at level L by the calling lane when `found`, out-degree
+// deg) in the distance vector and in the next frontier.  Must be reached by the
+// whole wave.
 template <int BLOCK>
-__device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool found,
-                                           Counters& c, WaveQueue& q) {
-  int deg = 0;
+__device__ __forceinline__ void emit_found_deg(const SsspArgs& a, int L, int v, bool found, int deg,
+                                               Counters& c, WaveQueue& q) {
   if (found) {
     a.dist[v] = L;
-    int r0 = a.rp[v];
-    deg = a.rp[v + 1] - r0;
     c.nf += 1;
     c.mf += (u64)deg;
   }
@@ -151,6 +149,14 @@ __device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool
   }
 }
 
+// emit_found with the out-degree loaded here.
+template <int BLOCK>
+__device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool found,
+                                           Counters& c, WaveQueue& q) {
+  const int deg = found ? a.rp[v + 1] - a.rp[v] : 0;
+  emit_found_deg<BLOCK>(a, L, v, found, deg, c, q);
+}
+
 // List the chunks of the workgroup's staged big-degree nodes (every thread
 // of the workgroup calls it; resets the staging list).
 template <int BLOCK>
@@ -190,23 +196,6 @@ __device__ __forceinline__ void flush_big(const SsspArgs& a, int L, WaveQueue& q
   }
 }
 
-// Claim target v (if `has`) at level L: test, then atomic OR on the visited bit.
-template <int BLOCK>
-__device__ __forceinline__ void visit(const SsspArgs& a, int L, u64* vis, int v, bool has,
-                                      Counters& c, WaveQueue& q) {
-  bool claimed = false;
-  if (has) {
-    c.edges += 1;
-    const u64 bit = 1ull << (v & 63);
-    u64* wp = vis + (v >> 6);
-    if ((*wp & bit) == 0) {
-      u64 old = atom_or(wp, bit);
-      claimed = (old & bit) == 0;
-    }
-  }
-  emit_found<BLOCK>(a, L, v, claimed, c, q);
-}
-
 // Prefix offsets of the kStripes sub-queues of level L-1, in LDS.
 __device__ __forceinline__ void stripe_prefix(const LevelSlot* in, unsigned* pre) {
   __syncthreads();
@@ -230,26 +219,67 @@ __device__ __forceinline__ int stripe_of(const unsigned* pre, unsigned i) {
   return lo;
 }
 
+// Claim up to four targets per lane (has[i]): every visited word, then every
+// claiming atomic, then the claimed nodes' degrees are loaded as one batch
+// of independent requests before the nodes are recorded.  Wave-uniform call.
+template <int BLOCK>
+__device__ __forceinline__ void visit4(const SsspArgs& a, int L, u64* vis, const int* v,
+                                       const bool* has, Counters& c, WaveQueue& q) {
+  u64 w[4], old[4], bit[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    bit[i] = 1ull << (v[i] & 63);
+    w[i] = has[i] ? vis[v[i] >> 6] : bit[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) old[i] = (w[i] & bit[i]) ? bit[i] : atom_or(&vis[v[i] >> 6], bit[i]);
+  bool claim[4];
+  int deg[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (has[i]) c.edges += 1;
+    claim[i] = !(old[i] & bit[i]);
+    deg[i] = claim[i] ? a.rp[v[i] + 1] - a.rp[v[i]] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) emit_found_deg<BLOCK>(a, L, v[i], claim[i], deg[i], c, q);
+}
+
+// pre: the sub-queue offsets of level L-1 in LDS; `nch` its chunk count, or
+// ~0u to have them read here.
 template <int BLOCK>
 __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQueue& q,
-                          unsigned* pre) {
+                          unsigned* pre, unsigned nch) {
   const LevelSlot* in = &a.ctrl->slot[(L - 1) % 3];
-  stripe_prefix(in, pre);
+  if (nch == ~0u) {
+    stripe_prefix(in, pre);
+    nch = ld_relaxed(&in->big_chunks);
+  }
   const unsigned nsmall = pre[kStripes];
-  const unsigned nchunks = ld_relaxed(&in->big_chunks);
+  const unsigned nchunks = nch;
 
-  // big-degree nodes: one chunk of BLOCK edges per workgroup iteration
+  // big-degree nodes: chunks of BLOCK edges, four chunks per workgroup
+  // iteration (one edge of each per thread)
   const int32_t* cu = chunk_u(a, L - 1);
   const int32_t* ck = chunk_k(a, L - 1);
-  for (unsigned g = blockIdx.x; g < nchunks; g += gridDim.x) {
-    const int u = cu[g];
-    const int k = ck[g];
-    const int start = a.rp[u] + k * BLOCK;
-    const int end = min(start + BLOCK, a.rp[u + 1]);
-    const int e = start + (int)threadIdx.x;
-    const bool has = e < end;
-    const int v = has ? a.col[e] : 0;
-    visit<BLOCK>(a, L, vis, v, has, c, q);
+  for (unsigned g = blockIdx.x; g < nchunks; g += 4 * gridDim.x) {
+    int v[4];
+    bool has[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned gi = g + (unsigned)i * gridDim.x;
+      has[i] = false;
+      v[i] = 0;
+      if (gi < nchunks) {
+        const int u = cu[gi];
+        const int start = a.rp[u] + ck[gi] * BLOCK;
+        const int end = min(start + BLOCK, a.rp[u + 1]);
+        const int e = start + (int)threadIdx.x;
+        has[i] = e < end;
+        if (has[i]) v[i] = a.col[e];
+      }
+    }
+    visit4<BLOCK>(a, L, vis, v, has, c, q);
   }
 
   // small-degree nodes: 64 per wave, union of their rows walked 64 edges a step
@@ -269,15 +299,21 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
     }
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, kWave - 1, kWave);
-    for (int eb = 0; eb < total; eb += kWave) {
-      const int x = eb + lane;
-      const bool has = x < total;
-      const int j = wave_owner(incl, has ? x : total - 1);
-      const int inc_j = __shfl(incl, j, kWave);
-      const int deg_j = __shfl(deg, j, kWave);
-      const int rs_j = __shfl(rs, j, kWave);
-      const int v = has ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
-      visit<BLOCK>(a, L, vis, v, has, c, q);
+    // four edges per lane and step
+    for (int eb = 0; eb < total; eb += 4 * kWave) {
+      int v[4];
+      bool has[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = eb + i * kWave + lane;
+        has[i] = x < total;
+        const int j = wave_owner(incl, has[i] ? x : total - 1);
+        const int inc_j = __shfl(incl, j, kWave);
+        const int deg_j = __shfl(deg, j, kWave);
+        const int rs_j = __shfl(rs, j, kWave);
+        v[i] = has[i] ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
+      }
+      visit4<BLOCK>(a, L, vis, v, has, c, q);
     }
   }
 }
@@ -533,7 +569,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
       pull_step<BLOCK>(a, L, vcur, vnext, c, q, ps);
       st.cur ^= 1;
     } else {
-      push_step<BLOCK>(a, L, vcur, c, q, pre);
+      push_step<BLOCK>(a, L, vcur, c, q, pre, ~0u);
     }
     finish_level<BLOCK>(a, L, c, q);
     if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
@@ -714,28 +750,51 @@ __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
   __shared__ LevelState sst;
   __shared__ int idle;
   __shared__ int32_t big_v[BLOCK], big_c[BLOCK];
-  __shared__ unsigned big_n;
-  if (threadIdx.x == 0) {
-    big_n = 0;
-    LevelState st = a.ctrl->st[parity ^ 1];
-    if (!st.done) {
-      const LevelSlot* sl = &a.ctrl->slot[st.level % 3];
-      SlotSum sum{0, 0, 0};
-      unsigned nsmall = 0;
-      for (int i = 0; i < kStripes; ++i) {
-        sum.nf += sl->s[i].nf;
-        sum.mf += sl->s[i].mf;
-        sum.edges += sl->s[i].edges;
-        nsmall += sl->s[i].small_count;
-      }
-      decide(a, st, sum, blockIdx.x == 0);
-      // a push level with nothing for this workgroup lets it leave at once
-      const unsigned first_small = blockIdx.x * (BLOCK / kWave) * kWave;
-      idle = !st.done && !st.pull && first_small >= nsmall && blockIdx.x >= sl->big_chunks;
-    } else {
-      idle = 1;
+  __shared__ unsigned big_n, nchunks;
+  // The first wave reads the state and, in the same round trip, the counters
+  // of all three slots (lane 16 s + i: stripe i of slot s; lanes 48..50 the
+  // chunk counts), keeps the slot of the previous level and reduces it: the
+  // push step finds its sub-queue offsets and chunk count in LDS.
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const LevelState st0 = a.ctrl->st[parity ^ 1];
+    unsigned nf = 0, sc = 0, bc = 0;
+    u64 mf = 0, ed = 0;
+    if (lane < 3 * kStripes) {
+      const SlotStripe& sp = a.ctrl->slot[lane / kStripes].s[lane % kStripes];
+      nf = sp.nf;
+      sc = sp.small_count;
+      mf = sp.mf;
+      ed = sp.edges;
+    } else if (lane < 3 * kStripes + 3) {
+      bc = a.ctrl->slot[lane - 3 * kStripes].big_chunks;
     }
-    sst = st;
+    const int sel = st0.level % 3;
+    const bool mine = lane < 3 * kStripes && lane / kStripes == sel;
+    if (!mine) {
+      nf = sc = 0;
+      mf = ed = 0;
+    }
+    const int sc_incl = wave_incl_scan((int)sc);
+    if (mine) pre[lane % kStripes] = (unsigned)(sc_incl - (int)sc);
+    const unsigned nsmall = (unsigned)__shfl(sc_incl, kWave - 1, kWave);
+    const SlotSum sum{wave_sum(nf), wave_sum(mf), wave_sum(ed)};
+    const unsigned nch = (unsigned)__shfl((int)bc, 3 * kStripes + sel, kWave);
+    if (lane == 0) {
+      pre[kStripes] = nsmall;
+      nchunks = nch;
+      big_n = 0;
+      LevelState st = st0;
+      if (!st.done) {
+        decide(a, st, sum, blockIdx.x == 0);
+        // a push level with nothing for this workgroup lets it leave at once
+        const unsigned first_small = blockIdx.x * (BLOCK / kWave) * kWave;
+        idle = !st.done && !st.pull && first_small >= nsmall && blockIdx.x >= nch;
+      } else {
+        idle = 1;
+      }
+      sst = st;
+    }
   }
   __syncthreads();
   const LevelState st = sst;
@@ -763,7 +822,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
     }
     pull_step<BLOCK>(a, L, look, vnext, c, q, ps);
   } else {
-    push_step<BLOCK>(a, L, vcur, c, q, pre);
+    push_step<BLOCK>(a, L, vcur, c, q, pre, nchunks);
   }
   finish_level<BLOCK>(a, L, c, q);
 }
