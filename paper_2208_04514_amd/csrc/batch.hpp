@@ -7,6 +7,7 @@
 namespace dawn {
 
 constexpr int kMaxPlanes = 16;    // relative levels up to 2^16 - 1 per source
+constexpr int kMaxBatchLanes = 4096;  // sources one batch carries: 64 words of 64 lanes
 
 // One stripe (a whole cache line) of the counters of one level of a batch.
 struct alignas(kLine) BatchStripe {

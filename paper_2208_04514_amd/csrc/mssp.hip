@@ -661,111 +661,153 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
 }
 
 // ------------------------------------------------------------------ emit --
-// Write the distance rows of the lanes in emask.  A workgroup takes a tile of
-// kEmitSub x 64 nodes; the tile's visited words and level planes are read
-// EW = 16 / DMAX words at a time (contiguous within each node's row) and
-// transposed into LDS.  Then, for each word of the chunk, wave q of the block
-// takes the emitted sources b with b % 4 == q: lane l holds nodes
-// v0 + 4 l .. v0 + 4 l + 3 in registers, rebuilds the source's level for them
-// and the wave writes the tile's 1 KiB run of the source's row.  With `clear` the emitted
-// lanes' bits are removed from vis and the planes (serving reuses the lanes).
-constexpr int kEmitSub = 4;       // nodes per lane (a tile is 4 x 64 nodes)
-typedef int v4i __attribute__((ext_vector_type(4)));
-constexpr int kEmitTile = kEmitSub * 64;
-
+// Write the distance rows of the lanes in emask.  A wave takes a task of 64
+// nodes (lane l owns node v0 + l) and a group of EG consecutive words of their
+// rows.  Each lane loads its node's EG visited words and EG words of each of
+// the D level planes into registers, so a node's 128-byte line is fetched by
+// one lane in 16 / EG back-to-back passes (one when EG = 16) instead of being
+// re-read later.  Then, for every emitted source b of the group, the lanes
+// rebuild b's level at their nodes (-1 where the visited bit is clear) and the
+// wave writes the 64 values as one 256-byte run of b's row.  Tasks run
+// word-group-major, so waves running side by side write neighbouring runs of
+// the same rows.  With `clear` the emitted lanes' bits are removed from vis and
+// the planes (serving reuses the lanes).
+// One source's 64 values: lane l writes b's level at its node (-1 where the
+// visited bit is clear) at byte offset voff of b's row.  b is wave-uniform, so
+// the row pointer comes from lane b's register and the store takes a scalar
+// base with a 32-bit lane offset.
 template <int DMAX>
-__global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D, const u64* emask,
+__device__ __forceinline__ void emit_one(u64 my_row, int b, int bit, unsigned xh,
+                                         const unsigned* ph, unsigned voff) {
+  typedef __attribute__((address_space(1))) char gchar;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)my_row, b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(my_row >> 32), b);
+  const unsigned long long addr = ((unsigned long long)hi << 32) | lo;
+  if (!addr) return;
+  int lv = 0;
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) lv |= (int)((ph[d] >> bit) & 1u) << d;
+  // visited: the level; not visited: -1 (all bits set)
+  const int val = lv | ((int)((xh >> bit) & 1u) - 1);
+  // written once and not read again by the library
+  __builtin_nontemporal_store(val, (__attribute__((address_space(1))) int*)((gchar*)addr + voff));
+}
+
+template <int DMAX, int EG>
+__global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
+                                                          const u64* __restrict__ emask,
                                                           int clear) {
-  constexpr int EW = 16 / DMAX;
-  __shared__ u64 sx[EW][kEmitTile + 1];
-  __shared__ u64 sp[DMAX][EW][kEmitTile + 1];
-  const int tid = threadIdx.x;
+  // the row pointers of all lanes, staged once: a per-word global load in the
+  // store loop would wait for every store before it
+  __shared__ u64 srow[kMaxBatchLanes];
   const int lane = lane_id();
-  const int wv = tid / kWave;
   const int W = a.W;
+  for (int i = threadIdx.x; i < W * 64; i += kBatchBlock) srow[i] = (u64)a.rows[i];
+  __syncthreads();
+  const int gw = __builtin_amdgcn_readfirstlane(
+      (int)((blockIdx.x * (unsigned)kBatchBlock + threadIdx.x) / kWave));
+  const int nwaves = (int)(gridDim.x * (kBatchBlock / kWave));
   const size_t Ws = (size_t)a.Ws;
-  const int ntiles = (a.n + kEmitTile - 1) / kEmitTile;
-  // sources b with b % 4 == wv belong to wave wv
-  const u64 wave_bits = 0x1111111111111111ull << wv;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int v0 = t * kEmitTile;
-    const int nv = min(kEmitTile, a.n - v0);
-    for (int wc0 = 0; wc0 < W; wc0 += EW) {
-      const int wcn = min(EW, W - wc0);
-      bool any = false;
-      for (int i = 0; i < wcn; ++i) any |= emask[wc0 + i] != 0;
-      if (!any) continue;
-      __syncthreads();
-      for (int e = tid; e < kEmitTile * wcn; e += kBatchBlock) {
-        const int j = e / wcn, wl = e % wcn;
-        u64 x = 0;
-        u64 pv[DMAX];
+  const int ntiles = (a.n + kWave - 1) / kWave;
+  const int ngroups = (W + EG - 1) / EG;
+  const long long tasks = (long long)ntiles * ngroups;
+  for (long long t = gw; t < tasks; t += nwaves) {
+    const int w0 = (int)(t / ntiles) * EG;
+    const int v = (int)(t % ntiles) * kWave + lane;
+    const int ew = min(EG, W - w0);
+    bool any = false;
+    for (int e = 0; e < ew; ++e) any |= emask[w0 + e] != 0;
+    if (!any) continue;
+    const bool live = v < a.n;
+    const bool full = (int)(t % ntiles) * kWave + kWave <= a.n;  // no lane past the last node
+    const size_t base = (size_t)(live ? v : 0) * Ws + w0;
+    u64 x[EG];
+    u64 pl[DMAX][EG];
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d) pv[d] = 0;
-        if (j < nv) {
-          const size_t idx = (size_t)(v0 + j) * Ws + wc0 + wl;
-          const u64 em = emask[wc0 + wl];
-          x = a.vis[idx];
+    for (int d = 0; d < DMAX; ++d)
 #pragma unroll
-          for (int d = 0; d < DMAX; ++d)
-            if (d < D) pv[d] = a.planes[d][idx];
-          if (clear && em) {
-            a.vis[idx] = x & ~em;
+      for (int e = 0; e < EG; ++e) pl[d][e] = 0;
+    if (ew == EG && (Ws & 1) == 0) {
+      // whole groups of 16-byte aligned words: each lane reads its node's
+      // words of one array in consecutive 16-byte loads, so the requests for
+      // a line follow each other closely enough that it is fetched once
+      // (lanes past the last node read node 0's row and drop it)
+      const ulonglong2* pv = reinterpret_cast<const ulonglong2*>(a.vis + base);
 #pragma unroll
-            for (int d = 0; d < DMAX; ++d)
-              if (d < D) a.planes[d][idx] = pv[d] & ~em;
-          }
-        }
-        // node j sits at (j % 4) * 64 + j / 4: lane l then reads nodes 4 l .. 4 l + 3
-        const int pj = ((j & 3) << 6) | (j >> 2);
-        sx[wl][pj] = x;
-#pragma unroll
-        for (int d = 0; d < DMAX; ++d) sp[d][wl][pj] = pv[d];
+      for (int q = 0; q < EG / 2; ++q) {
+        const ulonglong2 t2 = pv[q];
+        x[2 * q] = live ? t2.x : 0;
+        x[2 * q + 1] = live ? t2.y : 0;
       }
-      __syncthreads();
-      for (int wl = 0; wl < wcn; ++wl) {
-        const int w = wc0 + wl;
-        u64 em = emask[w] & wave_bits;
-        if (!em) continue;
-        u64 x[kEmitSub];
-        u64 pl[DMAX][kEmitSub];
 #pragma unroll
-        for (int q = 0; q < kEmitSub; ++q) {
-          x[q] = sx[wl][q * 64 + lane];
+      for (int d = 0; d < DMAX; ++d)
+        if (d < D) {
+          const ulonglong2* pp = reinterpret_cast<const ulonglong2*>(a.planes[d] + base);
 #pragma unroll
-          for (int d = 0; d < DMAX; ++d) pl[d][q] = sp[d][wl][q * 64 + lane];
-        }
-        // lane b holds source (64 w + b)'s row pointer; each row is read from
-        // that lane instead of a memory load per row
-        const unsigned long long my_row = (unsigned long long)a.rows[w * 64 + lane];
-        while (em) {
-          const int b = __ffsll((unsigned long long)em) - 1;
-          em &= em - 1;
-          const unsigned lo = __shfl((unsigned)my_row, b, kWave);
-          const unsigned hi = __shfl((unsigned)(my_row >> 32), b, kWave);
-          int32_t* row = (int32_t*)(((unsigned long long)hi << 32) | lo);
-          if (!row) continue;
-          int val[kEmitSub];
-#pragma unroll
-          for (int q = 0; q < kEmitSub; ++q) {
-            val[q] = -1;
-            if ((x[q] >> b) & 1ull) {
-              val[q] = 0;
-#pragma unroll
-              for (int d = 0; d < DMAX; ++d) val[q] |= (int)((pl[d][q] >> b) & 1ull) << d;
-            }
+          for (int q = 0; q < EG / 2; ++q) {
+            const ulonglong2 t2 = pp[q];
+            pl[d][2 * q] = live ? t2.x : 0;
+            pl[d][2 * q + 1] = live ? t2.y : 0;
           }
-          // written once and not read again by the library: bypass the caches.
-          // A full tile of a 16-byte aligned row goes out as one 1 KiB store.
-          if (nv == kEmitTile && ((uintptr_t)row & 15u) == 0) {
-            const v4i vv = {val[0], val[1], val[2], val[3]};
-            __builtin_nontemporal_store(vv, reinterpret_cast<v4i*>(row + v0) + lane);
-          } else {
+        }
+    } else {
 #pragma unroll
-            for (int q = 0; q < kEmitSub; ++q) {
-              const int j = 4 * lane + q;
-              if (j < nv) __builtin_nontemporal_store(val[q], &row[v0 + j]);
-            }
+      for (int e = 0; e < EG; ++e) x[e] = live && e < ew ? a.vis[base + e] : 0;
+#pragma unroll
+      for (int d = 0; d < DMAX; ++d)
+        if (d < D) {
+#pragma unroll
+          for (int e = 0; e < EG; ++e)
+            if (live && e < ew) pl[d][e] = a.planes[d][base + e];
+        }
+    }
+#pragma unroll 1
+    for (int e = 0; e < ew; ++e) {
+      u64 em = emask[w0 + e];
+      if (!em) continue;
+      // word e of the staged rows, picked out with selects so that the
+      // staging arrays stay in registers
+      u64 xe = 0;
+      u64 pe[DMAX];
+#pragma unroll
+      for (int d = 0; d < DMAX; ++d) pe[d] = 0;
+#pragma unroll
+      for (int k = 0; k < EG; ++k)
+        if (k == e) {
+          xe = x[k];
+#pragma unroll
+          for (int d = 0; d < DMAX; ++d) pe[d] = pl[d][k];
+        }
+      if (clear && live) {
+        a.vis[base + e] = xe & ~em;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+          if (d < D) a.planes[d][base + e] = pe[d] & ~em;
+      }
+      // lane b holds source (64 w + b)'s row pointer; each row is read from
+      // that lane
+      const u64 my_row = srow[(w0 + e) * 64 + lane];
+      const unsigned voff = (unsigned)v * 4u;
+      // one half-word at a time so the bit tests are 32-bit field extracts
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        unsigned emh = (unsigned)(em >> (32 * h));
+        if (!emh) continue;
+        const unsigned xh = (unsigned)(xe >> (32 * h));
+        unsigned ph[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) ph[d] = (unsigned)(pe[d] >> (32 * h));
+        if (full) {
+          while (emh) {
+            const int bit = __builtin_ctz(emh);
+            emh &= emh - 1;
+            emit_one<DMAX>(my_row, 32 * h + bit, bit, xh, ph, voff);
+          }
+        } else {
+          while (emh) {
+            const int bit = __builtin_ctz(emh);
+            emh &= emh - 1;
+            if (live) emit_one<DMAX>(my_row, 32 * h + bit, bit, xh, ph, voff);
           }
         }
       }
@@ -874,10 +916,10 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   alloc((void**)&w->ctrl, sizeof(BatchCtrl));
   alloc((void**)&w->act, 64 * 8);
   alloc((void**)&w->emask, 64 * 8);
-  alloc((void**)&w->rows, (size_t)4096 * sizeof(int32_t*));
-  alloc((void**)&w->base, (size_t)4096 * 4);
-  alloc((void**)&w->src, (size_t)4096 * 4);
-  alloc((void**)&w->lane, (size_t)4096 * 4);
+  alloc((void**)&w->rows, (size_t)kMaxBatchLanes * sizeof(int32_t*));
+  alloc((void**)&w->base, (size_t)kMaxBatchLanes * 4);
+  alloc((void**)&w->src, (size_t)kMaxBatchLanes * 4);
+  alloc((void**)&w->lane, (size_t)kMaxBatchLanes * 4);
   if (stage_ints) alloc((void**)&w->stage, stage_ints * 4);
   w->stage_ints = stage_ints;
   if (s != DAWN_OK) {
@@ -1016,19 +1058,37 @@ dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t 
   return DAWN_OK;
 }
 
-dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
-                              bool clear, hipStream_t s) {
-  const int ntiles = (a.n + kEmitTile - 1) / kEmitTile;
-  const int grid = std::max(1, std::min(ntiles, ctx->num_cu * 8));
-  const int D = nplanes_used;
-  if (D <= 4)
-    hipLaunchKernelGGL(batch_emit<4>, dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask, clear ? 1 : 0);
-  else if (D <= 8)
-    hipLaunchKernelGGL(batch_emit<8>, dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask, clear ? 1 : 0);
-  else
-    hipLaunchKernelGGL(batch_emit<16>, dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask, clear ? 1 : 0);
+template <int DMAX, int EG>
+static dawn_status launch_emit_t(Ctx* ctx, const BatchArgs& a, int D, const u64* d_emask, bool clear,
+                                 hipStream_t s) {
+  // one resident wave per slot: the tasks are equal, so a grid larger than
+  // what fits at once would only add a tail
+  static std::atomic<int> occ_cache{0};
+  int occ = occ_cache.load(std::memory_order_relaxed);
+  if (!occ) {
+    DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_emit<DMAX, EG>, kBatchBlock, 0));
+    occ = std::max(occ, 1);
+    occ_cache.store(occ, std::memory_order_relaxed);
+  }
+  const long long tasks = (long long)((a.n + kWave - 1) / kWave) * ((a.W + EG - 1) / EG);
+  const long long per_block = kBatchBlock / kWave;
+  const int grid = (int)std::max<long long>(
+      1, std::min<long long>((tasks + per_block - 1) / per_block, (long long)ctx->num_cu * occ));
+  hipLaunchKernelGGL((batch_emit<DMAX, EG>), dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask,
+                     clear ? 1 : 0);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
+}
+
+// The level planes a lane holds take (1 + DMAX) x EG register pairs; the
+// word group shrinks as the planes grow so that stays at 64 words.
+dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
+                              bool clear, hipStream_t s) {
+  const int D = nplanes_used;
+  if (D <= 3) return launch_emit_t<3, 16>(ctx, a, D, d_emask, clear, s);
+  if (D <= 7) return launch_emit_t<7, 8>(ctx, a, D, d_emask, clear, s);
+  if (D <= 15) return launch_emit_t<15, 4>(ctx, a, D, d_emask, clear, s);
+  return launch_emit_t<16, 2>(ctx, a, D, d_emask, clear, s);
 }
 
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s) {
@@ -1150,7 +1210,7 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources, int32_t k,
                      int32_t* dist, bool device_out, int64_t row_stride, dawn_run_stats* stats) {
   const uint64_t t0 = now_ns();
-  const int lanes = std::min(p.batch_lanes, 4096);
+  const int lanes = std::min(p.batch_lanes, kMaxBatchLanes);
   const int kb_max = std::min(lanes, (int)k);
   const size_t stage = device_out ? 0 : (size_t)kb_max * (size_t)g->n;
   BatchWs* w = nullptr;
