@@ -31,8 +31,22 @@ struct BatchLevelSum {
   unsigned nchunks;
 };
 
+// State of a level loop that runs without the host: batch_control, run once
+// before each level's expansion, folds the previous level's counters into the
+// totals, sets the active-lane words and the direction, and raises `done`
+// when no lane is active; the expansion and merge kernels of that level and
+// of every later one then return at once.
+struct alignas(kLine) BatchRun {
+  int done;
+  int pull;                     // 1: the level being expanded pulls
+  int last_nonempty;            // last level that found new bits
+  int push_levels, pull_levels;
+  u64 edges, reached, source_edges;
+};
+
 struct BatchCtrl {
   BatchLevel lv[2];
+  BatchRun run;
   // OR of the new bits of each word, per level parity, striped like the
   // counters (a workgroup ORs into stripe blockIdx % kStripes)
   u64 laneact[2][kStripes][64];
@@ -71,6 +85,7 @@ struct BatchArgs {
   const u64* act;               // [W] sources still expanding
   int32_t* const* rows;         // [lanes] distance row of each source (device)
   const int32_t* base;          // [lanes] level at which each source joined
+  int32_t gated;                // expansion and merge obey ctrl->run (device-driven loop)
 };
 
 struct BatchWs {
@@ -123,6 +138,17 @@ dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t 
 dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
                               bool clear, hipStream_t s);
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
+// Clear up to kZeroMax arrays in one launch.
+constexpr int kZeroMax = 24;
+struct ZeroList {
+  u64* p[kZeroMax];
+  size_t count[kZeroMax];
+  int k;
+};
+dawn_status batch_launch_zero_list(Ctx* ctx, const ZeroList& z, hipStream_t s);
+// One level's control step of the device-driven loop (see BatchRun).
+dawn_status batch_launch_control(const BatchArgs& a, u64* act, int L, const dawn_params& p,
+                                 hipStream_t s);
 dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src,
                               const int32_t* d_lane, int k, int L, bool live, hipStream_t s);
 bool batch_choose_pull(const dawn_params& p, const BatchLevelSum& last, int n, int W);

@@ -208,6 +208,9 @@ struct GraphRec {
   // level launches the recent traversals needed (the direct-launch driver
   // queues about this many before its first host check)
   std::atomic<int> launch_hint{0};
+  // batched level loop: levels the last run launched before it saw the end
+  // (its expansions + 1), the size of the next run's first chunk
+  mutable std::atomic<int> batch_hint{0};
   size_t bytes = 0;
   dawn_params params{};
   std::mutex mu;                          // guards the pools and the WCC cache

@@ -233,8 +233,19 @@ __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, c
   return min(j, e) - s;
 }
 
+// In a device-driven loop a level's kernels check the run state first: all
+// of them stand down once no lane is active, and only the expansion of the
+// chosen direction (dir 0 push, 1 pull; -1 the merge) runs.
+__device__ __forceinline__ bool batch_gate_open(const BatchArgs& a, int dir) {
+  if (!a.gated) return true;
+  const BatchRun& r = a.ctrl->run;
+  if (ld_relaxed(&r.done)) return false;
+  return dir < 0 || ld_relaxed(&r.pull) == dir;
+}
+
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
+  if (!batch_gate_open(a, 1)) return;
   const int lane = lane_id();
   const int w = lane & (P - 1);
   const int npw = kWave / P;
@@ -370,6 +381,7 @@ __device__ __forceinline__ void relax_edge_sparse(const BatchArgs& a, const u64*
 
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
+  if (!batch_gate_open(a, 0)) return;
   const int lane = lane_id();
   const int w = lane & (P - 1);
   const int npw = kWave / P;
@@ -493,6 +505,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
 // bitmap of the previous frontier.
 template <int P>
 __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
+  if (!batch_gate_open(a, -1)) return;
   __shared__ u64 lmask[kMaxPlanes][64];   // bit b of (L - base) for the lanes of each word
   __shared__ u64 actb[64];
   __shared__ int rank_j[kBatchBlock / kWave][kWave];
@@ -822,6 +835,75 @@ __global__ __launch_bounds__(kBatchBlock) void batch_zero(u64* p, size_t count) 
     p[i] = 0;
 }
 
+// Row y of the grid clears array y of the list.
+__global__ __launch_bounds__(kBatchBlock) void batch_zero_list(ZeroList z) {
+  u64* p = z.p[blockIdx.y];
+  const size_t count = z.count[blockIdx.y];
+  for (size_t i = blockIdx.x * (size_t)kBatchBlock + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * kBatchBlock)
+    p[i] = 0;
+}
+
+// The host's per-level step of the batched loop, on the device (one wave):
+// level L - 1's counters go into the run totals, the lanes that found new
+// bits become the active words, the direction of level L is chosen by the
+// batched rule (pull iff the frontier's out-degree x nonzero words times
+// alpha reaches n x words), and level L's counter slot is cleared.
+__global__ __launch_bounds__(kWave) void batch_control(BatchArgs a, u64* act, int L, int direction,
+                                                      double alpha) {
+  BatchCtrl* c = a.ctrl;
+  BatchRun* r = &c->run;
+  if (ld_relaxed(&r->done)) return;
+  const int lane = lane_id();
+  const int pl = (L - 1) & 1, cl = L & 1;
+  const int W = a.W;
+  u64 x = 0;
+  if (lane < W)
+    for (int i = 0; i < kStripes; ++i) x |= c->laneact[pl][i][lane];
+  const bool any = __ballot(x != 0) != 0;
+  if (lane < W) act[lane] = x;
+  u64 bits = 0, se = 0, edges = 0, mfw = 0;
+  if (lane < kStripes) {
+    const BatchStripe& st = c->lv[pl].s[lane];
+    bits = st.bits;
+    se = st.se;
+    edges = st.edges;
+    mfw = st.mfw;
+  }
+  bits = wave_sum(bits);
+  se = wave_sum(se);
+  edges = wave_sum(edges);
+  mfw = wave_sum(mfw);
+  for (int i = lane; i < kStripes * 64; i += kWave) c->laneact[cl][i / 64][i % 64] = 0;
+  if (lane < kStripes) {
+    BatchStripe& st = c->lv[cl].s[lane];
+    st.nodes = 0;
+    st.bits = 0;
+    st.se = 0;
+    st.mf = 0;
+    st.edges = 0;
+    st.mfw = 0;
+  }
+  if (lane == 0) {
+    c->lv[cl].nchunks = 0;
+    r->edges += edges;
+    r->reached += bits;
+    r->source_edges += se;
+    if (bits) r->last_nonempty = L - 1;
+    if (!any) {
+      r->done = 1;
+    } else {
+      const bool pull = direction == 2 ||
+                        (direction != 1 && (double)mfw * alpha >= (double)a.n * (double)W);
+      r->pull = pull ? 1 : 0;
+      if (pull)
+        r->pull_levels += 1;
+      else
+        r->push_levels += 1;
+    }
+  }
+}
+
 // Lane lane[i] starts at node src[i] at level L: its bit joins the new bits
 // of level L (nxt) and the node joins that level's frontier bitmap.  With
 // `live` (sources admitted after level L's merge ran) the seed also does the
@@ -1100,6 +1182,25 @@ dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s) {
   return DAWN_OK;
 }
 
+dawn_status batch_launch_zero_list(Ctx* ctx, const ZeroList& z, hipStream_t s) {
+  if (z.k <= 0) return DAWN_OK;
+  if (z.k > kZeroMax) return fail(DAWN_E_INVALID_ARG, "too many arrays to clear");
+  size_t most = 1;
+  for (int i = 0; i < z.k; ++i) most = std::max(most, z.count[i]);
+  const int gx = (int)std::min<size_t>((most + kBatchBlock - 1) / kBatchBlock, (size_t)ctx->num_cu * 4);
+  hipLaunchKernelGGL(batch_zero_list, dim3(gx, z.k), dim3(kBatchBlock), 0, s, z);
+  DAWN_HIP(hipGetLastError());
+  return DAWN_OK;
+}
+
+dawn_status batch_launch_control(const BatchArgs& a, u64* act, int L, const dawn_params& p,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(batch_control, dim3(1), dim3(kWave), 0, s, a, act, L, p.direction,
+                     (double)p.batch_alpha);
+  DAWN_HIP(hipGetLastError());
+  return DAWN_OK;
+}
+
 dawn_status batch_launch_seed(Ctx* ctx, const BatchArgs& a, const int32_t* d_src,
                               const int32_t* d_lane, int k, int L, bool live, hipStream_t s) {
   (void)ctx;
@@ -1147,54 +1248,75 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
                           hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemcpyAsync(w->base, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemcpyAsync(w->emask, em.data(), (size_t)W * 8, hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemsetAsync(w->ctrl, 0, sizeof(BatchCtrl), s));
   DAWN_HIP(hipEventRecord(w->ev0, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->vis, nW, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->nxt[0], nW, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->nxt[1], nW, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->touched[0], ((size_t)g->n + 63) / 64, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->touched[1], ((size_t)g->n + 63) / 64, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->fmap[0], (size_t)g->n, s));
-  DAWN_TRY(batch_launch_zero(ctx, w->fmap[1], (size_t)g->n, s));
-  for (int b = 0; b < w->planes_dirty; ++b) DAWN_TRY(batch_launch_zero(ctx, w->planes[b], nW, s));
+  {
+    ZeroList z;
+    memset(&z, 0, sizeof(z));
+    auto add = [&z](void* p, size_t count) {
+      z.p[z.k] = (u64*)p;
+      z.count[z.k++] = count;
+    };
+    const size_t nwords = ((size_t)g->n + 63) / 64;
+    add(w->ctrl, sizeof(BatchCtrl) / 8);
+    add(w->vis, nW);
+    add(w->nxt[0], nW);
+    add(w->nxt[1], nW);
+    add(w->touched[0], nwords);
+    add(w->touched[1], nwords);
+    add(w->fmap[0], (size_t)g->n);
+    add(w->fmap[1], (size_t)g->n);
+    for (int b = 0; b < w->planes_dirty; ++b) add(w->planes[b], nW);
+    DAWN_TRY(batch_launch_zero_list(ctx, z, s));
+  }
   w->planes_dirty = 0;
   BatchArgs a = batch_args(g, w, W);
+  a.gated = 1;
   DAWN_TRY(batch_launch_seed(ctx, a, w->src, w->lane, k, 0, false, s));
   DAWN_TRY(batch_launch_merge(ctx, a, 0, s));
-  int launches = 9 + w->planes_dirty;
-  int last_nonempty = 0;
-  for (int L = 1;; ++L) {
-    const int pl = (L - 1) & 1;
-    DAWN_HIP(hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, s));
-    DAWN_HIP(hipStreamSynchronize(s));
-    const BatchLevelSum prev = batch_level_sum(w->h_ctrl->lv[pl]);
-    tot->edges += prev.edges;
-    tot->reached += prev.bits;
-    tot->source_edges += prev.se;
-    if (prev.bits) last_nonempty = L - 1;
-    bool any = false;
-    for (int i = 0; i < W; ++i) {
-      w->h_act[i] = lane_activity(*w->h_ctrl, pl, i);
-      any |= w->h_act[i] != 0;
-    }
-    if (!any) break;
+  int launches = 3;
+  // Levels go out in chunks without a host round trip: batch_control picks
+  // each level's direction on the device and stops the run, after which the
+  // chunk's remaining launches return at once.  The host reads the run state
+  // once per chunk; the first chunk is as long as the graph's last run.
+  int L = 1;
+  const int hint = g->batch_hint.load(std::memory_order_relaxed);
+  int chunk = hint > 0 ? hint : 4;
+  for (;;) {
     if (L > g->n + 1) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
-    const int need = bit_length(L);
+    if (bit_length(L) > kMaxPlanes)
+      return fail(DAWN_E_DEVICE, "batched traversal exceeds %d levels", (1 << kMaxPlanes) - 1);
+    int Lend = L + chunk - 1;
+    while (bit_length(Lend) > kMaxPlanes) --Lend;
+    const int need = bit_length(Lend);
     if (need > w->nplanes) {
       DAWN_TRY(batch_ensure_planes(w, need, W));
       a = batch_args(g, w, W);
+      a.gated = 1;
     }
     w->planes_dirty = std::max(w->planes_dirty, need);
-    // active lanes and a clean slot for this level
-    DAWN_HIP(hipMemcpyAsync(w->act, w->h_act, (size_t)W * 8, hipMemcpyHostToDevice, s));
-    DAWN_HIP(hipMemsetAsync(&w->ctrl->lv[L & 1], 0, sizeof(BatchLevel), s));
-    DAWN_HIP(hipMemsetAsync(&w->ctrl->laneact[L & 1], 0, sizeof(w->ctrl->laneact[0]), s));
-    const bool pull = batch_choose_pull(p, prev, g->n, W);
-    DAWN_TRY(batch_launch_expand(ctx, a, pull, L, s));
-    DAWN_TRY(batch_launch_merge(ctx, a, L, s));
-    launches += 2;
-    if (pull) tot->pull_levels++; else tot->push_levels++;
+    for (int l = L; l <= Lend; ++l) {
+      DAWN_TRY(batch_launch_control(a, w->act, l, p, s));
+      DAWN_TRY(batch_launch_expand(ctx, a, false, l, s));
+      DAWN_TRY(batch_launch_expand(ctx, a, true, l, s));
+      DAWN_TRY(batch_launch_merge(ctx, a, l, s));
+      launches += 4;
+    }
+    DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->run, &w->ctrl->run, sizeof(BatchRun),
+                            hipMemcpyDeviceToHost, s));
+    DAWN_HIP(hipStreamSynchronize(s));
+    if (w->h_ctrl->run.done) break;
+    L = Lend + 1;
+    chunk = std::min(chunk * 2, 64);
   }
+  const BatchRun run = w->h_ctrl->run;
+  tot->edges += run.edges;
+  tot->reached += run.reached;
+  tot->source_edges += run.source_edges;
+  tot->push_levels += run.push_levels;
+  tot->pull_levels += run.pull_levels;
+  const int last_nonempty = run.last_nonempty;
+  // expansions 1 .. last_nonempty + 1, then the control step that ends the run
+  g->batch_hint.store(std::min(last_nonempty + 2, 64), std::memory_order_relaxed);
   DAWN_TRY(batch_launch_emit(ctx, a, bit_length(last_nonempty), w->emask, false, s));
   launches += 1;
   DAWN_HIP(hipEventRecord(w->ev1, s));
