@@ -74,7 +74,7 @@ struct BatchArgs {
   u64* vis;                     // [n][W]
   u64* nxt[2];                  // [n][W] new bits per level parity
   u64* planes[kMaxPlanes];      // [n][W] bit b of each source's relative level
-  int32_t nplanes;              // planes allocated (levels < 2^nplanes)
+  int32_t nplanes;              // planes in use (levels < 2^nplanes)
   u64* touched[2];              // one bit per node with new bits at a level of that
                                 //   parity: the frontier of the next level
   u64* fmap[2];                 // [n] bit w set iff word w of the node's nxt row of

@@ -553,12 +553,22 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
       const int cnt = __popcll(fw);
       if ((fw >> lane) & 1ull) rank_j[wv][__popcll(fw & lanes_below())] = lane;
       __builtin_amdgcn_wave_barrier();
-      for (int i0 = 0; i0 < cnt; i0 += npw) {
-        const int i = i0 + sub;
-        if (i < cnt && wok) {
-          const int v = (int)t * 64 + rank_j[wv][i];
-          prev[(size_t)v * Ws + w] = 0;
-          if (w == 0) pmap[v] = 0;
+      // only the words the frontier word map marks nonzero need clearing
+      // (a sparse row has one or two of them)
+      for (int i0 = 0; i0 < cnt; i0 += 4 * npw) {
+        int vq[4];
+        u64 pm[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + q * npw + sub;
+          vq[q] = i < cnt ? (int)t * 64 + rank_j[wv][i] : -1;
+          pm[q] = vq[q] >= 0 ? pmap[vq[q]] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (vq[q] < 0) continue;
+          if (wok && ((pm[q] >> w) & 1ull)) prev[(size_t)vq[q] * Ws + w] = 0;
+          if (w == 0 && pm[q]) pmap[vq[q]] = 0;
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -728,9 +738,12 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
     const int w0 = (int)(t / ntiles) * EG;
     const int v = (int)(t % ntiles) * kWave + lane;
     const int ew = min(EG, W - w0);
-    bool any = false;
-    for (int e = 0; e < ew; ++e) any |= emask[w0 + e] != 0;
-    if (!any) continue;
+    // words of the group with emitted lanes: only those are loaded (serving
+    // emits a few lanes at a time)
+    unsigned wm = 0;
+    for (int e = 0; e < ew; ++e)
+      if (emask[w0 + e]) wm |= 1u << e;
+    if (!wm) continue;
     const bool live = v < a.n;
     const bool full = (int)(t % ntiles) * kWave + kWave <= a.n;  // no lane past the last node
     const size_t base = (size_t)(live ? v : 0) * Ws + w0;
@@ -748,30 +761,34 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
       const ulonglong2* pv = reinterpret_cast<const ulonglong2*>(a.vis + base);
 #pragma unroll
       for (int q = 0; q < EG / 2; ++q) {
-        const ulonglong2 t2 = pv[q];
-        x[2 * q] = live ? t2.x : 0;
-        x[2 * q + 1] = live ? t2.y : 0;
+        x[2 * q] = x[2 * q + 1] = 0;
+        if ((wm >> (2 * q)) & 3u) {
+          const ulonglong2 t2 = pv[q];
+          x[2 * q] = live ? t2.x : 0;
+          x[2 * q + 1] = live ? t2.y : 0;
+        }
       }
 #pragma unroll
       for (int d = 0; d < DMAX; ++d)
         if (d < D) {
           const ulonglong2* pp = reinterpret_cast<const ulonglong2*>(a.planes[d] + base);
 #pragma unroll
-          for (int q = 0; q < EG / 2; ++q) {
-            const ulonglong2 t2 = pp[q];
-            pl[d][2 * q] = live ? t2.x : 0;
-            pl[d][2 * q + 1] = live ? t2.y : 0;
-          }
+          for (int q = 0; q < EG / 2; ++q)
+            if ((wm >> (2 * q)) & 3u) {
+              const ulonglong2 t2 = pp[q];
+              pl[d][2 * q] = live ? t2.x : 0;
+              pl[d][2 * q + 1] = live ? t2.y : 0;
+            }
         }
     } else {
 #pragma unroll
-      for (int e = 0; e < EG; ++e) x[e] = live && e < ew ? a.vis[base + e] : 0;
+      for (int e = 0; e < EG; ++e) x[e] = live && ((wm >> e) & 1u) ? a.vis[base + e] : 0;
 #pragma unroll
       for (int d = 0; d < DMAX; ++d)
         if (d < D) {
 #pragma unroll
           for (int e = 0; e < EG; ++e)
-            if (live && e < ew) pl[d][e] = a.planes[d][base + e];
+            if (live && ((wm >> e) & 1u)) pl[d][e] = a.planes[d][base + e];
         }
     }
 #pragma unroll 1

@@ -297,6 +297,8 @@ static dawn_status launch_level(Server* S, Engine* e) {
     DAWN_TRY(batch_ensure_planes(w, need, e->W));
     a = batch_args(g, w, e->W, Wa);
   }
+  // the merge writes only the planes a running lane's level can reach
+  a.nplanes = std::min(a.nplanes, std::max(need, 1));
   for (int i = 0; i < e->W; ++i) e->h_act[i] = e->act[i];
   DAWN_HIP(hipMemcpyAsync(w->act, e->h_act, (size_t)e->W * 8, hipMemcpyHostToDevice, s));
   DAWN_HIP(hipMemsetAsync(&w->ctrl->lv[(L + 1) & 1], 0, sizeof(BatchLevel), s));
@@ -352,7 +354,11 @@ static dawn_status level_done(Server* S, Engine* e) {
       break;
     }
   BatchArgs a = batch_args(e->g.get(), w, e->W, We);
-  DAWN_TRY(batch_launch_emit(S->ctx, a, w->nplanes, w->emask, true, s));
+  // planes that can hold a bit of a finished lane: its levels reach L - base
+  int min_base = L;
+  for (Query* q : done) min_base = std::min(min_base, q->base);
+  const int D = std::min(w->nplanes, bit_length(L - min_base));
+  DAWN_TRY(batch_launch_emit(S->ctx, a, D, w->emask, true, s));
   for (Query* q : done) {
     hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
     hipEventRecord(q->ev, s);
