@@ -490,8 +490,7 @@ __device__ void decide(const SsspArgs& a, LevelState& st, const SlotSum& sl, boo
 
 // Seed the source (one thread; slots 1 and 2 are zeroed by the caller).
 template <int BLOCK>
-__device__ void seed(const SsspArgs& a) {
-  const int s = a.ctrl->source;
+__device__ void seed(const SsspArgs& a, int s) {
   const int deg = a.rp[s + 1] - a.rp[s];
   LevelSlot* sl = &a.ctrl->slot[0];
   sl->s[0].nf = 1;
@@ -524,8 +523,7 @@ __device__ void seed(const SsspArgs& a) {
 }
 
 // dist = -1 except dist[s] = 0, visited = {s}, all counter slots zero.
-__device__ __forceinline__ void init_fill(const SsspArgs& a) {
-  const int s = a.ctrl->source;
+__device__ __forceinline__ void init_fill(const SsspArgs& a, int s) {
   const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned nt = gridDim.x * blockDim.x;
   for (unsigned i = tid; i < (unsigned)a.n; i += nt) a.dist[i] = (int)i == s ? 0 : -1;
@@ -547,9 +545,9 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
   __shared__ unsigned big_n;
   if (threadIdx.x == 0) big_n = 0;
   WaveQueue q{qbuf[threadIdx.x / kWave], 0, big_v, big_c, &big_n};
-  init_fill(a);
+  init_fill(a, a0.ctrl->source);
   if (!grid_sync(&a.ctrl->bar)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) seed<BLOCK>(a);
+  if (blockIdx.x == 0 && threadIdx.x == 0) seed<BLOCK>(a, a0.ctrl->source);
   if (!grid_sync(&a.ctrl->bar)) return;
 
   LevelState st;
@@ -724,13 +722,29 @@ __global__ __launch_bounds__(BLOCK) void sssp_component(SsspArgs a0) {
 // ------------------------------------------------------ per-level drivers --
 // Initial state of one traversal (the source is read from the control block).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0) {
+// The output row and source come as arguments (direct launches), or with
+// dist == nullptr from the control block, where the host copied them (a
+// captured graph or the persistent kernel must not depend on them).  Direct
+// launches publish them there for the level kernels.
+__global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0, int32_t* dist, int source) {
   SsspArgs a = a0;
-  a.dist = a0.ctrl->dist;
-  init_fill(a);
+  int s = source;
+  if (dist) {
+    a.dist = dist;
+  } else {
+    a.dist = a0.ctrl->dist;
+    s = a0.ctrl->source;
+  }
+  init_fill(a, s);
   if (blockIdx.x == 0) {
     __syncthreads();
-    if (threadIdx.x == 0) seed<BLOCK>(a);
+    if (threadIdx.x == 0) {
+      if (dist) {
+        a0.ctrl->dist = dist;
+        a0.ctrl->source = source;
+      }
+      seed<BLOCK>(a, s);
+    }
   }
 }
 
@@ -961,12 +975,13 @@ static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStre
 
 template <int BLOCK>
 static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& a, int grid,
-                              size_t shmem, int driver, int graph_levels, int* launches,
-                              double* level_ms, int* final_parity) {
+                              size_t shmem, int driver, int graph_levels, int32_t* d_dist,
+                              int source, int* launches, double* level_ms, int* final_parity) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
   const long long max_launch = (long long)a.n + 2;
   if (driver == 2) {
-    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
+                       source);
     DAWN_HIP(hipGetLastError());
     *launches = 1;
     int level_launches = 0;
@@ -1001,7 +1016,8 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
     // their level count, for the launch that sees the end), so a typical
     // traversal costs one host check and few launches past its end; a
     // launch after the end only carries the final state along.
-    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
+                       source);
     *launches = 1;
     const int hint = g->launch_hint.load(std::memory_order_relaxed);
     int batch = hint > 0 ? std::min(hint + 1, graph_levels * 4) : graph_levels;
@@ -1039,7 +1055,8 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
   }
   if (!w->gexec) {
     DAWN_TRY(capture(&w->gexec, [&](hipStream_t cs) {
-      hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, cs, a);
+      hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, cs, a,
+                         (int32_t*)nullptr, 0);
       for (int i = 0; i < graph_levels; ++i)
         hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
     }));
@@ -1076,11 +1093,12 @@ static bool small_component(const GraphRec* g, const dawn_params& p, int32_t sou
 
 template <int BLOCK>
 static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_params& p,
-                                 SsspArgs& a, int32_t source, int* launches, double* level_ms,
-                                 int* final_parity) {
+                                 SsspArgs& a, int32_t source, int32_t* d_dist, int* launches,
+                                 double* level_ms, int* final_parity) {
   if (small_component(g, p, source)) {
     const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
-    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a);
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
+                       source);
     hipLaunchKernelGGL(sssp_component<BLOCK>, dim3(1), dim3(BLOCK), 0, w->stream, a);
     DAWN_HIP(hipGetLastError());
     *launches = 2;
@@ -1108,7 +1126,8 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
   DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, shmem));
   int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
   return run_levels<BLOCK>(ctx, g, w, a, per_cu * ctx->num_cu, shmem, p.driver,
-                           std::max(p.graph_levels, 1), launches, level_ms, final_parity);
+                           std::max(p.graph_levels, 1), d_dist, source, launches, level_ms,
+                           final_parity);
 }
 
 dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source, int32_t* dist,
@@ -1144,16 +1163,20 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   double* lm = level_timing ? &level_ms : nullptr;
   int fp = 1;
   const uint64_t t_setup = now_ns();
-  w->h_ctrl->dist = d_dist;
-  w->h_ctrl->source = source;
-  DAWN_HIP(hipMemcpyAsync(&w->ctrl->dist, &w->h_ctrl->dist, sizeof(int32_t*) + sizeof(int),
-                          hipMemcpyHostToDevice, w->stream));
+  // the persistent kernel and captured graphs read the row and source from
+  // the control block; direct launches hand them to the init kernel
+  if (!small && (p.driver == 1 || p.driver == 4)) {
+    w->h_ctrl->dist = d_dist;
+    w->h_ctrl->source = source;
+    DAWN_HIP(hipMemcpyAsync(&w->ctrl->dist, &w->h_ctrl->dist, sizeof(int32_t*) + sizeof(int),
+                            hipMemcpyHostToDevice, w->stream));
+  }
   DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
-    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, source, &launches, lm, &fp); break;
-    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, &launches, lm, &fp); break;
-    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, &launches, lm, &fp); break;
+    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp); break;
+    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp); break;
+    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp); break;
   }
   if (!level_timing) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
