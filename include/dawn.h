@@ -186,7 +186,9 @@ dawn_status dawn_sssp(dawn_ctx *ctx, int32_t graph, int32_t source, int32_t *dis
  * from sources[r] (host array of k ids; repeats allowed and give equal rows).
  * Up to `batch_lanes` sources share one bitmask batch: one bit per source in
  * 64-bit words per node, and one level step advances all of them (the level
- * step of Algorithms 1/2 applied per bit).  k == 0 is a no-op.
+ * step of Algorithms 1/2 applied per bit).  Each level's direction and the
+ * end of the run are decided on the device; the host checks a batch once per
+ * chunk of queued levels.  k == 0 is a no-op.
  * Errors: INVALID_ARG, NOT_FOUND, NO_MEMORY, DEVICE. */
 dawn_status dawn_mssp(dawn_ctx *ctx, int32_t graph, const int32_t *sources, int32_t k,
                       int32_t *dist, uint32_t flags, dawn_run_stats *stats);

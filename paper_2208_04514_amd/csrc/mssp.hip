@@ -26,6 +26,11 @@
 // pass that rebuilds each level from the planes and stores every row as
 // whole 256-byte segments (64 consecutive nodes), -1 where the source's bit
 // never arrived; no row is touched while the levels run.
+//
+// dawn_mssp and APSP run the level loop on the device: a one-wave control
+// kernel before each level applies the direction rule and ends the run, and
+// the host only enqueues levels in chunks.  Serving steps levels from the
+// host, where it admits and retires queries.
 #include <string.h>
 
 #include <algorithm>
@@ -193,39 +198,65 @@ __device__ __forceinline__ u64 group_read64(u64 x, int gb, int i) {
 // Per lane r, an unvisited v has an in-neighbour visited in r iff it has one
 // whose bit r is new at level L - 1, and the two give the same bits of
 // `need`: the scan reads the previous level's new rows, and only the words
-// that the frontier word map marks nonzero.  The group reads P in-edges and
-// their map words at a time (lane i takes edge i), then walks the edges whose
-// source is on the frontier, each lane loading its own word of those rows.
+// that the frontier word map marks nonzero.  The group reads EPL x P in-edges
+// and their map words at a time (lane i takes edges i, i + P, ...: narrow
+// groups take several, so a short row still keeps loads in flight), then
+// walks the edges whose source is on the frontier, each lane loading its own
+// word of those rows.
 template <int P>
 __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, const u64* fm, int s,
                                          int e, u64 need, int w, int gb, u64 gm, u64& acc) {
+  constexpr int EPL = P >= 16 ? 1 : 16 / P;
   const size_t W = (size_t)a.Ws;
   int j = s;
   while (j < e) {
-    int my_u = 0;
-    u64 my_m = 0;
-    if (j + w < e) {
-      my_u = a.isrc[j + w];
-      my_m = fm[my_u];
+    int my_u[EPL];
+    u64 my_m[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+      my_u[k] = 0;
+      my_m[k] = 0;
+      if (j + k * P + w < e) my_u[k] = a.isrc[j + k * P + w];
     }
-    j += P;
-    u64 hits = (__ballot(my_m != 0) & gm) >> gb;    // bit i: edge i's source is on the frontier
+#pragma unroll
+    for (int k = 0; k < EPL; ++k)
+      if (j + k * P + w < e) my_m[k] = fm[my_u[k]];
+    j += EPL * P;
     u64 r = 0;
-    while (hits) {
-      u64 val[8];
+    if constexpr (P <= 8) {
+      // narrow group: every (slot k, lane i) edge's word is loaded at once
+      const bool want = acc != need;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        val[q] = 0;
-        if (hits) {
-          const int i = __builtin_ctzll(hits);
-          hits &= hits - 1;
-          const int u = group_read<P>(my_u, gb, i);
-          const u64 m = group_read64<P>(my_m, gb, i);
-          if (((m >> w) & 1ull) && acc != need) val[q] = front[(size_t)u * W + w];
+      for (int k = 0; k < EPL; ++k)
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const int u = group_read<P>(my_u[k], gb, i);
+          const u64 m = group_read64<P>(my_m[k], gb, i);
+          if (want && ((m >> w) & 1ull)) r |= front[(size_t)u * W + w];
         }
-      }
+      acc |= r & need;
+      if ((__ballot(acc != need) & gm) == 0) break;
+      continue;
+    }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) r |= val[q];
+    for (int k = 0; k < EPL; ++k) {
+      u64 hits = (__ballot(my_m[k] != 0) & gm) >> gb;   // bit i: edge i's source is on the frontier
+      while (hits) {
+        u64 val[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          val[q] = 0;
+          if (hits) {
+            const int i = __builtin_ctzll(hits);
+            hits &= hits - 1;
+            const int u = group_read<P>(my_u[k], gb, i);
+            const u64 m = group_read64<P>(my_m[k], gb, i);
+            if (((m >> w) & 1ull) && acc != need) val[q] = front[(size_t)u * W + w];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r |= val[q];
+      }
     }
     acc |= r & need;
     if ((__ballot(acc != need) & gm) == 0) break;
@@ -265,8 +296,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
 
   // long in-lists: one chunk of kPullChunk in-edges per lane group, the
   // chunks of a node OR their bits into its row
-  for (unsigned cb = gw * npw; cb < (unsigned)a.npc; cb += nwaves * npw) {
-    const unsigned c = cb + (unsigned)sub;
+  for (unsigned it = 0; gw + nwaves * npw * it < (unsigned)a.npc; ++it) {
+    // spread over the waves first: chunk gw + nwaves (sub + npw it)
+    const unsigned c = gw + nwaves * ((unsigned)sub + npw * it);
     const bool has = c < (unsigned)a.npc;
     int v = 0, s = 0, e = 0;
     u64 need = 0;
@@ -399,10 +431,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
   const unsigned gw = (blockIdx.x * kBatchBlock + threadIdx.x) / kWave;
   const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
 
-  // big-degree frontier nodes: chunks of kChunkB out-edges, one per lane group
+  // big-degree frontier nodes: chunks of kChunkB out-edges, one per lane
+  // group, spread over the waves first (chunk gw + nwaves (sub + npw it))
   const unsigned nch = ld_relaxed(&a.ctrl->lv[pl].nchunks);
-  for (unsigned cb = gw * npw; cb < nch; cb += nwaves * npw) {
-    const unsigned c = cb + (unsigned)sub;
+  for (unsigned it = 0; gw + nwaves * npw * it < nch; ++it) {
+    const unsigned c = gw + nwaves * ((unsigned)sub + npw * it);
     const bool has = c < nch;
     int e0 = 0, e1 = 0, u = 0;
     u64 f = 0, fmu = 0;
@@ -414,11 +447,24 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
       fmu = fmp[u];
     }
     if (has && w == 0) edges += (u64)(e1 - e0);
-    if (__popcll(fmu) <= kSparseWords) {
-      // few nonzero words: lane w of the group takes edges e0 + w, e0 + w + P, ...
-      for (int e = e0 + w; e < e1; e += P) relax_edge_sparse(a, front, out, T, u, a.col[e], fmu);
-      continue;
+    const bool sparse = has && __popcll(fmu) <= kSparseWords;
+    // chunks with few nonzero words: the wave walks the union of its groups'
+    // sparse chunks, one edge per lane
+    const int cnt = (sparse && w == 0) ? e1 - e0 : 0;
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    for (int eb = 0; eb < total; eb += kWave) {
+      const int x = eb + lane;
+      const bool in = x < total;
+      const int j = wave_owner(incl, in ? x : total - 1);
+      const int inc_j = __shfl(incl, j, kWave);
+      const int cnt_j = __shfl(cnt, j, kWave);
+      const int e0_j = __shfl(e0, j, kWave);
+      const int u_j = __shfl(u, j, kWave);
+      const u64 fm_j = shfl64(fmu, j);
+      if (in) relax_edge_sparse(a, front, out, T, u_j, a.col[e0_j + (x - (inc_j - cnt_j))], fm_j);
     }
+    if (!has || sparse) continue;
     if (wok && ((fmu >> w) & 1ull)) f = front[(size_t)u * W + w];
     // group-uniform steps of four edges (past e1: no bits)
     for (int e = e0; e < e1; e += 4) {

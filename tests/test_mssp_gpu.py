@@ -95,6 +95,22 @@ def test_many_batches(ctx, upload, params):
     _check_rows(g, srcs, got, st)
 
 
+def test_level_chunks_deep_then_shallow(ctx, upload):
+    """The device-driven loop queues levels in chunks sized from the graph's
+    last run: a deep run after a shallow one needs further chunks, a shallow
+    run after a deep one leaves queued levels that must do nothing."""
+    h, g, _ = upload("grid128ns")
+    want0 = oracle.sssp(g, 0)
+    far = int(np.argmax(want0))                  # deepest node from corner 0
+    mid = int(np.argsort(want0)[g.n // 2])       # a node half-way in
+    runs = [np.array([0, far], np.int32), np.array([mid], np.int32),
+            np.array([0], np.int32), np.array([mid, far, 0], np.int32)]
+    for src in runs:
+        _say(f"[mssp] grid128ns chunked levels sources={src.tolist()}")
+        got, st = D.dawn_mssp(ctx, h, src)
+        _check_rows(g, src, got, st)
+
+
 @pytest.mark.parametrize("k", [4095, 4096, 4097, 5000])
 def test_batch_edges(ctx, upload, k):
     h, g, _ = upload("uniform4096")
