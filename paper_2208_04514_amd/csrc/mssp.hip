@@ -264,6 +264,47 @@ __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, c
   return min(j, e) - s;
 }
 
+// Narrow batched rows (<= 8 words): an in-list longer than this is scanned
+// by the whole wave, 64 edges per step.
+constexpr int kWideScan = 48;
+
+// Narrow rows (W <= P <= 8 words): the whole wave scans in-edges [s, e) of
+// one node, one edge per lane and step, and ORs each word's bits across the
+// wave.  needw / accw: the node's needed and found bits per word
+// (wave-uniform).  Returns the number of in-edges read (wave-uniform call).
+template <int P>
+__device__ __forceinline__ int wave_scan(const BatchArgs& a, const u64* front, const u64* fm, int s,
+                                         int e, const u64* needw, u64* accw) {
+  const size_t W = (size_t)a.Ws;
+  const int lane = lane_id();
+  int j = s;
+  while (j < e) {
+    int u = 0;
+    u64 m = 0;
+    if (j + lane < e) {
+      u = a.isrc[j + lane];
+      m = fm[u];
+    }
+    j += kWave;
+    u64 loc[P];
+#pragma unroll
+    for (int x = 0; x < P; ++x) {
+      loc[x] = 0;
+      if (x < a.W && ((m >> x) & 1ull) && accw[x] != needw[x]) loc[x] = front[(size_t)u * W + x];
+    }
+    bool done = true;
+#pragma unroll
+    for (int x = 0; x < P; ++x) {
+      u64 r = loc[x] & needw[x];
+      for (int off = 1; off < kWave; off <<= 1) r |= shfl_xor64(r, off);
+      accw[x] |= r;
+      done = done && accw[x] == needw[x];
+    }
+    if (done) break;
+  }
+  return min(j, e) - s;
+}
+
 // In a device-driven loop a level's kernels check the run state first: all
 // of them stand down once no lane is active, and only the expansion of the
 // chosen direction (dir 0 push, 1 pull; -1 the merge) runs.
@@ -294,6 +335,35 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
   const unsigned gw = (blockIdx.x * kBatchBlock + threadIdx.x) / kWave;
   const unsigned nwaves = gridDim.x * kBatchBlock / kWave;
 
+  if constexpr (P <= 8) {
+    // narrow rows: a wave per chunk of a long in-list
+    for (unsigned c = gw; c < (unsigned)a.npc; c += nwaves) {
+      const int v = a.pcv[c];
+      const int s = a.ip[v] + a.pck[c] * kPullChunk;
+      const int e = min(s + kPullChunk, a.ip[v + 1]);
+      const u64 mine = lane < a.W ? a.act[lane] & ~a.vis[(size_t)v * W + lane] : 0ull;
+      u64 needw[P], accw[P];
+      bool any_need = false;
+#pragma unroll
+      for (int x = 0; x < P; ++x) {
+        needw[x] = shfl64(mine, x);
+        accw[x] = 0;
+        any_need = any_need || needw[x] != 0;
+      }
+      if (!any_need) continue;
+      const int nr = wave_scan<P>(a, front, fm, s, e, needw, accw);
+      if (lane == 0) edges += (u64)nr;
+      u64 got = 0;
+#pragma unroll
+      for (int x = 0; x < P; ++x)
+        if (x == lane) got = accw[x];
+      if (got) atom_or(&nxt[(size_t)v * W + lane], got);
+      bool any = false;
+#pragma unroll
+      for (int x = 0; x < P; ++x) any = any || accw[x] != 0;
+      if (any && lane == 0) atom_or(&T[v >> 6], 1ull << (v & 63));
+    }
+  } else {
   // long in-lists: one chunk of kPullChunk in-edges per lane group, the
   // chunks of a node OR their bits into its row
   for (unsigned it = 0; gw + nwaves * npw * it < (unsigned)a.npc; ++it) {
@@ -318,6 +388,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     const bool any = (__ballot(acc != 0) & gm) != 0;
     if (any && w == 0) atom_or(&T[v >> 6], 1ull << (v & 63));
   }
+  }
 
   for (unsigned base = gw * npw; base < (unsigned)a.n; base += nwaves * npw) {
     const int v = (int)base + sub;
@@ -330,14 +401,45 @@ __global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
     const bool mine = valid && e - s < kPullBig;     // long in-lists went by chunks
     const u64 vw = (mine && wok) ? a.vis[(size_t)v * W + w] : ~0ull;
     const u64 need = (mine && wok) ? (actw & ~vw) : 0ull;
+    const u64 gneed = __ballot(need != 0) & gm;
+    // narrow rows: in-lists of more than kWideScan entries go to the whole
+    // wave below instead of the node's few lanes
+    const bool wide = P <= 8 && e - s > kWideScan;
     u64 acc = 0;
-    if ((__ballot(need != 0) & gm) != 0) {
+    if (gneed != 0 && !wide) {
       const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gb, gm, acc);
       if (w == 0) edges += (u64)nr;
     }
     if (acc) nxt[(size_t)v * W + w] = acc;
     const bool any = (__ballot(acc != 0) & gm) != 0;
     if (any && w == 0) atom_or(&T[v >> 6], 1ull << (v & 63));
+    if constexpr (P <= 8) {
+      u64 lead = __ballot(wide && gneed != 0 && w == 0);
+      while (lead) {
+        const int ld = __ffsll((unsigned long long)lead) - 1;
+        lead &= lead - 1;
+        const int vv = __builtin_amdgcn_readlane(v, ld);
+        const int ss = __builtin_amdgcn_readlane(s, ld);
+        const int ee = __builtin_amdgcn_readlane(e, ld);
+        u64 needw[P], accw[P];
+#pragma unroll
+        for (int x = 0; x < P; ++x) {
+          needw[x] = shfl64(need, ld + x);
+          accw[x] = 0;
+        }
+        const int nr = wave_scan<P>(a, front, fm, ss, ee, needw, accw);
+        if (lane == 0) edges += (u64)nr;
+        u64 got = 0;
+#pragma unroll
+        for (int x = 0; x < P; ++x)
+          if (x == lane) got = accw[x];
+        if (got) nxt[(size_t)vv * W + lane] = got;
+        bool anyw = false;
+#pragma unroll
+        for (int x = 0; x < P; ++x) anyw = anyw || accw[x] != 0;
+        if (anyw && lane == 0) atom_or(&T[vv >> 6], 1ull << (vv & 63));
+      }
+    }
   }
   block_add_edges(a, L, edges);
 }
