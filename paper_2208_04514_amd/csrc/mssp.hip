@@ -728,15 +728,19 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   u64* fmap = a.fmap[cl];
   const u64* T = a.touched[cl];
   u64 act_acc = 0, bits = 0, se = 0, nodes = 0, mf = 0, mfw = 0;
-  // a work unit is a quarter of a frontier word (ranks 16 s .. 16 s + 15 of
-  // its set bits), so that dense words spread over four waves; within a unit
-  // four nodes' rows are loaded before any of them is written back
-  const unsigned nunits = (unsigned)nwords * 4u;
+  // a work unit is a part of a frontier word: with wide rows a quarter (ranks
+  // 16 s .. 16 s + 15 of its set bits), so that dense words spread over four
+  // waves; with narrow rows (P <= 16: 4 nodes or more per wave and step) the
+  // whole word.  Within a unit four nodes' rows per group are loaded before
+  // any of them is written back.
+  constexpr int kParts = P >= 64 ? 4 : (P >= 32 ? 2 : 1);
+  constexpr int kPartNodes = 64 / kParts;
+  const unsigned nunits = (unsigned)nwords * (unsigned)kParts;
   for (unsigned ux = gw; ux < nunits; ux += nwaves) {
-    const unsigned t = ux >> 2;
+    const unsigned t = ux / kParts;
     const u64 tw = T[t];
     const int cnt = __popcll(tw);
-    const int ib = (int)(ux & 3u) * 16, ie = min(ib + 16, cnt);
+    const int ib = (int)(ux % kParts) * kPartNodes, ie = min(ib + kPartNodes, cnt);
     if (ib >= ie) continue;
     const int v0 = (int)t * 64;
     const bool bit = (tw >> lane) & 1ull;
