@@ -19,6 +19,7 @@
 // Engines of different graphs overlap on the device; the thread polls their
 // events instead of blocking on one.  Timestamps: submit, admit, done.
 #include <string.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <condition_variable>
@@ -401,9 +402,15 @@ static void copier_main(Server* S) {
   }
 }
 
+// Polling without sleeping this long after the last step that made progress.
+constexpr uint64_t kSpinNs = 2000000;
+
 static void scheduler_main(Server* S) {
   hipSetDevice(S->ctx->device);
+  // timed sleeps of this thread end close to their deadline
+  prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
   std::unique_lock<std::mutex> lk(S->mu);
+  uint64_t last_progress = now_ns();
   while (!S->stop) {
     bool progressed = false;
     // engines for graphs with waiting queries
@@ -489,12 +496,22 @@ static void scheduler_main(Server* S) {
         progressed = true;
       }
     }
+    if (progressed) last_progress = now_ns();
     if (!progressed) {
       bool busy = false;
       for (auto& kv : S->engines) busy |= kv.second->running || !kv.second->emitting.empty();
       if (busy) {
+        // a level or an emission is on the device: poll again at once for a
+        // while (a level can take tens of microseconds, less than a timed
+        // sleep often lasts), then back off to short sleeps
         lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (now_ns() - last_progress < kSpinNs) {
+          // a few microseconds without the lock, so submitters get it
+          const uint64_t until = now_ns() + 5000;
+          while (now_ns() < until) std::this_thread::yield();
+        } else {
+          std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
         lk.lock();
       } else {
         S->cv.wait_for(lk, std::chrono::milliseconds(50));
