@@ -146,6 +146,14 @@ struct ZeroList {
   int k;
 };
 dawn_status batch_launch_zero_list(Ctx* ctx, const ZeroList& z, hipStream_t s);
+// Active-lane words passed by value to a kernel.
+struct BatchActWords {
+  u64 w[64];
+  int W;
+};
+// Set the active words and clear counter slot `slot` (serving, before a level).
+dawn_status batch_launch_level_prep(const BatchActWords& act, u64* d_act, BatchCtrl* ctrl, int slot,
+                                    hipStream_t s);
 // One level's control step of the device-driven loop (see BatchRun).
 dawn_status batch_launch_control(const BatchArgs& a, u64* act, int L, const dawn_params& p,
                                  hipStream_t s);

@@ -1004,6 +1004,26 @@ __global__ __launch_bounds__(kBatchBlock) void batch_zero(u64* p, size_t count) 
     p[i] = 0;
 }
 
+// Serving's step before a level: the active-lane words (by value) and a
+// cleared counter slot for the level, in one launch instead of a copy and
+// two fills.
+__global__ __launch_bounds__(kWave) void batch_level_prep(BatchActWords act, u64* d_act,
+                                                         BatchCtrl* ctrl, int slot) {
+  const int lane = lane_id();
+  if (lane < act.W) d_act[lane] = act.w[lane];
+  for (int i = lane; i < kStripes * 64; i += kWave) ctrl->laneact[slot][i / 64][i % 64] = 0;
+  if (lane < kStripes) {
+    BatchStripe& st = ctrl->lv[slot].s[lane];
+    st.nodes = 0;
+    st.bits = 0;
+    st.se = 0;
+    st.mf = 0;
+    st.edges = 0;
+    st.mfw = 0;
+  }
+  if (lane == 0) ctrl->lv[slot].nchunks = 0;
+}
+
 // Row y of the grid clears array y of the list.
 __global__ __launch_bounds__(kBatchBlock) void batch_zero_list(ZeroList z) {
   u64* p = z.p[blockIdx.y];
@@ -1358,6 +1378,13 @@ dawn_status batch_launch_zero_list(Ctx* ctx, const ZeroList& z, hipStream_t s) {
   for (int i = 0; i < z.k; ++i) most = std::max(most, z.count[i]);
   const int gx = (int)std::min<size_t>((most + kBatchBlock - 1) / kBatchBlock, (size_t)ctx->num_cu * 4);
   hipLaunchKernelGGL(batch_zero_list, dim3(gx, z.k), dim3(kBatchBlock), 0, s, z);
+  DAWN_HIP(hipGetLastError());
+  return DAWN_OK;
+}
+
+dawn_status batch_launch_level_prep(const BatchActWords& act, u64* d_act, BatchCtrl* ctrl, int slot,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(batch_level_prep, dim3(1), dim3(kWave), 0, s, act, d_act, ctrl, slot);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }

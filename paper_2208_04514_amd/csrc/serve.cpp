@@ -75,7 +75,6 @@ struct Engine {
   int32_t* h_base = nullptr;
   int32_t* h_src = nullptr;
   int32_t* h_lane = nullptr;
-  u64* h_act = nullptr;
   u64* h_em = nullptr;
   int nseed = 0;
 };
@@ -132,7 +131,7 @@ static void engine_destroy_raw(Engine* e) {
   }
   if (e->lev_ev) hipEventDestroy(e->lev_ev);
   for (void* p : {(void*)e->h_rows, (void*)e->h_base, (void*)e->h_src, (void*)e->h_lane,
-                  (void*)e->h_act, (void*)e->h_em})
+                  (void*)e->h_em})
     if (p) hipHostFree(p);
   delete e;
 }
@@ -170,7 +169,6 @@ static dawn_status engine_create(Server* S, const std::shared_ptr<GraphRec>& g, 
   if (he == hipSuccess) he = hipHostMalloc((void**)&e->h_base, 4096 * 4, 0);
   if (he == hipSuccess) he = hipHostMalloc((void**)&e->h_src, 4096 * 4, 0);
   if (he == hipSuccess) he = hipHostMalloc((void**)&e->h_lane, 4096 * 4, 0);
-  if (he == hipSuccess) he = hipHostMalloc((void**)&e->h_act, 64 * 8, 0);
   if (he == hipSuccess) he = hipHostMalloc((void**)&e->h_em, 64 * 8, 0);
   if (he == hipSuccess) {
     for (int i = 0; i < 4096; ++i) {
@@ -300,10 +298,10 @@ static dawn_status launch_level(Server* S, Engine* e) {
   }
   // the merge writes only the planes a running lane's level can reach
   a.nplanes = std::min(a.nplanes, std::max(need, 1));
-  for (int i = 0; i < e->W; ++i) e->h_act[i] = e->act[i];
-  DAWN_HIP(hipMemcpyAsync(w->act, e->h_act, (size_t)e->W * 8, hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemsetAsync(&w->ctrl->lv[(L + 1) & 1], 0, sizeof(BatchLevel), s));
-  DAWN_HIP(hipMemsetAsync(&w->ctrl->laneact[(L + 1) & 1], 0, sizeof(w->ctrl->laneact[0]), s));
+  BatchActWords aw;
+  aw.W = e->W;
+  for (int i = 0; i < 64; ++i) aw.w[i] = i < e->W ? e->act[i] : 0ull;
+  DAWN_TRY(batch_launch_level_prep(aw, w->act, w->ctrl, (L + 1) & 1, s));
   dawn_params p;
   {
     std::lock_guard<std::mutex> lk(e->g->mu);
