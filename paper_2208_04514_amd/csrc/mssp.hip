@@ -1424,11 +1424,28 @@ static int bit_length(int x) {
   return b;
 }
 
-// One batch of k <= lanes sources through the per-level loop.
-static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn_params& p,
-                             const int32_t* h_src, int k, int32_t* const* h_rows,
-                             BatchTotals* tot) {
-  const int W = (k + 63) / 64;
+// One batch of k <= lanes sources through the level loop, in steps so that
+// several batches (each on its own workspace and stream) can run side by
+// side: begin, then chunks of levels (enqueue, and after a stream sync,
+// check) until the run state says done, then finish (emission).
+struct BatchJob {
+  BatchWs* w = nullptr;
+  int k = 0;
+  int W = 0;
+  BatchArgs a;
+  int L = 1;        // first level of the next chunk
+  int Lend = 0;     // last level of the chunk in flight
+  int chunk = 4;
+  int launches = 0;
+  bool done = false;
+};
+
+static dawn_status batch_begin(Ctx* ctx, const GraphRec* g, BatchJob& j, const int32_t* h_src,
+                               int k, int32_t* const* h_rows) {
+  BatchWs* w = j.w;
+  j.k = k;
+  j.W = (k + 63) / 64;
+  const int W = j.W;
   hipStream_t s = w->stream;
   const size_t nW = (size_t)g->n * W;
   std::vector<int32_t> zeros(64 * W, 0);
@@ -1465,45 +1482,63 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
     DAWN_TRY(batch_launch_zero_list(ctx, z, s));
   }
   w->planes_dirty = 0;
-  BatchArgs a = batch_args(g, w, W);
-  a.gated = 1;
-  DAWN_TRY(batch_launch_seed(ctx, a, w->src, w->lane, k, 0, false, s));
-  DAWN_TRY(batch_launch_merge(ctx, a, 0, s));
-  int launches = 3;
-  // Levels go out in chunks without a host round trip: batch_control picks
-  // each level's direction on the device and stops the run, after which the
-  // chunk's remaining launches return at once.  The host reads the run state
-  // once per chunk; the first chunk is as long as the graph's last run.
-  int L = 1;
+  j.a = batch_args(g, w, W);
+  j.a.gated = 1;
+  DAWN_TRY(batch_launch_seed(ctx, j.a, w->src, w->lane, k, 0, false, s));
+  DAWN_TRY(batch_launch_merge(ctx, j.a, 0, s));
+  j.launches = 3;
+  j.L = 1;
   const int hint = g->batch_hint.load(std::memory_order_relaxed);
-  int chunk = hint > 0 ? hint : 4;
-  for (;;) {
-    if (L > g->n + 1) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
-    if (bit_length(L) > kMaxPlanes)
-      return fail(DAWN_E_DEVICE, "batched traversal exceeds %d levels", (1 << kMaxPlanes) - 1);
-    int Lend = L + chunk - 1;
-    while (bit_length(Lend) > kMaxPlanes) --Lend;
-    const int need = bit_length(Lend);
-    if (need > w->nplanes) {
-      DAWN_TRY(batch_ensure_planes(w, need, W));
-      a = batch_args(g, w, W);
-      a.gated = 1;
-    }
-    w->planes_dirty = std::max(w->planes_dirty, need);
-    for (int l = L; l <= Lend; ++l) {
-      DAWN_TRY(batch_launch_control(a, w->act, l, p, s));
-      DAWN_TRY(batch_launch_expand(ctx, a, false, l, s));
-      DAWN_TRY(batch_launch_expand(ctx, a, true, l, s));
-      DAWN_TRY(batch_launch_merge(ctx, a, l, s));
-      launches += 4;
-    }
-    DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->run, &w->ctrl->run, sizeof(BatchRun),
-                            hipMemcpyDeviceToHost, s));
-    DAWN_HIP(hipStreamSynchronize(s));
-    if (w->h_ctrl->run.done) break;
-    L = Lend + 1;
-    chunk = std::min(chunk * 2, 64);
+  j.chunk = hint > 0 ? hint : 4;
+  j.done = false;
+  return DAWN_OK;
+}
+
+// Levels go out in chunks without a host round trip: batch_control picks
+// each level's direction on the device and stops the run, after which the
+// chunk's remaining launches return at once.  The host reads the run state
+// once per chunk; the first chunk is as long as the graph's last run.
+static dawn_status batch_enqueue(Ctx* ctx, const GraphRec* g, const dawn_params& p, BatchJob& j) {
+  BatchWs* w = j.w;
+  hipStream_t s = w->stream;
+  const int L = j.L;
+  if (L > g->n + 1) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
+  if (bit_length(L) > kMaxPlanes)
+    return fail(DAWN_E_DEVICE, "batched traversal exceeds %d levels", (1 << kMaxPlanes) - 1);
+  int Lend = L + j.chunk - 1;
+  while (bit_length(Lend) > kMaxPlanes) --Lend;
+  const int need = bit_length(Lend);
+  if (need > w->nplanes) {
+    DAWN_TRY(batch_ensure_planes(w, need, j.W));
+    j.a = batch_args(g, w, j.W);
+    j.a.gated = 1;
   }
+  w->planes_dirty = std::max(w->planes_dirty, need);
+  for (int l = L; l <= Lend; ++l) {
+    DAWN_TRY(batch_launch_control(j.a, w->act, l, p, s));
+    DAWN_TRY(batch_launch_expand(ctx, j.a, false, l, s));
+    DAWN_TRY(batch_launch_expand(ctx, j.a, true, l, s));
+    DAWN_TRY(batch_launch_merge(ctx, j.a, l, s));
+    j.launches += 4;
+  }
+  DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->run, &w->ctrl->run, sizeof(BatchRun),
+                          hipMemcpyDeviceToHost, s));
+  j.Lend = Lend;
+  return DAWN_OK;
+}
+
+// After the stream has drained the chunk.
+static void batch_check(BatchJob& j) {
+  if (j.w->h_ctrl->run.done) {
+    j.done = true;
+    return;
+  }
+  j.L = j.Lend + 1;
+  j.chunk = std::min(j.chunk * 2, 64);
+}
+
+static dawn_status batch_finish(Ctx* ctx, const GraphRec* g, BatchJob& j, BatchTotals* tot) {
+  BatchWs* w = j.w;
   const BatchRun run = w->h_ctrl->run;
   tot->edges += run.edges;
   tot->reached += run.reached;
@@ -1513,16 +1548,28 @@ static dawn_status run_batch(Ctx* ctx, const GraphRec* g, BatchWs* w, const dawn
   const int last_nonempty = run.last_nonempty;
   // expansions 1 .. last_nonempty + 1, then the control step that ends the run
   g->batch_hint.store(std::min(last_nonempty + 2, 64), std::memory_order_relaxed);
-  DAWN_TRY(batch_launch_emit(ctx, a, bit_length(last_nonempty), w->emask, false, s));
-  launches += 1;
-  DAWN_HIP(hipEventRecord(w->ev1, s));
-  DAWN_HIP(hipStreamSynchronize(s));
-  float ms = 0.f;
-  DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-  tot->kernel_ms += ms;
-  tot->launches += launches;
+  DAWN_TRY(batch_launch_emit(ctx, j.a, bit_length(last_nonempty), w->emask, false, w->stream));
+  j.launches += 1;
+  DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+  tot->launches += j.launches;
   tot->levels = std::max(tot->levels, last_nonempty + 1);
   return DAWN_OK;
+}
+
+// Batches that run side by side: small graphs leave most of the device idle
+// in one batch's level kernels.
+constexpr int kConcurrentBatches = 4;
+
+static BatchWs* pool_take(GraphRec* g, int lanes, size_t stage) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  for (size_t i = 0; i < g->batch_pool.size(); ++i) {
+    BatchWs* c = g->batch_pool[i];
+    if (c->lanes >= lanes && c->stage_ints >= stage) {
+      g->batch_pool.erase(g->batch_pool.begin() + i);
+      return c;
+    }
+  }
+  return nullptr;
 }
 
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources, int32_t k,
@@ -1531,42 +1578,88 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
   const int lanes = std::min(p.batch_lanes, kMaxBatchLanes);
   const int kb_max = std::min(lanes, (int)k);
   const size_t stage = device_out ? 0 : (size_t)kb_max * (size_t)g->n;
-  BatchWs* w = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g->mu);
-    for (size_t i = 0; i < g->batch_pool.size(); ++i) {
-      BatchWs* c = g->batch_pool[i];
-      if (c->lanes >= kb_max && c->stage_ints >= stage) {
-        w = c;
-        g->batch_pool.erase(g->batch_pool.begin() + i);
+  const int nbatches = (int)(((int64_t)k + lanes - 1) / lanes);
+  // workspaces: from the pool, then new ones while the budget allows (at
+  // least one, or the call fails)
+  std::vector<BatchWs*> ws;
+  const int want = std::max(1, std::min(nbatches, kConcurrentBatches));
+  while ((int)ws.size() < want) {
+    BatchWs* w = pool_take(g, kb_max, stage);
+    if (!w) {
+      dawn_status cs = batch_ws_create(ctx, g, kb_max, stage, &w);
+      if (cs != DAWN_OK) {
+        if (ws.empty()) return cs;
         break;
       }
     }
+    ws.push_back(w);
   }
-  if (!w) DAWN_TRY(batch_ws_create(ctx, g, kb_max, stage, &w));
+  const int conc = (int)ws.size();
   BatchTotals tot;
   memset(&tot, 0, sizeof(tot));
   dawn_status st = DAWN_OK;
-  std::vector<int32_t*> rows(kb_max);
-  for (int32_t b0 = 0; b0 < k && st == DAWN_OK; b0 += lanes) {
-    const int kb = std::min(lanes, k - b0);
-    for (int r = 0; r < kb; ++r)
-      rows[r] = device_out ? dist + (size_t)(b0 + r) * row_stride : w->stage + (size_t)r * g->n;
-    st = run_batch(ctx, g, w, p, sources + b0, kb, rows.data(), &tot);
-    if (st == DAWN_OK && !device_out) {
-      hipError_t e = hipMemcpy2DAsync(dist + (size_t)b0 * row_stride, (size_t)row_stride * 4,
-                                      w->stage, (size_t)g->n * 4, (size_t)g->n * 4, kb,
-                                      hipMemcpyDeviceToHost, w->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
-      if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "copy to host: %s", hipGetErrorString(e));
+  std::vector<std::vector<int32_t*>> rows(conc, std::vector<int32_t*>(kb_max));
+  std::vector<BatchJob> jobs(conc);
+  for (int bg = 0; bg < nbatches && st == DAWN_OK; bg += conc) {
+    const int nj = std::min(conc, nbatches - bg);
+    for (int i = 0; i < nj && st == DAWN_OK; ++i) {
+      const int64_t b0 = (int64_t)(bg + i) * lanes;
+      const int kb = (int)std::min<int64_t>(lanes, k - b0);
+      BatchJob& j = jobs[i];
+      j = BatchJob();
+      j.w = ws[i];
+      for (int r = 0; r < kb; ++r)
+        rows[i][r] = device_out ? dist + (size_t)(b0 + r) * row_stride
+                                : ws[i]->stage + (size_t)r * g->n;
+      st = batch_begin(ctx, g, j, sources + b0, kb, rows[i].data());
     }
+    // chunks of levels, all running batches side by side
+    for (bool busy = true; busy && st == DAWN_OK;) {
+      busy = false;
+      for (int i = 0; i < nj && st == DAWN_OK; ++i)
+        if (!jobs[i].done) st = batch_enqueue(ctx, g, p, jobs[i]);
+      for (int i = 0; i < nj && st == DAWN_OK; ++i) {
+        if (jobs[i].done) continue;
+        hipError_t e = hipStreamSynchronize(ws[i]->stream);
+        if (e != hipSuccess) {
+          st = fail(DAWN_E_DEVICE, "batched level loop: %s", hipGetErrorString(e));
+          break;
+        }
+        batch_check(jobs[i]);
+        busy |= !jobs[i].done;
+      }
+    }
+    for (int i = 0; i < nj && st == DAWN_OK; ++i) st = batch_finish(ctx, g, jobs[i], &tot);
+    float group_ms = 0.f;
+    for (int i = 0; i < nj && st == DAWN_OK; ++i) {
+      hipError_t e = hipStreamSynchronize(ws[i]->stream);
+      // the group's device time: first start to last end
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ws[0]->ev0, ws[i]->ev1);
+      if (e != hipSuccess) {
+        st = fail(DAWN_E_DEVICE, "batched run: %s", hipGetErrorString(e));
+        break;
+      }
+      group_ms = std::max(group_ms, ms);
+      if (!device_out) {
+        const int64_t b0 = (int64_t)(bg + i) * lanes;
+        e = hipMemcpy2DAsync(dist + (size_t)b0 * row_stride, (size_t)row_stride * 4, ws[i]->stage,
+                             (size_t)g->n * 4, (size_t)g->n * 4, jobs[i].k,
+                             hipMemcpyDeviceToHost, ws[i]->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ws[i]->stream);
+        if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "copy to host: %s", hipGetErrorString(e));
+      }
+    }
+    tot.kernel_ms += group_ms;
   }
   if (st == DAWN_OK) {
     std::lock_guard<std::mutex> lk(g->mu);
-    g->batch_pool.push_back(w);
+    for (BatchWs* w : ws) g->batch_pool.push_back(w);
   } else {
-    hipStreamSynchronize(w->stream);
-    batch_ws_destroy(w);
+    for (BatchWs* w : ws) {
+      hipStreamSynchronize(w->stream);
+      batch_ws_destroy(w);
+    }
     return st;
   }
   if (stats) {
