@@ -1575,10 +1575,11 @@ static BatchWs* pool_take(GraphRec* g, int lanes, size_t stage) {
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources, int32_t k,
                      int32_t* dist, bool device_out, int64_t row_stride, dawn_run_stats* stats) {
   const uint64_t t0 = now_ns();
+  if (k <= 0) return DAWN_OK;   // the entry points return before this
   const int lanes = std::min(p.batch_lanes, kMaxBatchLanes);
+  const int nbatches = (int)(((int64_t)k + lanes - 1) / lanes);
   const int kb_max = std::min(lanes, (int)k);
   const size_t stage = device_out ? 0 : (size_t)kb_max * (size_t)g->n;
-  const int nbatches = (int)(((int64_t)k + lanes - 1) / lanes);
   // workspaces: from the pool, then new ones while the budget allows (at
   // least one, or the call fails)
   std::vector<BatchWs*> ws;
