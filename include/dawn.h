@@ -219,7 +219,9 @@ dawn_status dawn_autotune(dawn_ctx *ctx, int32_t graph, const int32_t *sources, 
  * resident graph; at every level boundary it retires finished sources, then
  * admits waiting queries into free lanes while the HBM budget allows, so
  * queries that arrive while others run join the running batch (continuous
- * batching).  The caller keeps `sources` only until the call returns, but must
+ * batching).  While a level runs the scheduler polls the device without
+ * sleeping (one host core busy), for up to 2 ms after its last step, then
+ * in 20 us sleeps.  The caller keeps `sources` only until the call returns, but must
  * keep dist_out valid and unread until dawn_serve_poll returns DAWN_OK.
  * Errors: INVALID_ARG, NOT_FOUND, NO_MEMORY (the query can never fit),
  * BUSY (queue full). */
