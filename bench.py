@@ -174,6 +174,25 @@ def component_edge_sums(g):
     return sums[lab].astype(np.int64)
 
 
+def batched_only(D, ctx):
+    """R-MAT 18, the 4096 bench sources in one dawn_mssp call, three times with
+    the library's default knobs: the batched kernels alone, for a profiler."""
+    import torch
+    import graphgen as gg
+    g, src = gg.load_config("rmat18")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
+    runs = []
+    for _ in range(3):
+        _, st = D.dawn_mssp(ctx, h, src, out=out)
+        runs.append(round(st["kernel_ms"], 3))
+    torch.cuda.synchronize()
+    print(json.dumps({"batched_only": {"workload": "rmat18_ef16_sym_4096src_one_launch",
+                                       "kernel_ms": runs, "levels": st["levels"],
+                                       "push_levels": st["push_levels"],
+                                       "pull_levels": st["pull_levels"]}}), flush=True)
+
+
 def batched_bench(D, ctx):
     """R-MAT 18, 4096 sources in one dawn_mssp launch, and the same sources
     one at a time through dawn_sssp."""
@@ -484,6 +503,8 @@ def main():
                     help="only the level-kernel timing pass (for rocprofv3)")
     ap.add_argument("--params", default="", help="JSON knobs for --roofline-only")
     ap.add_argument("--digest", action="store_true", help="print the level kernel's source digest")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only R-MAT 18 x 4096 sources through dawn_mssp, 3 calls (for profiling)")
     args = ap.parse_args()
     if args.digest:
         print(kernel_digest())
@@ -501,6 +522,10 @@ def main():
     if args.roofline_only:
         ctx = D.dawn_create(0, 0)
         roofline_only(D, ctx, args.params)
+        return
+    if args.batched_only:
+        ctx = D.dawn_create(0, 0)
+        batched_only(D, ctx)
         return
 
     _log("[bench] R-MAT 20")
