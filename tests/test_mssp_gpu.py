@@ -111,6 +111,26 @@ def test_level_chunks_deep_then_shallow(ctx, upload):
         _check_rows(g, src, got, st)
 
 
+@pytest.mark.parametrize("device_out", [False, True])
+def test_concurrent_batch_groups(ctx, upload, params, device_out):
+    """Ten batches of 64 lanes: groups of four batches run side by side (each
+    on its own workspace and stream), the last group holds two, the last
+    batch is ragged."""
+    h, g, _ = upload("rmat12")
+    params(h, batch_lanes=64)
+    srcs = gg.sample_sources(g.n, 64 * 9 + 5, 31)
+    _say(f"[mssp] rmat12 k={srcs.size} in batches of 64, device_out={device_out}")
+    if device_out:
+        import torch
+        out = torch.full((srcs.size, g.n), 7, dtype=torch.int32, device="cuda")
+        _, st = D.dawn_mssp(ctx, h, srcs, out=out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+    else:
+        got, st = D.dawn_mssp(ctx, h, srcs)
+    _check_rows(g, srcs, got, st)
+
+
 @pytest.mark.parametrize("k", [4095, 4096, 4097, 5000])
 def test_batch_edges(ctx, upload, k):
     h, g, _ = upload("uniform4096")
