@@ -47,6 +47,9 @@ struct alignas(kLine) BatchRun {
 struct BatchCtrl {
   BatchLevel lv[2];
   BatchRun run;
+  // next emission task to claim (cleared before every emission: at the start
+  // of a batched run, and by serving's per-level prep)
+  alignas(kLine) unsigned emit_next;
   // OR of the new bits of each word, per level parity, striped like the
   // counters (a workgroup ORs into stripe blockIdx % kStripes)
   u64 laneact[2][kStripes][64];

@@ -871,7 +871,7 @@ __device__ __forceinline__ void emit_one(u64 my_row, int b, int bit, unsigned xh
 template <int DMAX, int EG>
 __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
                                                           const u64* __restrict__ emask,
-                                                          int clear) {
+                                                          int clear, int claim) {
   // the row pointers of all lanes, staged once: a per-word global load in the
   // store loop would wait for every store before it
   __shared__ u64 srow[kMaxBatchLanes];
@@ -886,7 +886,17 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
   const int ntiles = (a.n + kWave - 1) / kWave;
   const int ngroups = (W + EG - 1) / EG;
   const long long tasks = (long long)ntiles * ngroups;
-  for (long long t = gw; t < tasks; t += nwaves) {
+  // a wave's first task is its index; with `claim` (many tasks per wave)
+  // later ones are claimed in order from a counter, so no wave idles while
+  // another has several left (with few per wave the claims, serialised on
+  // one line, would cost more than they balance)
+  auto next_task = [&](long long t) -> long long {
+    if (!claim) return t + nwaves;
+    unsigned c = 0;
+    if (lane == 0) c = atomicAdd(&a.ctrl->emit_next, 1u);
+    return nwaves + (unsigned)__builtin_amdgcn_readfirstlane((int)c);
+  };
+  for (long long t = gw; t < tasks; t = next_task(t)) {
     const int w0 = (int)(t / ntiles) * EG;
     const int v = (int)(t % ntiles) * kWave + lane;
     const int ew = min(EG, W - w0);
@@ -1021,7 +1031,10 @@ __global__ __launch_bounds__(kWave) void batch_level_prep(BatchActWords act, u64
     st.edges = 0;
     st.mfw = 0;
   }
-  if (lane == 0) ctrl->lv[slot].nchunks = 0;
+  if (lane == 0) {
+    ctrl->lv[slot].nchunks = 0;
+    ctrl->emit_next = 0;
+  }
 }
 
 // Row y of the grid clears array y of the list.
@@ -1345,8 +1358,9 @@ static dawn_status launch_emit_t(Ctx* ctx, const BatchArgs& a, int D, const u64*
   const long long per_block = kBatchBlock / kWave;
   const int grid = (int)std::max<long long>(
       1, std::min<long long>((tasks + per_block - 1) / per_block, (long long)ctx->num_cu * occ));
+  const int claim = tasks >= 4 * (long long)grid * per_block ? 1 : 0;
   hipLaunchKernelGGL((batch_emit<DMAX, EG>), dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask,
-                     clear ? 1 : 0);
+                     clear ? 1 : 0, claim);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }
