@@ -120,7 +120,6 @@ struct BatchWs {
   int32_t* stage = nullptr;     // device rows for host-destination calls
   size_t stage_ints = 0;
   BatchCtrl* h_ctrl = nullptr;
-  u64* h_act = nullptr;         // pinned [64]: active lanes for the next level
 };
 
 struct BatchTotals {

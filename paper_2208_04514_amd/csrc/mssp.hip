@@ -1162,7 +1162,6 @@ void batch_ws_destroy(BatchWs* w) {
   if (ctx) ctx->used -= w->bytes;
   if (ctx && w->plane_reserve) dev_unreserve(ctx, w->plane_reserve);
   if (w->h_ctrl) hipHostFree(w->h_ctrl);
-  if (w->h_act) hipHostFree(w->h_act);
   if (w->ev0) hipEventDestroy(w->ev0);
   if (w->ev1) hipEventDestroy(w->ev1);
   if (w->stream && w->own_stream) hipStreamDestroy(w->stream);
@@ -1211,7 +1210,6 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
     return s;
   }
   hipError_t e = hipHostMalloc((void**)&w->h_ctrl, sizeof(BatchCtrl), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&w->h_act, 64 * 8, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
   w->own_stream = true;
   if (e == hipSuccess) e = hipEventCreate(&w->ev0);
