@@ -61,6 +61,16 @@ def cpu_model() -> str:
     return platform.processor()
 
 
+def host_cores() -> int:
+    """CPUs this process may run on (its affinity set), at most the 16 that
+    one GPU's share of the box provides."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def kernel_digest() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -260,6 +270,43 @@ def apsp_bench(D, ctx):
             "gteps": round(st["source_edges"] / t / 1e9, 2), "levels": st["levels"]}
 
 
+def uniform_bench(D, ctx, reps=20):
+    """The small CPU-checkable case: directed uniform n = 4096, m = 32,768, its
+    8 sources one at a time through dawn_sssp (device output), with the
+    per-level cost; latency-bound by construction (a few levels of a few
+    hundred nodes)."""
+    import torch
+    import graphgen as gg
+    import oracle
+    g, src = gg.load_config("uniform4096")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
+    for i, s in enumerate(src):
+        D.dawn_sssp(ctx, h, int(s), out=out[i])
+    torch.cuda.synchronize()
+    calls, se, ks, lv = [], 0, 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for i, s in enumerate(src):
+            c0 = time.perf_counter()
+            _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
+            calls.append((time.perf_counter() - c0) * 1e6)
+            se += st["source_edges"]
+            ks += st["kernel_ms"]
+            lv += st["levels"]
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    same = bool(np.array_equal(out.cpu().numpy(), oracle.mssp(g, src)))
+    D.dawn_graph_release(ctx, h)
+    return {"workload": "uniform4096_m32768_directed_8src_plain_sssp", "n": g.n, "m": g.m,
+            "sources": int(src.size), "gteps": round(se / t / 1e9, 4),
+            "gteps_device": round(se / ks / 1e6, 4),
+            "us_per_source_p50": round(float(np.percentile(calls, 50)), 1),
+            "us_per_source_p99": round(float(np.percentile(calls, 99)), 1),
+            "us_per_level": round(t / lv * 1e6, 2), "levels_per_source": round(lv / reps / src.size, 2),
+            "bit_exact": same}
+
+
 def small_component_bench(D, ctx):
     """Sources in small components (512 components of 16..2048 nodes): one
     workgroup per source (small_n = 2048) vs the general level loop
@@ -407,7 +454,7 @@ def serving_bench(D, ctx, nq=200, seed=105):
     return res
 
 
-def cpu_baseline(g, src, dist_rows):
+def cpu_baseline(g, src):
     """The CPU oracle on the host cores: one thread, then one source per thread."""
     import oracle
     import graphgen as gg
@@ -415,27 +462,27 @@ def cpu_baseline(g, src, dist_rows):
     ref = oracle.mssp(g, src, threads=1)
     tc = time.perf_counter() - t0
     se = gg.reach_edges_from_dist(g, ref)
-    cores = min(os.cpu_count() or 1, 16)
+    cores = host_cores()
     t0 = time.perf_counter()
     oracle.mssp(g, src, threads=cores)
     tm = time.perf_counter() - t0
     base = {"value": round(se / tc / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"rmat20, the {src.size} timed sources, FIFO-queue BFS one source at a "
                       f"time, {tc:.1f} s",
-            "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
+            "cpu_model": cpu_model(), "host_cores": cores}
     par = {"value": round(se / tm / 1e9, 4), "unit": "GTEPS", "cores": cores, "kind": "oracle",
            "sample": f"same sources, one source per thread, {tm:.1f} s"}
-    return base, par, bool(np.array_equal(ref, dist_rows[: src.size]))
+    return base, par, ref
 
 
-def host_dawn_bench(g, src, threads=(1, 2, 4, 8, 16), per=4):
+def host_dawn_bench(g, src, threads=(1, 2, 4, 8, 16), per=16):
     """The host CPU DAWN (SOVM on CPU threads) on R-MAT 20: one source at a
     time with N threads sharing each level, and the thread efficiency of the
     paper's scalability section, eta_N = T_1 / (T_N x N); then 64 sources
     spread one per thread."""
     from paper_2208_04514_amd import dawn_host as H
     hg = H.HostGraph(g.row_ptr, g.col)
-    cores = os.cpu_count() or 1
+    cores = host_cores()
     res, t1 = {}, None
     row = np.empty(g.n, np.int32)
     for nt in threads:
@@ -547,11 +594,21 @@ def main():
     se, dt, ks, levels, calls = run_plain(D, ctx, h, src, out, args.steps, args.warmup)
     value = se / dt / 1e9
     ms_per_step = dt / args.steps * 1e3
+    timed_rows = out.cpu().numpy()          # the rows of the last timed pass
+
+    _log("[bench] plain SSSP, host-destination rows (end to end, with the copy)")
+    host_rows = np.empty((src.size, g.n), np.int32)
+    t0 = time.perf_counter()
+    se_h = 0
+    for i, s in enumerate(src):
+        _, st = D.dawn_sssp(ctx, h, int(s), out=host_rows[i])
+        se_h += st["source_edges"]
+    gteps_host = se_h / (time.perf_counter() - t0) / 1e9
 
     _log("[bench] level kernel per-launch timing")
     lk_ms, lk_launches, lk_levels = level_kernel_timing(D, ctx, h, src, out)
     torch.cuda.synchronize()
-    dist_rows = out.cpu().numpy()
+    dist_rows = out.cpu().numpy()           # the rows of the per-launch timing pass
     roofline = roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs)
     bytes_full = D.dawn_graph_get_info(ctx, h)["device_bytes"]
     D.dawn_graph_release(ctx, h)
@@ -572,6 +629,8 @@ def main():
         _log("[bench] batched R-MAT 18, 4096 sources")
         extra["batched"] = batched_bench(D, ctx)
     if not args.no_extra:
+        _log("[bench] uniform n = 4096, 8 sources")
+        extra["uniform4096"] = uniform_bench(D, ctx)
         _log("[bench] APSP over the largest WCC of R-MAT 14")
         extra["apsp"] = apsp_bench(D, ctx)
         _log("[bench] grid 2048^2 level-loop drivers")
@@ -585,9 +644,14 @@ def main():
     cpu = None
     if not args.no_cpu:
         _log(f"[bench] CPU oracle on {src.size} sources")
-        cpu, cpu_par, same = cpu_baseline(g, src, dist_rows)
+        cpu, cpu_par, ref = cpu_baseline(g, src)
         extra["cpu_parallel"] = cpu_par
-        extra["parity_sample_bit_exact"] = same
+        # the oracle's rows against the rows of the timed pass itself, the
+        # per-launch timing pass and the host-destination pass
+        extra["parity"] = {"timed_pass_bit_exact": bool(np.array_equal(ref, timed_rows)),
+                           "timing_pass_bit_exact": bool(np.array_equal(ref, dist_rows)),
+                           "host_output_bit_exact": bool(np.array_equal(ref, host_rows)),
+                           "rows": int(src.size)}
         _log("[bench] host CPU DAWN (SOVM on CPU threads)")
         extra["host_dawn"] = host_dawn_bench(g, src)
 
@@ -599,6 +663,7 @@ def main():
         "config": {"workload": "rmat20_ef16_sym_64src_plain_sssp", "n": g.n, "m": g.m,
                    "sources": int(src.size), "source_edges_per_step": int(se // args.steps),
                    "gteps_device": round(se / ks / 1e6, 3),
+                   "gteps_host_output": round(gteps_host, 3),
                    "gteps_graph500_halved": round(value / 2, 3),
                    "ms_per_source_p50": round(float(np.percentile(calls, 50)), 4),
                    "ms_per_source_p99": round(float(np.percentile(calls, 99)), 4),

@@ -21,13 +21,14 @@
  *    -1 when v is not reachable from s.  The paper's "0 = unvisited" would
  *    collide with dist[s] = 0, hence the separate -1.
  *  - Every call returns a dawn_status.  On any error the output buffers are
- *    left untouched and dawn_last_error() describes the failure.
+ *    left untouched and dawn_last_error() describes the failure (for errors
+ *    found on the device by dawn_mssp_device, see there).
  *  - Unless DAWN_DEVICE_OUT is set, pointers are host memory.  With
  *    DAWN_DEVICE_OUT the distance buffer is device memory on the context's GPU
  *    (for example a torch tensor's data_ptr()); it is written on the device
  *    and no copy to the host is made.
- *  - Synchronous calls (everything except dawn_serve_submit) have finished
- *    writing their outputs when they return.
+ *  - Synchronous calls (everything except dawn_serve_submit and
+ *    dawn_mssp_device) have finished writing their outputs when they return.
  *  - All calls are thread-safe on one context.  Calls on the same graph from
  *    several threads run on separate HIP streams.
  */
@@ -192,6 +193,32 @@ dawn_status dawn_sssp(dawn_ctx *ctx, int32_t graph, int32_t source, int32_t *dis
  * Errors: INVALID_ARG, NOT_FOUND, NO_MEMORY, DEVICE. */
 dawn_status dawn_mssp(dawn_ctx *ctx, int32_t graph, const int32_t *sources, int32_t k,
                       int32_t *dist, uint32_t flags, dawn_run_stats *stats);
+
+/* Device-ordered multi-source run: the same rows as dawn_mssp, with every step
+ * queued on the caller's HIP stream `hip_stream` (NULL: the null stream) and
+ * no wait on the host.  The call returns once the work is queued; work the
+ * caller queues on the stream afterwards sees the finished rows.
+ * d_sources: k int32 node ids in device memory on the context's GPU, read on
+ * the device (k == 0 queues nothing but the status).  d_dist: k x n int32,
+ * device memory, row r = distances from d_sources[r].  d_status (device int32,
+ * may be NULL): written on the stream with DAWN_OK, DAWN_E_INVALID_ARG (a
+ * source outside [0, n): no row is written) or DAWN_E_DEVICE (a run needed
+ * more than min(n, 65535) levels, or its grid barrier timed out: rows of
+ * earlier batches of 4096 sources may be written, later ones are not).
+ * Levels are queued as separate launches up to the depth of the graph's last
+ * finished run, then one cooperative kernel runs any further levels with a
+ * grid barrier between steps; the level bit-planes are allocated for the
+ * deepest possible run (min(16, bit_length(n)) planes of n x 64-lane words
+ * per batch word, i.e. at most half the size of a full batch's rows).
+ * Buffers stay owned by the caller and must stay valid until the stream has
+ * run the work.  Not for stream capture (it waits on events and launches a
+ * cooperative kernel).  Host-side errors (returned at once, nothing queued):
+ * INVALID_ARG (null or non-device pointers, pointers on another GPU, buffers
+ * smaller than k or k x n int32 within their allocation), NOT_FOUND,
+ * NO_MEMORY, DEVICE.  Section 3.3: the multi-source run is the SSSP of every
+ * source, each lane advancing by the level step of Algorithms 1 and 2. */
+dawn_status dawn_mssp_device(dawn_ctx *ctx, int32_t graph, const int32_t *d_sources, int32_t k,
+                             int32_t *d_dist, int32_t *d_status, void *hip_stream);
 
 /* All-pairs over the largest weakly connected component (ties: the component
  * holding the smallest node id).  Reachability implies weak connectivity, so

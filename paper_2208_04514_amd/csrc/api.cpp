@@ -128,6 +128,33 @@ static dawn_status check_ctx(dawn_ctx* c) {
 
 static Ctx* C(dawn_ctx* c) { return reinterpret_cast<Ctx*>(c); }
 
+// `bytes` of device memory at p on the context's GPU, inside one allocation
+// (a caching allocator's block may be larger than the tensor: the check then
+// only bounds the block).
+static dawn_status check_device_span(Ctx* ctx, const void* p, size_t bytes, const char* what) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess || (at.type != hipMemoryTypeDevice && !at.isManaged)) {
+    (void)hipGetLastError();
+    return fail(DAWN_E_INVALID_ARG, "%s is not device memory", what);
+  }
+  if (at.device != ctx->device)
+    return fail(DAWN_E_INVALID_ARG, "%s is on device %d, the context on %d", what, at.device,
+                ctx->device);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) == hipSuccess && base) {
+    const size_t off = (size_t)((const char*)p - (const char*)base);
+    if (off + bytes > size)
+      return fail(DAWN_E_INVALID_ARG, "%s: %zu bytes past %p overrun its allocation of %zu bytes",
+                  what, bytes, p, size);
+  } else {
+    (void)hipGetLastError();
+  }
+  return DAWN_OK;
+}
+
 }  // namespace dawn
 
 using namespace dawn;
@@ -164,6 +191,8 @@ dawn_status dawn_create(int32_t device, uint64_t hbm_budget_bytes, dawn_ctx** ou
   ctx->budget = budget;
   const char* fa = getenv("DAWN_FAIL_ALLOC_AFTER");
   if (fa && *fa) ctx->fail_after = atoll(fa);
+  const char* fp = getenv("DAWN_FAIL_PLANE_AFTER");
+  if (fp && *fp) ctx->fail_plane_after = atoll(fp);
   *out = reinterpret_cast<dawn_ctx*>(ctx);
   return DAWN_OK;
 }
@@ -335,6 +364,30 @@ dawn_status dawn_mssp(dawn_ctx* c, int32_t graph, const int32_t* sources, int32_
     p = g->params;
   }
   return mssp_run(ctx, g.get(), p, sources, k, dist, (flags & DAWN_DEVICE_OUT) != 0, g->n, stats);
+}
+
+dawn_status dawn_mssp_device(dawn_ctx* c, int32_t graph, const int32_t* d_sources, int32_t k,
+                             int32_t* d_dist, int32_t* d_status, void* hip_stream) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (k < 0) return fail(DAWN_E_INVALID_ARG, "k must be >= 0");
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  DAWN_HIP(hipSetDevice(ctx->device));
+  if (k > 0) {
+    if (!d_sources || !d_dist) return fail(DAWN_E_INVALID_ARG, "null pointer");
+    DAWN_TRY(check_device_span(ctx, d_sources, (size_t)k * 4, "sources"));
+    DAWN_TRY(check_device_span(ctx, d_dist, (size_t)k * (size_t)g->n * 4, "dist"));
+  }
+  if (d_status) DAWN_TRY(check_device_span(ctx, d_status, 4, "status"));
+  dawn_params p;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    p = g->params;
+  }
+  return mssp_device_run(ctx, g.get(), p, d_sources, k, d_dist, d_status,
+                         reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 dawn_status dawn_apsp_wcc(dawn_ctx* c, int32_t graph, int32_t* wcc_nodes, int32_t* s_wcc,

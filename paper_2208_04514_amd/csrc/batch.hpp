@@ -37,7 +37,8 @@ struct BatchLevelSum {
 // when no lane is active; the expansion and merge kernels of that level and
 // of every later one then return at once.
 struct alignas(kLine) BatchRun {
-  int done;
+  int done;                     // 0 running, 1 finished, 2 watchdog (too many levels or a
+                                //   grid barrier timed out), 3 stopped by an invalid source
   int pull;                     // 1: the level being expanded pulls
   int last_nonempty;            // last level that found new bits
   int push_levels, pull_levels;
@@ -47,6 +48,7 @@ struct alignas(kLine) BatchRun {
 struct BatchCtrl {
   BatchLevel lv[2];
   BatchRun run;
+  GridBarrier bar;              // the cooperative tail of a device-ordered run
   // next emission task to claim (cleared before every emission: at the start
   // of a batched run, and by serving's per-level prep)
   alignas(kLine) unsigned emit_next;
@@ -86,10 +88,19 @@ struct BatchArgs {
   int32_t* ck[2];               //                                             chunk index
   BatchCtrl* ctrl;
   const u64* act;               // [W] sources still expanding
-  int32_t* const* rows;         // [lanes] distance row of each source (device)
-  const int32_t* base;          // [lanes] level at which each source joined
+  int32_t* const* rows;         // [lanes] distance row of each source (device), or null:
+  int32_t* row_base;            //   then lane r < emit_k writes row_base + r x row_stride
+  long long row_stride;
+  int32_t emit_k;               // with a null emission mask: lanes < emit_k are emitted
+  const int32_t* base;          // [lanes] level at which each source joined (null: all 0)
   int32_t gated;                // expansion and merge obey ctrl->run (device-driven loop)
+  unsigned* flags;              // [0] the workspace may hold bits (set by the seed, cleared by
+                                //   a complete emission), [1] run status: 0 ok, 1 invalid
+                                //   source, 2 watchdog (device-ordered calls report it)
 };
+
+constexpr int kFlagDirty = 0;
+constexpr int kFlagStatus = 1;
 
 struct BatchWs {
   Ctx* ctx = nullptr;
@@ -104,7 +115,6 @@ struct BatchWs {
   u64* nxt[2] = {nullptr, nullptr};
   u64* planes[kMaxPlanes] = {};
   int nplanes = 0;              // allocated
-  int planes_dirty = 0;         // planes that may hold bits from an earlier batch
   size_t plane_reserve = 0;     // budget set aside for planes not yet allocated
   u64* touched[2] = {nullptr, nullptr};
   u64* fmap[2] = {nullptr, nullptr};
@@ -117,9 +127,12 @@ struct BatchWs {
   int32_t* base = nullptr;
   int32_t* src = nullptr;
   int32_t* lane = nullptr;      // lane of each seeded source
-  int32_t* stage = nullptr;     // device rows for host-destination calls
-  size_t stage_ints = 0;
+  unsigned* flags = nullptr;    // see BatchArgs::flags
   BatchCtrl* h_ctrl = nullptr;
+  // the last work enqueued on the workspace (by a call on any stream); whoever
+  // takes it next makes its stream wait for this event first
+  hipEvent_t busy = nullptr;
+  bool busy_set = false;
 };
 
 struct BatchTotals {
@@ -128,8 +141,7 @@ struct BatchTotals {
   double kernel_ms;
 };
 
-dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage_ints,
-                            BatchWs** out);
+dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, BatchWs** out);
 dawn_status batch_ensure_planes(BatchWs* w, int need, int W);
 // Ws = row stride (the batch's width); W = words the kernels process (<= Ws;
 // 0 = Ws).
@@ -137,8 +149,12 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W = 0);
 BatchLevelSum batch_level_sum(const BatchLevel& l);
 dawn_status batch_launch_expand(Ctx* ctx, const BatchArgs& a, bool pull, int L, hipStream_t s);
 dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t s);
+// mode: kEmitClear | kEmitFromRun | kEmitMarkClean (mssp.hip)
+constexpr int kEmitClear = 1;        // remove the emitted lanes' bits from vis and the planes
+constexpr int kEmitFromRun = 2;      // plane count and go-ahead from the run state (device)
+constexpr int kEmitMarkClean = 4;    // every lane emitted with kEmitClear: workspace is clear
 dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
-                              bool clear, hipStream_t s);
+                              int mode, hipStream_t s);
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
 // Clear up to kZeroMax arrays in one launch.
 constexpr int kZeroMax = 24;

@@ -244,6 +244,8 @@ GraphRec::~GraphRec() {
   sssp_pool.clear();
   for (BatchWs* b : batch_pool) batch_ws_destroy(b);
   batch_pool.clear();
+  if (stage) dev_free(ctx, stage, stage_bytes);
+  stage = nullptr;
   wcc_sub.reset();
   if (ctx) free_graph_buffers(this);
 }

@@ -216,6 +216,9 @@ struct GraphRec {
   std::mutex mu;                          // guards the pools and the WCC cache
   std::vector<std::unique_ptr<SsspWs>> sssp_pool;
   std::vector<BatchWs*> batch_pool;
+  // device staging of host-destination batched rows, kept between calls
+  int32_t* stage = nullptr;
+  size_t stage_bytes = 0;
   // largest-WCC cache (apsp_wcc)
   bool wcc_ready = false;
   std::vector<int32_t> wcc_nodes;
@@ -235,6 +238,7 @@ struct Ctx {
   std::atomic<uint64_t> used{0};
   std::atomic<uint64_t> reserved{0};       // budget set aside (serving engines' level planes)
   std::atomic<long long> fail_after{-1};   // failure injection: allocations left before failing
+  std::atomic<long long> fail_plane_after{-1};   // ... level-plane allocations left before failing
   std::mutex mu;
   std::mutex budget_mu;
   std::map<int32_t, std::shared_ptr<GraphRec>> graphs;
@@ -259,6 +263,9 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources,
                      int32_t k, int32_t* dist, bool device_out, int64_t row_stride,
                      dawn_run_stats* stats);
+// Everything queued on stream s: sources and rows are device memory.
+dawn_status mssp_device_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* d_src,
+                            int32_t k, int32_t* d_dist, int32_t* d_status, hipStream_t s);
 
 // tune.cpp
 dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, uint32_t what,

@@ -316,8 +316,7 @@ __device__ __forceinline__ bool batch_gate_open(const BatchArgs& a, int dir) {
 }
 
 template <int P>
-__global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
-  if (!batch_gate_open(a, 1)) return;
+__device__ __forceinline__ void pull_level(const BatchArgs& a, int L) {
   const int lane = lane_id();
   const int w = lane & (P - 1);
   const int npw = kWave / P;
@@ -514,8 +513,7 @@ __device__ __forceinline__ void relax_edge_sparse(const BatchArgs& a, const u64*
 }
 
 template <int P>
-__global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
-  if (!batch_gate_open(a, 0)) return;
+__device__ __forceinline__ void push_level(const BatchArgs& a, int L) {
   const int lane = lane_id();
   const int w = lane & (P - 1);
   const int npw = kWave / P;
@@ -652,8 +650,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
 // big-degree nodes' out-edge chunks for the next push, and clear the rows and
 // bitmap of the previous frontier.
 template <int P>
-__global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
-  if (!batch_gate_open(a, -1)) return;
+__device__ __forceinline__ void merge_level(const BatchArgs& a, int L) {
   __shared__ u64 lmask[kMaxPlanes][64];   // bit b of (L - base) for the lanes of each word
   __shared__ u64 actb[64];
   __shared__ int rank_j[kBatchBlock / kWave][kWave];
@@ -669,7 +666,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   // one word per wave: lane r holds source (64 x + r)'s relative level, and a
   // ballot per plane gives that plane's mask
   for (int x = wv; x < W; x += kBatchBlock / kWave) {
-    const int rel = L - a.base[x * 64 + lane];
+    const int rel = L - (a.base ? a.base[x * 64 + lane] : 0);
 #pragma unroll
     for (int b = 0; b < kMaxPlanes; ++b) {
       const u64 m = __ballot(b < D && ((rel >> b) & 1));
@@ -835,6 +832,21 @@ __global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
   }
 }
 
+template <int P>
+__global__ __launch_bounds__(kBatchBlock) void batch_pull(BatchArgs a, int L) {
+  if (batch_gate_open(a, 1)) pull_level<P>(a, L);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBatchBlock) void batch_push(BatchArgs a, int L) {
+  if (batch_gate_open(a, 0)) push_level<P>(a, L);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBatchBlock) void batch_merge(BatchArgs a, int L) {
+  if (batch_gate_open(a, -1)) merge_level<P>(a, L);
+}
+
 // ------------------------------------------------------------------ emit --
 // Write the distance rows of the lanes in emask.  A wave takes a task of 64
 // nodes (lane l owns node v0 + l) and a group of EG consecutive words of their
@@ -868,16 +880,48 @@ __device__ __forceinline__ void emit_one(u64 my_row, int b, int bit, unsigned xh
   __builtin_nontemporal_store(val, (__attribute__((address_space(1))) int*)((gchar*)addr + voff));
 }
 
+// Planes an emission variant handles: DMAX 3 takes 0..3, 7 takes 4..7, 15
+// takes 8..15, 16 takes 16.
+template <int DMAX>
+__device__ __forceinline__ int emit_dmin() {
+  return DMAX <= 3 ? 0 : DMAX <= 7 ? 4 : DMAX <= 15 ? 8 : 16;
+}
+
+__device__ __forceinline__ int bit_length_dev(int x) { return x > 0 ? 32 - __clz(x) : 0; }
+
+// Lanes of word w to emit: the mask, or without one every lane < emit_k.
+__device__ __forceinline__ u64 emit_word(const BatchArgs& a, const u64* emask, int w) {
+  if (emask) return emask[w];
+  const int lo = w * 64;
+  if (a.emit_k >= lo + 64) return ~0ull;
+  return a.emit_k > lo ? (1ull << (a.emit_k - lo)) - 1ull : 0ull;
+}
+
+// mode bit 0 (kEmitClear): remove the emitted lanes' bits from vis and the
+// planes; bit 1 (kEmitFromRun): the run state decides: emit only after a run
+// that finished, with D = bit_length of its last level, and only in the
+// variant whose plane range holds D; bit 2 (kEmitMarkClean): every lane is
+// emitted with kEmitClear, so the workspace holds no bits afterwards.
 template <int DMAX, int EG>
 __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
                                                           const u64* __restrict__ emask,
-                                                          int clear, int claim) {
+                                                          int mode, int claim) {
+  const int clear = mode & kEmitClear;
+  if (mode & kEmitFromRun) {
+    const BatchRun& r = a.ctrl->run;
+    if (ld_relaxed(&r.done) != 1 || ld_relaxed(&a.flags[kFlagStatus]) != 0) return;
+    D = min(bit_length_dev(ld_relaxed(&r.last_nonempty)), a.nplanes);
+    if (D < emit_dmin<DMAX>() || D > DMAX) return;
+  }
+  if ((mode & kEmitMarkClean) && blockIdx.x == 0 && threadIdx.x == 0) a.flags[kFlagDirty] = 0;
   // the row pointers of all lanes, staged once: a per-word global load in the
   // store loop would wait for every store before it
   __shared__ u64 srow[kMaxBatchLanes];
   const int lane = lane_id();
   const int W = a.W;
-  for (int i = threadIdx.x; i < W * 64; i += kBatchBlock) srow[i] = (u64)a.rows[i];
+  for (int i = threadIdx.x; i < W * 64; i += kBatchBlock)
+    srow[i] = a.rows ? (u64)a.rows[i]
+                     : (i < a.emit_k ? (u64)(a.row_base + (size_t)i * (size_t)a.row_stride) : 0ull);
   __syncthreads();
   const int gw = __builtin_amdgcn_readfirstlane(
       (int)((blockIdx.x * (unsigned)kBatchBlock + threadIdx.x) / kWave));
@@ -904,7 +948,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
     // emits a few lanes at a time)
     unsigned wm = 0;
     for (int e = 0; e < ew; ++e)
-      if (emask[w0 + e]) wm |= 1u << e;
+      if (emit_word(a, emask, w0 + e)) wm |= 1u << e;
     if (!wm) continue;
     const bool live = v < a.n;
     const bool full = (int)(t % ntiles) * kWave + kWave <= a.n;  // no lane past the last node
@@ -955,7 +999,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
     }
 #pragma unroll 1
     for (int e = 0; e < ew; ++e) {
-      u64 em = emask[w0 + e];
+      u64 em = emit_word(a, emask, w0 + e);
       if (!em) continue;
       // word e of the staged rows, picked out with selects so that the
       // staging arrays stay in registers
@@ -1051,12 +1095,20 @@ __global__ __launch_bounds__(kBatchBlock) void batch_zero_list(ZeroList z) {
 // bits become the active words, the direction of level L is chosen by the
 // batched rule (pull iff the frontier's out-degree x nonzero words times
 // alpha reaches n x words), and level L's counter slot is cleared.
-__global__ __launch_bounds__(kWave) void batch_control(BatchArgs a, u64* act, int L, int direction,
-                                                      double alpha) {
+//
+// The run also stops here (done = 2) when level L would need more level
+// planes than the workspace holds or exceeds n levels (the watchdog), and
+// (done = 3) when the call's sources were found invalid.  Called by one wave.
+__device__ __forceinline__ void control_level(const BatchArgs& a, u64* act, int L, int direction,
+                                              double alpha) {
   BatchCtrl* c = a.ctrl;
   BatchRun* r = &c->run;
   if (ld_relaxed(&r->done)) return;
   const int lane = lane_id();
+  if (ld_relaxed(&a.flags[kFlagStatus]) != 0) {
+    if (lane == 0) r->done = 3;
+    return;
+  }
   const int pl = (L - 1) & 1, cl = L & 1;
   const int W = a.W;
   u64 x = 0;
@@ -1094,6 +1146,9 @@ __global__ __launch_bounds__(kWave) void batch_control(BatchArgs a, u64* act, in
     if (bits) r->last_nonempty = L - 1;
     if (!any) {
       r->done = 1;
+    } else if (L > a.n + 1 || bit_length_dev(L) > a.nplanes) {
+      r->done = 2;
+      atomicMax(&a.flags[kFlagStatus], 2u);
     } else {
       const bool pull = direction == 2 ||
                         (direction != 1 && (double)mfw * alpha >= (double)a.n * (double)W);
@@ -1106,21 +1161,29 @@ __global__ __launch_bounds__(kWave) void batch_control(BatchArgs a, u64* act, in
   }
 }
 
+__global__ __launch_bounds__(kWave) void batch_control(BatchArgs a, u64* act, int L, int direction,
+                                                      double alpha) {
+  control_level(a, act, L, direction, alpha);
+}
+
 // Lane lane[i] starts at node src[i] at level L: its bit joins the new bits
 // of level L (nxt) and the node joins that level's frontier bitmap.  With
 // `live` (sources admitted after level L's merge ran) the seed also does the
-// merge's part: the visited bit and the big-degree chunks.
+// merge's part: the visited bit and the big-degree chunks.  lane == null:
+// source i takes lane i.  A source outside [0, n) is skipped (device-ordered
+// calls find it beforehand and stop the run).
 __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane, int k, int L,
                            int live) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[kFlagDirty] = 1;
   // whole waves walk the sources so that chunk listing is wave-aggregated
   const int stride = gridDim.x * blockDim.x;
   for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); i0 < k; i0 += stride) {
     const int i = i0 + lane_id();
     int s = 0, deg = 0;
     bool first = false;
-    if (i < k) {
+    if (i < k && (unsigned)src[i] < (unsigned)a.n) {
       s = src[i];
-      const int l = lane[i];
+      const int l = lane ? lane[i] : i;
       const size_t idx = (size_t)s * a.Ws + (l >> 6);
       const u64 bit = 1ull << (l & 63);
       atom_or(&a.nxt[L & 1][idx], bit);
@@ -1137,10 +1200,83 @@ __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane,
   }
 }
 
+// Start of a batched run: the control block is cleared, and the bitmap
+// arrays too when the workspace may still hold bits (its first run, or a run
+// that stopped before its emission); after a complete run the emission has
+// already left them clear.  z.p[0] is the control block.  clear_status:
+// reset the run status (device-ordered calls set it once per call instead).
+__global__ __launch_bounds__(kBatchBlock) void batch_prepare(ZeroList z, unsigned* flags,
+                                                            int clear_status) {
+  // nothing in this launch writes the flag, so every workgroup reads the same
+  const bool dirty = ld_relaxed(&flags[kFlagDirty]) != 0;
+  const size_t t0 = blockIdx.x * (size_t)kBatchBlock + threadIdx.x;
+  const size_t nt = (size_t)gridDim.x * kBatchBlock;
+  for (int y = 0; y < z.k; ++y) {
+    if (y > 0 && !dirty) break;
+    u64* p = z.p[y];
+    for (size_t i = t0; i < z.count[y]; i += nt) p[i] = 0;
+  }
+  if (clear_status && t0 == 0) flags[kFlagStatus] = 0;
+}
+
+// Device-ordered calls: the run status is 1 when a source lies outside
+// [0, n), else 0 (one workgroup; every batch's first control step stops on 1).
+__global__ __launch_bounds__(1024) void batch_validate(const int32_t* src, long long k, int n,
+                                                      unsigned* flags) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  bool b = false;
+  for (long long i = threadIdx.x; i < k; i += blockDim.x) b = b || (unsigned)src[i] >= (unsigned)n;
+  if (b) bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) flags[kFlagStatus] = bad ? 1u : 0u;
+}
+
+// The call's status for the caller (device memory): DAWN_OK, DAWN_E_INVALID_ARG
+// (a source outside [0, n): no row was written) or DAWN_E_DEVICE (watchdog).
+__global__ void batch_status(const unsigned* flags, int32_t* out) {
+  const unsigned f = ld_relaxed(&flags[kFlagStatus]);
+  *out = f == 0 ? DAWN_OK : f == 1 ? DAWN_E_INVALID_ARG : DAWN_E_DEVICE;
+}
+
+// The levels after the queued ones, in one cooperative launch: per level the
+// first wave runs the control step, then every workgroup the chosen
+// expansion and the merge, with a grid barrier between the steps.  Returns at
+// once when the queued levels already reached the end of the run.
+template <int P>
+__global__ __launch_bounds__(kBatchBlock) void batch_finish_levels(BatchArgs a, u64* act, int L0,
+                                                                  int direction, double alpha) {
+  BatchRun* r = &a.ctrl->run;
+  GridBarrier* bar = &a.ctrl->bar;
+  // read before any workgroup can write it (the first write follows the
+  // barrier below), so every workgroup takes the same branch
+  if (ld_relaxed(&r->done)) return;
+  bool ok = grid_sync(bar);
+  for (int L = L0; ok; ++L) {
+    if (blockIdx.x == 0 && threadIdx.x < kWave) control_level(a, act, L, direction, alpha);
+    if (!(ok = grid_sync(bar))) break;
+    if (ld_relaxed(&r->done)) return;
+    if (ld_relaxed(&r->pull))
+      pull_level<P>(a, L);
+    else
+      push_level<P>(a, L);
+    if (!(ok = grid_sync(bar))) break;
+    merge_level<P>(a, L);
+    ok = grid_sync(bar);
+  }
+  // a barrier wait timed out: the run stops with the watchdog status
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    r->done = 2;
+    atomicMax(&a.flags[kFlagStatus], 2u);
+  }
+}
+
 // ------------------------------------------------------------------ host --
 void batch_ws_destroy(BatchWs* w) {
   if (!w) return;
   Ctx* ctx = w->ctx;
+  if (w->busy_set) hipEventSynchronize(w->busy);
   dev_free(ctx, w->vis, 0);
   dev_free(ctx, w->nxt[0], 0);
   dev_free(ctx, w->nxt[1], 0);
@@ -1158,18 +1294,20 @@ void batch_ws_destroy(BatchWs* w) {
   dev_free(ctx, w->base, 0);
   dev_free(ctx, w->src, 0);
   dev_free(ctx, w->lane, 0);
-  dev_free(ctx, w->stage, 0);
+  dev_free(ctx, w->flags, 0);
   if (ctx) ctx->used -= w->bytes;
   if (ctx && w->plane_reserve) dev_unreserve(ctx, w->plane_reserve);
   if (w->h_ctrl) hipHostFree(w->h_ctrl);
   if (w->ev0) hipEventDestroy(w->ev0);
   if (w->ev1) hipEventDestroy(w->ev1);
+  if (w->busy) hipEventDestroy(w->busy);
   if (w->stream && w->own_stream) hipStreamDestroy(w->stream);
   delete w;
 }
 
-dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage_ints,
-                            BatchWs** out) {
+// A new workspace is marked as possibly holding bits, so its first run's
+// prepare step clears every array; afterwards complete runs leave it clear.
+dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, BatchWs** out) {
   BatchWs* w = new BatchWs();
   w->ctx = ctx;
   w->n = g->n;
@@ -1203,8 +1341,7 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   alloc((void**)&w->base, (size_t)kMaxBatchLanes * 4);
   alloc((void**)&w->src, (size_t)kMaxBatchLanes * 4);
   alloc((void**)&w->lane, (size_t)kMaxBatchLanes * 4);
-  if (stage_ints) alloc((void**)&w->stage, stage_ints * 4);
-  w->stage_ints = stage_ints;
+  alloc((void**)&w->flags, 256);
   if (s != DAWN_OK) {
     batch_ws_destroy(w);
     return s;
@@ -1214,6 +1351,11 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, size_t stage
   w->own_stream = true;
   if (e == hipSuccess) e = hipEventCreate(&w->ev0);
   if (e == hipSuccess) e = hipEventCreate(&w->ev1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&w->busy, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    static const unsigned init_flags[2] = {1u, 0u};   // dirty, status
+    e = hipMemcpy(w->flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     batch_ws_destroy(w);
     return fail(DAWN_E_DEVICE, "batch workspace: %s", hipGetErrorString(e));
@@ -1228,12 +1370,19 @@ dawn_status batch_ensure_planes(BatchWs* w, int need, int W) {
     return fail(DAWN_E_DEVICE, "batched traversal exceeds %d levels", (1 << kMaxPlanes) - 1);
   const size_t bytes = (size_t)w->n * (size_t)w->Wmax * 8;
   while (w->nplanes < need) {
+    // failure injection ($DAWN_FAIL_PLANE_AFTER = N): the plane allocation
+    // after the next N fails once (a run that fails part-way through)
+    const long long left = w->ctx->fail_plane_after.load();
+    if (left >= 0) {
+      w->ctx->fail_plane_after.fetch_sub(1);
+      if (left == 0) return fail(DAWN_E_NO_MEMORY, "level plane refused (injected failure)");
+    }
     u64* p = nullptr;
     const bool res = w->plane_reserve >= bytes;
     DAWN_TRY(dev_alloc(w->ctx, (void**)&p, bytes, res));
     if (res) w->plane_reserve -= bytes;
     w->bytes += bytes;
-    DAWN_HIP(hipMemsetAsync(p, 0, bytes, w->stream));
+    DAWN_TRY(batch_launch_zero(w->ctx, p, bytes / 8, w->stream));
     w->planes[w->nplanes++] = p;
   }
   (void)W;
@@ -1269,6 +1418,7 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W) {
   a.act = w->act;
   a.rows = w->rows;
   a.base = w->base;
+  a.flags = w->flags;
   return a;
 }
 
@@ -1341,7 +1491,7 @@ dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t 
 }
 
 template <int DMAX, int EG>
-static dawn_status launch_emit_t(Ctx* ctx, const BatchArgs& a, int D, const u64* d_emask, bool clear,
+static dawn_status launch_emit_t(Ctx* ctx, const BatchArgs& a, int D, const u64* d_emask, int mode,
                                  hipStream_t s) {
   // one resident wave per slot: the tasks are equal, so a grid larger than
   // what fits at once would only add a tail
@@ -1358,7 +1508,7 @@ static dawn_status launch_emit_t(Ctx* ctx, const BatchArgs& a, int D, const u64*
       1, std::min<long long>((tasks + per_block - 1) / per_block, (long long)ctx->num_cu * occ));
   const int claim = tasks >= 4 * (long long)grid * per_block ? 1 : 0;
   hipLaunchKernelGGL((batch_emit<DMAX, EG>), dim3(grid), dim3(kBatchBlock), 0, s, a, D, d_emask,
-                     clear ? 1 : 0, claim);
+                     mode, claim);
   DAWN_HIP(hipGetLastError());
   return DAWN_OK;
 }
@@ -1366,12 +1516,20 @@ static dawn_status launch_emit_t(Ctx* ctx, const BatchArgs& a, int D, const u64*
 // The level planes a lane holds take (1 + DMAX) x EG register pairs; the
 // word group shrinks as the planes grow so that stays at 64 words.
 dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, const u64* d_emask,
-                              bool clear, hipStream_t s) {
+                              int mode, hipStream_t s) {
+  if (mode & kEmitFromRun) {
+    // the plane count is known on the device only: every variant is queued
+    // and the one whose range holds it runs
+    DAWN_TRY((launch_emit_t<3, 16>(ctx, a, 0, d_emask, mode, s)));
+    DAWN_TRY((launch_emit_t<7, 8>(ctx, a, 0, d_emask, mode, s)));
+    DAWN_TRY((launch_emit_t<15, 4>(ctx, a, 0, d_emask, mode, s)));
+    return launch_emit_t<16, 2>(ctx, a, 0, d_emask, mode, s);
+  }
   const int D = nplanes_used;
-  if (D <= 3) return launch_emit_t<3, 16>(ctx, a, D, d_emask, clear, s);
-  if (D <= 7) return launch_emit_t<7, 8>(ctx, a, D, d_emask, clear, s);
-  if (D <= 15) return launch_emit_t<15, 4>(ctx, a, D, d_emask, clear, s);
-  return launch_emit_t<16, 2>(ctx, a, D, d_emask, clear, s);
+  if (D <= 3) return launch_emit_t<3, 16>(ctx, a, D, d_emask, mode, s);
+  if (D <= 7) return launch_emit_t<7, 8>(ctx, a, D, d_emask, mode, s);
+  if (D <= 15) return launch_emit_t<15, 4>(ctx, a, D, d_emask, mode, s);
+  return launch_emit_t<16, 2>(ctx, a, D, d_emask, mode, s);
 }
 
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s) {
@@ -1436,6 +1594,53 @@ static int bit_length(int x) {
   return b;
 }
 
+// The prepare step's list: the control block first, then every array a run
+// writes, whole (an earlier run may have used a wider row stride).
+static ZeroList prepare_list(const GraphRec* g, const BatchWs* w) {
+  ZeroList z;
+  memset(&z, 0, sizeof(z));
+  auto add = [&z](void* p, size_t count) {
+    z.p[z.k] = (u64*)p;
+    z.count[z.k++] = count;
+  };
+  const size_t nW = (size_t)g->n * (size_t)w->Wmax;
+  const size_t nwords = ((size_t)g->n + 63) / 64;
+  add(w->ctrl, sizeof(BatchCtrl) / 8);
+  add(w->vis, nW);
+  add(w->nxt[0], nW);
+  add(w->nxt[1], nW);
+  add(w->touched[0], nwords);
+  add(w->touched[1], nwords);
+  add(w->fmap[0], (size_t)g->n);
+  add(w->fmap[1], (size_t)g->n);
+  for (int b = 0; b < w->nplanes; ++b) add(w->planes[b], nW);
+  return z;
+}
+
+static dawn_status batch_launch_prepare(Ctx* ctx, const GraphRec* g, BatchWs* w, bool clear_status,
+                                        hipStream_t s) {
+  static_assert(8 + kMaxPlanes <= kZeroMax, "prepare list too long");
+  const ZeroList z = prepare_list(g, w);
+  const size_t most = (size_t)g->n * (size_t)w->Wmax;
+  const int gx = (int)std::max<size_t>(
+      1, std::min<size_t>((most + kBatchBlock - 1) / kBatchBlock, (size_t)ctx->num_cu * 4));
+  hipLaunchKernelGGL(batch_prepare, dim3(gx), dim3(kBatchBlock), 0, s, z, w->flags,
+                     clear_status ? 1 : 0);
+  DAWN_HIP(hipGetLastError());
+  return DAWN_OK;
+}
+
+// The rows of a dawn_mssp batch: lane r writes row_base + r x row_stride, all
+// lanes < k are emitted, every source joins at level 0.
+static void set_rows(BatchArgs& a, int32_t* row_base, long long row_stride, int k) {
+  a.rows = nullptr;
+  a.row_base = row_base;
+  a.row_stride = row_stride;
+  a.emit_k = k;
+  a.base = nullptr;
+  a.gated = 1;
+}
+
 // One batch of k <= lanes sources through the level loop, in steps so that
 // several batches (each on its own workspace and stream) can run side by
 // side: begin, then chunks of levels (enqueue, and after a stream sync,
@@ -1445,6 +1650,8 @@ struct BatchJob {
   int k = 0;
   int W = 0;
   BatchArgs a;
+  int32_t* row_base = nullptr;
+  long long row_stride = 0;
   int L = 1;        // first level of the next chunk
   int Lend = 0;     // last level of the chunk in flight
   int chunk = 4;
@@ -1453,55 +1660,22 @@ struct BatchJob {
 };
 
 static dawn_status batch_begin(Ctx* ctx, const GraphRec* g, BatchJob& j, const int32_t* h_src,
-                               int k, int32_t* const* h_rows) {
+                               int k) {
   BatchWs* w = j.w;
   j.k = k;
   j.W = (k + 63) / 64;
-  const int W = j.W;
   hipStream_t s = w->stream;
-  const size_t nW = (size_t)g->n * W;
-  std::vector<int32_t> zeros(64 * W, 0);
-  std::vector<u64> em(W, ~0ull);
-  if (k % 64) em[W - 1] = (1ull << (k % 64)) - 1ull;
-  std::vector<int32_t*> rows(64 * W, nullptr);
-  for (int r = 0; r < k; ++r) rows[r] = h_rows[r];
-  std::vector<int32_t> lanes(k);
-  for (int r = 0; r < k; ++r) lanes[r] = r;
   DAWN_HIP(hipMemcpyAsync(w->src, h_src, (size_t)k * 4, hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemcpyAsync(w->lane, lanes.data(), (size_t)k * 4, hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemcpyAsync(w->rows, rows.data(), rows.size() * sizeof(int32_t*),
-                          hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemcpyAsync(w->base, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, s));
-  DAWN_HIP(hipMemcpyAsync(w->emask, em.data(), (size_t)W * 8, hipMemcpyHostToDevice, s));
   DAWN_HIP(hipEventRecord(w->ev0, s));
-  {
-    ZeroList z;
-    memset(&z, 0, sizeof(z));
-    auto add = [&z](void* p, size_t count) {
-      z.p[z.k] = (u64*)p;
-      z.count[z.k++] = count;
-    };
-    const size_t nwords = ((size_t)g->n + 63) / 64;
-    add(w->ctrl, sizeof(BatchCtrl) / 8);
-    add(w->vis, nW);
-    add(w->nxt[0], nW);
-    add(w->nxt[1], nW);
-    add(w->touched[0], nwords);
-    add(w->touched[1], nwords);
-    add(w->fmap[0], (size_t)g->n);
-    add(w->fmap[1], (size_t)g->n);
-    for (int b = 0; b < w->planes_dirty; ++b) add(w->planes[b], nW);
-    DAWN_TRY(batch_launch_zero_list(ctx, z, s));
-  }
-  w->planes_dirty = 0;
-  j.a = batch_args(g, w, W);
-  j.a.gated = 1;
-  DAWN_TRY(batch_launch_seed(ctx, j.a, w->src, w->lane, k, 0, false, s));
+  DAWN_TRY(batch_launch_prepare(ctx, g, w, true, s));
+  j.a = batch_args(g, w, j.W);
+  set_rows(j.a, j.row_base, j.row_stride, k);
+  DAWN_TRY(batch_launch_seed(ctx, j.a, w->src, nullptr, k, 0, false, s));
   DAWN_TRY(batch_launch_merge(ctx, j.a, 0, s));
   j.launches = 3;
   j.L = 1;
   const int hint = g->batch_hint.load(std::memory_order_relaxed);
-  j.chunk = hint > 0 ? hint : 4;
+  j.chunk = hint > 0 ? std::min(hint, 64) : 4;
   j.done = false;
   return DAWN_OK;
 }
@@ -1523,9 +1697,8 @@ static dawn_status batch_enqueue(Ctx* ctx, const GraphRec* g, const dawn_params&
   if (need > w->nplanes) {
     DAWN_TRY(batch_ensure_planes(w, need, j.W));
     j.a = batch_args(g, w, j.W);
-    j.a.gated = 1;
+    set_rows(j.a, j.row_base, j.row_stride, j.k);
   }
-  w->planes_dirty = std::max(w->planes_dirty, need);
   for (int l = L; l <= Lend; ++l) {
     DAWN_TRY(batch_launch_control(j.a, w->act, l, p, s));
     DAWN_TRY(batch_launch_expand(ctx, j.a, false, l, s));
@@ -1540,13 +1713,16 @@ static dawn_status batch_enqueue(Ctx* ctx, const GraphRec* g, const dawn_params&
 }
 
 // After the stream has drained the chunk.
-static void batch_check(BatchJob& j) {
-  if (j.w->h_ctrl->run.done) {
+static dawn_status batch_check(BatchJob& j) {
+  const BatchRun& r = j.w->h_ctrl->run;
+  if (r.done == 1) {
     j.done = true;
-    return;
+    return DAWN_OK;
   }
+  if (r.done) return fail(DAWN_E_DEVICE, "batched level loop stopped (watchdog)");
   j.L = j.Lend + 1;
   j.chunk = std::min(j.chunk * 2, 64);
+  return DAWN_OK;
 }
 
 static dawn_status batch_finish(Ctx* ctx, const GraphRec* g, BatchJob& j, BatchTotals* tot) {
@@ -1560,7 +1736,9 @@ static dawn_status batch_finish(Ctx* ctx, const GraphRec* g, BatchJob& j, BatchT
   const int last_nonempty = run.last_nonempty;
   // expansions 1 .. last_nonempty + 1, then the control step that ends the run
   g->batch_hint.store(std::min(last_nonempty + 2, 64), std::memory_order_relaxed);
-  DAWN_TRY(batch_launch_emit(ctx, j.a, bit_length(last_nonempty), w->emask, false, w->stream));
+  // every lane is emitted and its bits cleared: the workspace is left clear
+  DAWN_TRY(batch_launch_emit(ctx, j.a, bit_length(last_nonempty), nullptr,
+                             kEmitClear | kEmitMarkClean, w->stream));
   j.launches += 1;
   DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   tot->launches += j.launches;
@@ -1572,16 +1750,67 @@ static dawn_status batch_finish(Ctx* ctx, const GraphRec* g, BatchJob& j, BatchT
 // in one batch's level kernels.
 constexpr int kConcurrentBatches = 4;
 
-static BatchWs* pool_take(GraphRec* g, int lanes, size_t stage) {
+static BatchWs* pool_take(GraphRec* g, int lanes) {
   std::lock_guard<std::mutex> lk(g->mu);
   for (size_t i = 0; i < g->batch_pool.size(); ++i) {
     BatchWs* c = g->batch_pool[i];
-    if (c->lanes >= lanes && c->stage_ints >= stage) {
+    if (c->lanes >= lanes) {
       g->batch_pool.erase(g->batch_pool.begin() + i);
       return c;
     }
   }
   return nullptr;
+}
+
+static void pool_give(GraphRec* g, BatchWs* w) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->batch_pool.push_back(w);
+}
+
+// A workspace from the pool, or a new one; work on stream s then follows the
+// last work queued on it (by a call on any stream).
+// (s == null: the workspace's own stream).
+static dawn_status ws_acquire(Ctx* ctx, GraphRec* g, int lanes, const hipStream_t* s,
+                              BatchWs** out) {
+  BatchWs* w = pool_take(g, lanes);
+  if (!w) DAWN_TRY(batch_ws_create(ctx, g, lanes, &w));
+  if (w->busy_set) {
+    hipError_t e = hipStreamWaitEvent(s ? *s : w->stream, w->busy, 0);
+    if (e != hipSuccess) {
+      pool_give(g, w);
+      return fail(DAWN_E_DEVICE, "stream wait: %s", hipGetErrorString(e));
+    }
+  }
+  *out = w;
+  return DAWN_OK;
+}
+
+// Device staging of host-destination rows, kept per graph between calls.
+static dawn_status stage_take(Ctx* ctx, GraphRec* g, size_t bytes, int32_t** out) {
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->stage && g->stage_bytes >= bytes) {
+      *out = g->stage;
+      g->stage = nullptr;
+      return DAWN_OK;
+    }
+  }
+  return dev_alloc(ctx, (void**)out, bytes);
+}
+
+static void stage_give(Ctx* ctx, GraphRec* g, int32_t* p, size_t bytes) {
+  int32_t* drop = p;
+  size_t drop_bytes = bytes;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->stage || g->stage_bytes < bytes) {
+      drop = g->stage;
+      drop_bytes = g->stage_bytes;
+      g->stage = p;
+      g->stage_bytes = bytes;
+    }
+  }
+  if (drop) dev_free(ctx, drop, drop_bytes);
 }
 
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources, int32_t k,
@@ -1591,19 +1820,25 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
   const int lanes = std::min(p.batch_lanes, kMaxBatchLanes);
   const int nbatches = (int)(((int64_t)k + lanes - 1) / lanes);
   const int kb_max = std::min(lanes, (int)k);
-  const size_t stage = device_out ? 0 : (size_t)kb_max * (size_t)g->n;
+  // host destination: every row is staged on the device and copied out once
+  // all batches have finished, so a failure leaves dist untouched
+  int32_t* stage = nullptr;
+  const size_t stage_bytes = device_out ? 0 : (size_t)k * (size_t)g->n * 4;
+  if (!device_out) DAWN_TRY(stage_take(ctx, g, stage_bytes, &stage));
   // workspaces: from the pool, then new ones while the budget allows (at
   // least one, or the call fails)
   std::vector<BatchWs*> ws;
   const int want = std::max(1, std::min(nbatches, kConcurrentBatches));
   while ((int)ws.size() < want) {
-    BatchWs* w = pool_take(g, kb_max, stage);
-    if (!w) {
-      dawn_status cs = batch_ws_create(ctx, g, kb_max, stage, &w);
-      if (cs != DAWN_OK) {
-        if (ws.empty()) return cs;
-        break;
+    BatchWs* w = nullptr;
+    dawn_status cs = ws_acquire(ctx, g, kb_max, nullptr, &w);
+    if (cs != DAWN_OK) {
+      if (ws.empty()) {
+        // a failed call keeps no staging: the budget goes back at once
+        if (stage) dev_free(ctx, stage, stage_bytes);
+        return cs;
       }
+      break;
     }
     ws.push_back(w);
   }
@@ -1611,7 +1846,6 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
   BatchTotals tot;
   memset(&tot, 0, sizeof(tot));
   dawn_status st = DAWN_OK;
-  std::vector<std::vector<int32_t*>> rows(conc, std::vector<int32_t*>(kb_max));
   std::vector<BatchJob> jobs(conc);
   for (int bg = 0; bg < nbatches && st == DAWN_OK; bg += conc) {
     const int nj = std::min(conc, nbatches - bg);
@@ -1621,10 +1855,9 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
       BatchJob& j = jobs[i];
       j = BatchJob();
       j.w = ws[i];
-      for (int r = 0; r < kb; ++r)
-        rows[i][r] = device_out ? dist + (size_t)(b0 + r) * row_stride
-                                : ws[i]->stage + (size_t)r * g->n;
-      st = batch_begin(ctx, g, j, sources + b0, kb, rows[i].data());
+      j.row_base = device_out ? dist + (size_t)b0 * row_stride : stage + (size_t)b0 * g->n;
+      j.row_stride = device_out ? row_stride : g->n;
+      st = batch_begin(ctx, g, j, sources + b0, kb);
     }
     // chunks of levels, all running batches side by side
     for (bool busy = true; busy && st == DAWN_OK;) {
@@ -1638,7 +1871,7 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
           st = fail(DAWN_E_DEVICE, "batched level loop: %s", hipGetErrorString(e));
           break;
         }
-        batch_check(jobs[i]);
+        st = batch_check(jobs[i]);
         busy |= !jobs[i].done;
       }
     }
@@ -1654,20 +1887,28 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
         break;
       }
       group_ms = std::max(group_ms, ms);
-      if (!device_out) {
-        const int64_t b0 = (int64_t)(bg + i) * lanes;
-        e = hipMemcpy2DAsync(dist + (size_t)b0 * row_stride, (size_t)row_stride * 4, ws[i]->stage,
-                             (size_t)g->n * 4, (size_t)g->n * 4, jobs[i].k,
-                             hipMemcpyDeviceToHost, ws[i]->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ws[i]->stream);
-        if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "copy to host: %s", hipGetErrorString(e));
-      }
     }
     tot.kernel_ms += group_ms;
   }
+  if (st == DAWN_OK && !device_out) {
+    hipError_t e = hipMemcpy2DAsync(dist, (size_t)row_stride * 4, stage, (size_t)g->n * 4,
+                                    (size_t)g->n * 4, (size_t)k, hipMemcpyDeviceToHost,
+                                    ws[0]->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ws[0]->stream);
+    if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "copy to host: %s", hipGetErrorString(e));
+  }
+  if (stage) {
+    for (BatchWs* w : ws) hipStreamSynchronize(w->stream);
+    if (st == DAWN_OK)
+      stage_give(ctx, g, stage, stage_bytes);
+    else
+      dev_free(ctx, stage, stage_bytes);
+  }
   if (st == DAWN_OK) {
-    std::lock_guard<std::mutex> lk(g->mu);
-    for (BatchWs* w : ws) g->batch_pool.push_back(w);
+    for (BatchWs* w : ws) {
+      w->busy_set = false;   // every stream of the call has drained
+      pool_give(g, w);
+    }
   } else {
     for (BatchWs* w : ws) {
       hipStreamSynchronize(w->stream);
@@ -1686,6 +1927,124 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
     stats->kernel_ms = tot.kernel_ms;
     stats->total_ms = (now_ns() - t0) / 1e6;
   }
+  return DAWN_OK;
+}
+
+// ------------------------------------------------- device-ordered batches --
+__global__ void write_status(int32_t* out, int32_t v) { *out = v; }
+
+template <int P>
+static dawn_status launch_finish_t(Ctx* ctx, const BatchArgs& a, u64* act, int L0,
+                                   const dawn_params& p, hipStream_t s) {
+  static std::atomic<int> occ_cache{0};
+  int occ = occ_cache.load(std::memory_order_relaxed);
+  if (!occ) {
+    DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_finish_levels<P>, kBatchBlock, 0));
+    if (occ < 1) return fail(DAWN_E_DEVICE, "cooperative level kernel cannot be resident");
+    occ_cache.store(occ, std::memory_order_relaxed);
+  }
+  BatchArgs args = a;
+  int l0 = L0;
+  int dir = p.direction;
+  double alpha = (double)p.batch_alpha;
+  void* kargs[] = {&args, &act, &l0, &dir, &alpha};
+  DAWN_HIP(hipLaunchCooperativeKernel((const void*)batch_finish_levels<P>,
+                                      dim3(occ * ctx->num_cu), dim3(kBatchBlock), kargs, 0, s));
+  return DAWN_OK;
+}
+
+static dawn_status launch_finish(Ctx* ctx, const BatchArgs& a, u64* act, int L0,
+                                 const dawn_params& p, hipStream_t s) {
+  switch (pow2_at_least(a.W)) {
+    case 1: return launch_finish_t<1>(ctx, a, act, L0, p, s);
+    case 2: return launch_finish_t<2>(ctx, a, act, L0, p, s);
+    case 4: return launch_finish_t<4>(ctx, a, act, L0, p, s);
+    case 8: return launch_finish_t<8>(ctx, a, act, L0, p, s);
+    case 16: return launch_finish_t<16>(ctx, a, act, L0, p, s);
+    case 32: return launch_finish_t<32>(ctx, a, act, L0, p, s);
+    case 64: return launch_finish_t<64>(ctx, a, act, L0, p, s);
+    default: return fail(DAWN_E_INVALID_ARG, "batch too wide");
+  }
+}
+
+// Levels queued as separate launches before the cooperative tail takes over.
+constexpr int kDeviceHintMax = 256;
+
+dawn_status mssp_device_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* d_src,
+                            int32_t k, int32_t* d_dist, int32_t* d_status, hipStream_t s) {
+  if (k <= 0) {
+    if (d_status) {
+      hipLaunchKernelGGL(write_status, dim3(1), dim3(1), 0, s, d_status, (int32_t)DAWN_OK);
+      DAWN_HIP(hipGetLastError());
+    }
+    return DAWN_OK;
+  }
+  const int lanes = std::min(p.batch_lanes, kMaxBatchLanes);
+  const int kb_max = std::min(lanes, (int)k);
+  BatchWs* w = nullptr;
+  DAWN_TRY(ws_acquire(ctx, g, kb_max, &s, &w));
+  // the last device-ordered run on this workspace, if it has finished, tells
+  // how many levels to queue as separate launches
+  if (w->busy_set && hipEventQuery(w->busy) == hipSuccess && w->h_ctrl->run.done == 1)
+    g->batch_hint.store(std::min(w->h_ctrl->run.last_nonempty + 2, kDeviceHintMax),
+                        std::memory_order_relaxed);
+  // planes for the deepest run a graph of n nodes can have (fewer than n
+  // levels), up to kMaxPlanes: the planes cannot grow while the run is queued
+  const int need = std::min(kMaxPlanes, std::max(1, bit_length(g->n)));
+  dawn_status st = DAWN_OK;
+  if (need > w->nplanes) {
+    // zeroed on the workspace's stream, which the call's stream then follows
+    st = batch_ensure_planes(w, need, 0);
+    if (st == DAWN_OK) {
+      hipError_t e = hipEventRecord(w->busy, w->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, w->busy, 0);
+      if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "stream wait: %s", hipGetErrorString(e));
+    }
+  }
+  if (st == DAWN_OK) {
+    hipLaunchKernelGGL(batch_validate, dim3(1), dim3(1024), 0, s, d_src, (long long)k, g->n,
+                       w->flags);
+    if (hipGetLastError() != hipSuccess) st = fail(DAWN_E_DEVICE, "validate launch failed");
+  }
+  const int hint0 = g->batch_hint.load(std::memory_order_relaxed);
+  const int hint = hint0 > 0 ? std::min(hint0, kDeviceHintMax) : 8;
+  for (int64_t b0 = 0; b0 < k && st == DAWN_OK; b0 += lanes) {
+    const int kb = (int)std::min<int64_t>(lanes, k - b0);
+    const int W = (kb + 63) / 64;
+    st = batch_launch_prepare(ctx, g, w, false, s);
+    BatchArgs a = batch_args(g, w, W);
+    set_rows(a, d_dist + (size_t)b0 * g->n, g->n, kb);
+    if (st == DAWN_OK) st = batch_launch_seed(ctx, a, d_src + b0, nullptr, kb, 0, false, s);
+    if (st == DAWN_OK) st = batch_launch_merge(ctx, a, 0, s);
+    for (int l = 1; l <= hint && st == DAWN_OK; ++l) {
+      st = batch_launch_control(a, w->act, l, p, s);
+      if (st == DAWN_OK) st = batch_launch_expand(ctx, a, false, l, s);
+      if (st == DAWN_OK) st = batch_launch_expand(ctx, a, true, l, s);
+      if (st == DAWN_OK) st = batch_launch_merge(ctx, a, l, s);
+    }
+    if (st == DAWN_OK) st = launch_finish(ctx, a, w->act, hint + 1, p, s);
+    if (st == DAWN_OK)
+      st = batch_launch_emit(ctx, a, 0, nullptr, kEmitClear | kEmitFromRun | kEmitMarkClean, s);
+  }
+  if (st == DAWN_OK && d_status) {
+    hipLaunchKernelGGL(batch_status, dim3(1), dim3(1), 0, s, w->flags, d_status);
+    if (hipGetLastError() != hipSuccess) st = fail(DAWN_E_DEVICE, "status launch failed");
+  }
+  if (st == DAWN_OK) {
+    hipError_t e = hipMemcpyAsync(&w->h_ctrl->run, &w->ctrl->run, sizeof(BatchRun),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(w->busy, s);
+    if (e != hipSuccess) st = fail(DAWN_E_DEVICE, "device-ordered batch: %s", hipGetErrorString(e));
+  }
+  if (st != DAWN_OK) {
+    // launches may be queued on the caller's stream: drain it before the
+    // workspace goes
+    hipStreamSynchronize(s);
+    batch_ws_destroy(w);
+    return st;
+  }
+  w->busy_set = true;
+  pool_give(g, w);
   return DAWN_OK;
 }
 

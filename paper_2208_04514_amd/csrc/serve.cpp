@@ -60,7 +60,7 @@ struct Engine {
   int capacity = 0;
   int L = 0;                       // last level merged
   bool running = false;
-  bool dirty = false;              // something was seeded and not yet run
+  bool broken = false;             // a step failed: its queries ended; rebuilt once idle
   hipEvent_t lev_ev = nullptr;
   std::vector<Query*> owner;       // per lane
   std::vector<u64> busy;           // lanes held by a query
@@ -146,7 +146,7 @@ static dawn_status engine_create(Server* S, const std::shared_ptr<GraphRec>& g, 
   }
   e->capacity = p.batch_lanes;
   e->W = (e->capacity + 63) / 64;
-  dawn_status st = batch_ws_create(S->ctx, g.get(), e->capacity, 0, &e->ws);
+  dawn_status st = batch_ws_create(S->ctx, g.get(), e->capacity, &e->ws);
   if (st != DAWN_OK) {
     e->ws = nullptr;
     engine_destroy_raw(e);
@@ -208,13 +208,22 @@ static dawn_status engine_create(Server* S, const std::shared_ptr<GraphRec>& g, 
 
 static void engine_destroy(Engine* e) { engine_destroy_raw(e); }
 
-// Admit queued queries of this engine's graph (FIFO) into free lanes.
-// Returns the number admitted; S->mu held.
-static int admit(Server* S, Engine* e) {
-  int admitted = 0;
+// A query that does not fit the free lanes lets later, smaller queries of
+// its graph pass it while it has waited less than this; after that nothing
+// passes it, so the lanes drain for it.
+constexpr uint64_t kBypassNs = 20000000;
+
+// Admit queued queries of this engine's graph into free lanes, in arrival
+// order, with the bounded bypass above.  Their sources are added to the seeds
+// the next launch_level issues.  Returns the query that waits for device
+// memory (its host-destination staging), or null; S->mu held.
+static Query* admit(Server* S, Engine* e) {
+  Query* mem_wait = nullptr;
   BatchWs* w = e->ws;
-  e->nseed = 0;
+  if (e->broken) return nullptr;
   int lo = e->capacity, hi = -1;
+  bool blocked = false;   // an earlier query of this graph waits for lanes
+  const uint64_t now = now_ns();
   for (auto it = S->pending.begin(); it != S->pending.end();) {
     Query* q = *it;
     if (q->g.get() != e->g.get()) {
@@ -222,11 +231,21 @@ static int admit(Server* S, Engine* e) {
       continue;
     }
     const int k = (int)q->src.size();
-    if (k > e->capacity - e->busy_count) break;   // arrival order: wait for lanes
+    if (k > e->capacity - e->busy_count) {
+      if (!blocked) {
+        blocked = true;
+        if (now - q->qs.submit_ns >= kBypassNs) break;
+      }
+      ++it;
+      continue;
+    }
     if (!q->device_out) {
       const size_t bytes = (size_t)k * e->g->n * 4;
       void* p = nullptr;
-      if (dev_alloc(S->ctx, &p, bytes) != DAWN_OK) break;   // wait for memory to free up
+      if (dev_alloc(S->ctx, &p, bytes) != DAWN_OK) {   // wait for memory to free up
+        mem_wait = q;
+        break;
+      }
       q->stage = (int32_t*)p;
       q->stage_bytes = bytes;
     }
@@ -254,7 +273,6 @@ static int admit(Server* S, Engine* e) {
     q->qs.admit_ns = now_ns();
     q->qs.batch_peak = std::max(q->qs.batch_peak, e->busy_count);
     it = S->pending.erase(it);
-    ++admitted;
   }
   if (hi >= lo) {
     hipMemcpyAsync(w->rows + lo, e->h_rows + lo, (size_t)(hi - lo + 1) * sizeof(int32_t*),
@@ -262,7 +280,7 @@ static int admit(Server* S, Engine* e) {
     hipMemcpyAsync(w->base + lo, e->h_base + lo, (size_t)(hi - lo + 1) * 4, hipMemcpyHostToDevice,
                    w->stream);
   }
-  return admitted;
+  return mem_wait;
 }
 
 // Launch seeds (if any) and the next level of engine e.  S->mu held.
@@ -357,7 +375,7 @@ static dawn_status level_done(Server* S, Engine* e) {
   int min_base = L;
   for (Query* q : done) min_base = std::min(min_base, q->base);
   const int D = std::min(w->nplanes, bit_length(L - min_base));
-  DAWN_TRY(batch_launch_emit(S->ctx, a, D, w->emask, true, s));
+  DAWN_TRY(batch_launch_emit(S->ctx, a, D, w->emask, kEmitClear, s));
   for (Query* q : done) {
     hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
     hipEventRecord(q->ev, s);
@@ -373,12 +391,34 @@ static dawn_status level_done(Server* S, Engine* e) {
   return DAWN_OK;
 }
 
+// A step of the engine failed: its running queries end with `st`, their
+// lanes are released, and the engine takes no more work; the scheduler
+// destroys it once its last emissions have drained and builds a fresh one
+// (with clear bitmaps) for the next query of the graph.
 static void engine_fail(Server* S, Engine* e, dawn_status st) {
   for (int lane = 0; lane < e->capacity; ++lane) {
     Query* q = e->owner[lane];
     if (!q) continue;
     for (int l : q->lanes) e->owner[l] = nullptr;
     finish_query(S, q, st);
+  }
+  std::fill(e->busy.begin(), e->busy.end(), 0ull);
+  std::fill(e->act.begin(), e->act.end(), 0ull);
+  e->busy_count = 0;
+  e->nseed = 0;
+  e->broken = true;
+}
+
+// Engines of other graphs that hold no work give their memory back.
+static void reclaim_idle(Server* S, const Engine* keep) {
+  for (auto it = S->engines.begin(); it != S->engines.end();) {
+    Engine* x = it->second;
+    if (x != keep && !x->running && x->busy_count == 0 && x->emitting.empty()) {
+      engine_destroy(x);
+      it = S->engines.erase(it);
+    } else {
+      ++it;
+    }
   }
 }
 
@@ -422,15 +462,7 @@ static void scheduler_main(Server* S) {
       dawn_status st = engine_create(S, q->g, &e);
       if (st != DAWN_OK) {
         // give the memory of idle engines back, then try once more
-        for (auto e2 = S->engines.begin(); e2 != S->engines.end();) {
-          Engine* x = e2->second;
-          if (!x->running && x->busy_count == 0 && x->emitting.empty()) {
-            engine_destroy(x);
-            e2 = S->engines.erase(e2);
-          } else {
-            ++e2;
-          }
-        }
+        reclaim_idle(S, nullptr);
         st = engine_create(S, q->g, &e);
       }
       if (st == DAWN_OK) {
@@ -452,7 +484,8 @@ static void scheduler_main(Server* S) {
         std::lock_guard<std::mutex> gl(e->g->mu);
         want = e->g->params.batch_lanes;
       }
-      if (want != e->capacity && !e->running && e->busy_count == 0 && e->emitting.empty()) {
+      const bool idle = !e->running && e->busy_count == 0 && e->emitting.empty();
+      if ((want != e->capacity || e->broken) && idle) {
         engine_destroy(e);
         it = S->engines.erase(it);
         progressed = true;
@@ -460,37 +493,70 @@ static void scheduler_main(Server* S) {
         ++it;
       }
     }
+    Engine* mem_engine = nullptr;
     for (auto& kv : S->engines) {
       Engine* e = kv.second;
       // queries whose rows are written
       for (auto it = e->emitting.begin(); it != e->emitting.end();) {
         Query* q = *it;
-        if (hipEventQuery(q->ev) == hipSuccess) {
-          if (q->device_out) {
-            finish_query(S, q, DAWN_OK);
-          } else {
-            S->copies.push_back(q);
-            S->copy_cv.notify_one();
-          }
-          it = e->emitting.erase(it);
-          progressed = true;
-        } else {
+        const hipError_t qe = hipEventQuery(q->ev);
+        if (qe == hipErrorNotReady) {
           ++it;
+          continue;
         }
+        if (qe != hipSuccess) {
+          (void)hipGetLastError();
+          finish_query(S, q, fail(DAWN_E_DEVICE, "serving emission: %s", hipGetErrorString(qe)));
+        } else if (q->device_out) {
+          finish_query(S, q, DAWN_OK);
+        } else {
+          S->copies.push_back(q);
+          S->copy_cv.notify_one();
+        }
+        it = e->emitting.erase(it);
+        progressed = true;
       }
       if (e->running) {
-        if (hipEventQuery(e->lev_ev) != hipSuccess) continue;
+        const hipError_t le = hipEventQuery(e->lev_ev);
+        if (le == hipErrorNotReady) continue;
         e->running = false;
-        dawn_status st = level_done(S, e);
+        dawn_status st = le == hipSuccess
+                             ? level_done(S, e)
+                             : fail(DAWN_E_DEVICE, "serving level: %s", hipGetErrorString(le));
         if (st != DAWN_OK) engine_fail(S, e, st);
         progressed = true;
       }
-      admit(S, e);
+      if (e->broken) continue;
+      if (admit(S, e) && !mem_engine) mem_engine = e;
       bool any = false;
       for (u64 x : e->act) any |= x != 0;
       if (any) {
         dawn_status st = launch_level(S, e);
         if (st != DAWN_OK) engine_fail(S, e, st);
+        progressed = true;
+      }
+    }
+    if (mem_engine) {
+      // a query waits for staging memory: idle engines of other graphs give
+      // theirs back; if nothing else holds memory, it can never be admitted
+      reclaim_idle(S, mem_engine);
+      Query* q = admit(S, mem_engine);
+      if (q) {
+        bool others = !S->copies.empty() || mem_engine->running || mem_engine->busy_count > 0 ||
+                      !mem_engine->emitting.empty();
+        for (auto& kv : S->engines) others |= kv.second != mem_engine;
+        if (!others) {
+          S->pending.erase(std::find(S->pending.begin(), S->pending.end(), q));
+          finish_query(S, q, fail(DAWN_E_NO_MEMORY, "no device memory for the query's rows"));
+          progressed = true;
+        }
+      } else {
+        bool any = false;
+        for (u64 x : mem_engine->act) any |= x != 0;
+        if (any && !mem_engine->running) {
+          dawn_status st = launch_level(S, mem_engine);
+          if (st != DAWN_OK) engine_fail(S, mem_engine, st);
+        }
         progressed = true;
       }
     }

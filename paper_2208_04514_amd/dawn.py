@@ -36,7 +36,7 @@ EXPORTED = (
     "dawn_create", "dawn_destroy", "dawn_last_error", "dawn_memory", "dawn_graph_upload",
     "dawn_graph_release", "dawn_graph_get_info", "dawn_get_params", "dawn_set_params",
     "dawn_sssp", "dawn_mssp", "dawn_apsp_wcc", "dawn_autotune", "dawn_serve_submit",
-    "dawn_serve_poll", "dawn_serve_wait",
+    "dawn_serve_poll", "dawn_serve_wait", "dawn_mssp_device",
 )
 
 
@@ -133,6 +133,7 @@ def load(path: str | None = None):
         "dawn_serve_submit": [V, I32, V, I32, V, U32, ctypes.POINTER(U64)],
         "dawn_serve_poll": [V, U64, ctypes.POINTER(QueryStats)],
         "dawn_serve_wait": [V, U64, I32, ctypes.POINTER(QueryStats)],
+        "dawn_mssp_device": [V, I32, V, I32, V, V, V],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -165,19 +166,65 @@ def _is_torch_cuda(x) -> bool:
     return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
 
 
-def _out_ptr(out, count: int):
-    """(pointer, flags, keepalive) for an output of `count` int32."""
+# Facts the binding keeps per context and graph, so that an output buffer can
+# be checked against what the library will write before the call is made:
+# the device of each context, and n of each resident graph (ids are never
+# reused within a context).
+_CTX_DEVICE: dict[int, int] = {}
+_GRAPH_N: dict[tuple[int, int], int] = {}
+
+
+def _ctx_key(ctx) -> int:
+    return int(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx or 0)
+
+
+def _graph_n(ctx, graph: int) -> int:
+    key = (_ctx_key(ctx), int(graph))
+    n = _GRAPH_N.get(key)
+    if n is None:
+        n = dawn_graph_get_info(ctx, graph)["n"]
+        _GRAPH_N[key] = n
+    return n
+
+
+def check_out(out, shape: tuple, device: int | None = None):
+    """Validate an output buffer for a call that writes ``prod(shape)`` int32.
+
+    ``out`` must hold exactly that many elements (its shape may be flat or
+    ``shape``): a host ``numpy`` int32 C-contiguous array, or a contiguous
+    int32 torch CUDA tensor on ``device`` (the context's GPU).  Returns
+    ``(pointer, flags, keepalive)``; raises ``ValueError`` before any library
+    call when the buffer does not match.
+    """
+    count = 1
+    for d in shape:
+        count *= int(d)
     if _is_torch_cuda(out):
         import torch
-        if out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < count:
-            raise ValueError("device output must be a contiguous int32 CUDA tensor of enough size")
-        # the library writes on its own stream: finish pending torch work first
-        torch.cuda.current_stream(out.device).synchronize()
+        if out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("device output must be a contiguous int32 CUDA tensor")
+        if out.numel() != count or (out.dim() > 1 and tuple(out.shape) != tuple(shape)):
+            raise ValueError(f"device output has shape {tuple(out.shape)}, the call writes {tuple(shape)}")
+        if device is not None and out.device.index != device:
+            raise ValueError(f"device output is on cuda:{out.device.index}, the context on cuda:{device}")
         return ctypes.c_void_p(out.data_ptr()), DAWN_DEVICE_OUT, out
     if not (isinstance(out, np.ndarray) and out.dtype == np.int32 and out.flags.c_contiguous
-            and out.size >= count):
-        raise ValueError("host output must be a C-contiguous int32 numpy array of enough size")
+            and out.flags.writeable):
+        raise ValueError("host output must be a writeable C-contiguous int32 numpy array")
+    if out.size != count or (out.ndim > 1 and out.shape != tuple(shape)):
+        raise ValueError(f"host output has shape {out.shape}, the call writes {tuple(shape)}")
     return out.ctypes.data_as(ctypes.c_void_p), 0, out
+
+
+def _out_ptr(ctx, out, shape: tuple):
+    """check_out against the context's device; a synchronous call with device
+    output first lets pending torch work on the caller's stream finish (the
+    library writes on its own streams)."""
+    ptr, flags, keep = check_out(out, shape, _CTX_DEVICE.get(_ctx_key(ctx)))
+    if flags & DAWN_DEVICE_OUT:
+        import torch
+        torch.cuda.current_stream(out.device).synchronize()
+    return ptr, flags, keep
 
 
 # -------------------------------------------------------------- entry points --
@@ -185,11 +232,16 @@ def _out_ptr(out, count: int):
 def dawn_create(device: int = 0, hbm_budget_bytes: int = 0) -> ctypes.c_void_p:
     h = ctypes.c_void_p()
     _check(load().dawn_create(device, hbm_budget_bytes, ctypes.byref(h)))
+    _CTX_DEVICE[_ctx_key(h)] = int(device)
     return h
 
 
 def dawn_destroy(ctx) -> None:
+    key = _ctx_key(ctx)
     _check(load().dawn_destroy(ctx))
+    _CTX_DEVICE.pop(key, None)
+    for gk in [gk for gk in _GRAPH_N if gk[0] == key]:
+        del _GRAPH_N[gk]
 
 
 def dawn_memory(ctx) -> tuple[int, int]:
@@ -206,11 +258,13 @@ def dawn_graph_upload(ctx, row_ptr, col, flags: int = 0) -> int:
     _check(load().dawn_graph_upload(ctx, n, int(c.size), rp.ctypes.data_as(ctypes.c_void_p),
                                     c.ctypes.data_as(ctypes.c_void_p) if c.size else None,
                                     flags, ctypes.byref(g)))
+    _GRAPH_N[(_ctx_key(ctx), g.value)] = n
     return g.value
 
 
 def dawn_graph_release(ctx, graph: int) -> None:
     _check(load().dawn_graph_release(ctx, graph))
+    _GRAPH_N.pop((_ctx_key(ctx), int(graph)), None)
 
 
 def dawn_graph_get_info(ctx, graph: int) -> dict:
@@ -234,19 +288,16 @@ def dawn_set_params(ctx, graph: int, **kw) -> dict:
     return dawn_get_params(ctx, graph)
 
 
-def dawn_sssp(ctx, graph: int, source: int, out=None, n: int | None = None,
-              frontier_cap: int = 0):
+def dawn_sssp(ctx, graph: int, source: int, out=None, frontier_cap: int = 0):
     """Distances from `source`.  `out`: numpy int32[n] or torch int32 CUDA tensor.
 
     Returns ``(out, stats)``; with ``frontier_cap`` > 0 the stats dict also has
     ``frontier_sizes`` and ``directions`` lists.
     """
+    n = _graph_n(ctx, graph)
     if out is None:
-        if n is None:
-            n = dawn_graph_get_info(ctx, graph)["n"]
         out = np.empty(n, dtype=np.int32)
-    n = out.numel() if _is_torch_cuda(out) else out.size
-    ptr, flags, _keep = _out_ptr(out, n)
+    ptr, flags, _keep = _out_ptr(ctx, out, (n,))
     st = RunStats()
     if frontier_cap > 0:
         fs = np.zeros(frontier_cap, np.int32)
@@ -263,26 +314,50 @@ def dawn_sssp(ctx, graph: int, source: int, out=None, n: int | None = None,
     return out, d
 
 
-def dawn_mssp(ctx, graph: int, sources, out=None, n: int | None = None):
+def dawn_mssp(ctx, graph: int, sources, out=None):
     """Row r = distances from sources[r].  `out`: int32 [k, n] numpy or torch CUDA."""
-    src = _host_i32(sources)
+    src = _host_i32(sources).ravel()
     k = src.size
+    n = _graph_n(ctx, graph)
     if out is None:
-        if n is None:
-            n = dawn_graph_get_info(ctx, graph)["n"]
         out = np.empty((k, n), dtype=np.int32)
-    count = out.numel() if _is_torch_cuda(out) else out.size
-    ptr, flags, _keep = _out_ptr(out, count)
+    ptr, flags, _keep = _out_ptr(ctx, out, (k, n))
     st = RunStats()
     _check(load().dawn_mssp(ctx, graph, src.ctypes.data_as(ctypes.c_void_p), k, ptr, flags,
                             ctypes.byref(st)))
     return out, st.as_dict()
 
 
+def dawn_mssp_device(ctx, graph: int, sources, out, status=None, stream=None):
+    """Queue a multi-source run on a torch stream (default: the current one).
+
+    ``sources``: int32 CUDA tensor of k node ids; ``out``: int32 CUDA tensor
+    [k, n]; ``status`` (optional): int32 CUDA tensor of one element that
+    receives the run's status on the stream.  Returns at once: later work on
+    the stream sees the rows; nothing here waits for the device.
+    """
+    import torch
+    dev = _CTX_DEVICE.get(_ctx_key(ctx))
+    if not (_is_torch_cuda(sources) and sources.dtype == torch.int32 and sources.is_contiguous()
+            and sources.dim() == 1):
+        raise ValueError("sources must be a contiguous 1-D int32 CUDA tensor")
+    if dev is not None and sources.device.index != dev:
+        raise ValueError(f"sources are on cuda:{sources.device.index}, the context on cuda:{dev}")
+    k = int(sources.numel())
+    ptr, _flags, _keep = check_out(out, (k, _graph_n(ctx, graph)), dev)
+    sp = None
+    if status is not None:
+        sp, _f, _k = check_out(status, (1,), dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    _check(load().dawn_mssp_device(ctx, graph, ctypes.c_void_p(sources.data_ptr()), k, ptr, sp,
+                                   ctypes.c_void_p(stream.cuda_stream)))
+    return out
+
+
 def dawn_apsp_wcc(ctx, graph: int, out=None, query_only: bool = False):
     """(wcc_nodes, dist [s_wcc, s_wcc] or None, stats)."""
-    info = dawn_graph_get_info(ctx, graph)
-    nodes = np.empty(info["n"], np.int32)
+    nodes = np.empty(_graph_n(ctx, graph), np.int32)
     s = ctypes.c_int32(0)
     st = RunStats()
     lib = load()
@@ -290,12 +365,12 @@ def dawn_apsp_wcc(ctx, graph: int, out=None, query_only: bool = False):
         _check(lib.dawn_apsp_wcc(ctx, graph, nodes.ctypes.data_as(ctypes.c_void_p),
                                  ctypes.byref(s), None, 0, ctypes.byref(st)))
         return nodes[: s.value].copy(), None, st.as_dict()
+    # the component's size first: the call writes s_wcc x s_wcc
+    _check(lib.dawn_apsp_wcc(ctx, graph, nodes.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(s), None, 0, None))
     if out is None:
-        _check(lib.dawn_apsp_wcc(ctx, graph, nodes.ctypes.data_as(ctypes.c_void_p),
-                                 ctypes.byref(s), None, 0, None))
         out = np.empty((s.value, s.value), np.int32)
-    count = out.numel() if _is_torch_cuda(out) else out.size
-    ptr, flags, _keep = _out_ptr(out, max(count, 0))
+    ptr, flags, _keep = _out_ptr(ctx, out, (s.value, s.value))
     _check(lib.dawn_apsp_wcc(ctx, graph, nodes.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
                              ptr, flags, ctypes.byref(st)))
     return nodes[: s.value].copy(), out, st.as_dict()
@@ -311,9 +386,9 @@ def dawn_autotune(ctx, graph: int, sources, what: int = 3) -> dict:
 
 def dawn_serve_submit(ctx, graph: int, sources, out) -> int:
     """Queue a query; `out` (int32 [k, n], numpy or torch CUDA) must stay alive until done."""
-    src = _host_i32(sources)
-    count = out.numel() if _is_torch_cuda(out) else out.size
-    ptr, flags, _keep = _out_ptr(out, count)
+    src = _host_i32(sources).ravel()
+    ptr, flags, _keep = check_out(out, (src.size, _graph_n(ctx, graph)),
+                                  _CTX_DEVICE.get(_ctx_key(ctx)))
     t = ctypes.c_uint64(0)
     _check(load().dawn_serve_submit(ctx, graph, src.ctypes.data_as(ctypes.c_void_p), src.size,
                                     ptr, flags, ctypes.byref(t)))

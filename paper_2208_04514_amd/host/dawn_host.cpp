@@ -4,15 +4,23 @@
 //
 // One source, N threads: the threads of a team share every level.  The
 // frontier is an array of node ids with the exclusive prefix sum of their
-// out-degrees, so the level's work is a range of edges: each thread takes
-// blocks of kEdgeBlock edges through one atomic counter (a hub's row is
-// split over many blocks), finds the block's first node by binary search in
-// the prefix, walks the edges, claims unreached targets with an atomic OR on
-// a visited bitmap, writes their distance and appends them, with their
-// out-degrees, to its own next-frontier list.  At the level's end (a spinning
-// barrier) the lists are concatenated in parallel into the next frontier at
-// offsets from prefix sums over the threads.  The loop ends when a level
-// adds no node.
+// out-degrees, so the level's work is a range of edges.  A level has two
+// phases, so that no cache line of the visited bitmap is written by two
+// threads (on a many-core host such lines bounce between cores on every
+// claim, and every visited test then misses):
+//  1. expand: each thread takes blocks of kEdgeBlock edges through one atomic
+//     counter (a hub's row is split over many blocks), finds the block's first
+//     node by binary search in the prefix and walks the edges; a target whose
+//     visited bit is clear (the bitmap is only read in this phase) goes to the
+//     bucket of the thread that owns it (thread t owns a contiguous range of
+//     nodes, a whole number of 512-node bitmap lines);
+//  2. claim: each thread takes the targets bucketed for it by every thread,
+//     sets their visited bits (plain stores to its own lines), writes their
+//     distance and appends them, with their out-degrees, to its own
+//     next-frontier list.
+// At the level's end (a spinning barrier) the lists are concatenated in
+// parallel into the next frontier at offsets from prefix sums over the
+// threads.  The loop ends when a level adds no node.
 #include "dawn_host.h"
 
 #include <algorithm>
@@ -82,6 +90,7 @@ class SpinBarrier {
 };
 
 struct alignas(64) ThreadOut {
+  std::vector<std::vector<int32_t>> bucket;   // [owner] targets found for that thread
   std::vector<int32_t> next;   // nodes this thread claimed in the current level
   std::vector<int32_t> deg;    // ... and their out-degrees
   int64_t level_edges = 0;     // sum of deg
@@ -95,7 +104,8 @@ struct Team {
   const dawn_host_graph* g;
   int nthreads;
   int32_t* dist;
-  std::unique_ptr<std::atomic<uint64_t>[]> vis;
+  std::vector<uint64_t> vis;
+  int32_t own = 0;                   // nodes owned per thread (multiple of 512)
   std::vector<int32_t> front, next;
   std::vector<int64_t> fpre, npre;   // exclusive prefix of out-degrees over the frontier
   std::vector<ThreadOut> out;
@@ -109,7 +119,9 @@ struct Team {
   Team(const dawn_host_graph* gr, int t, int32_t* d)
       : g(gr), nthreads(t), dist(d), out(t), bar(t) {
     const size_t nw = ((size_t)g->n + 63) / 64;
-    vis.reset(new std::atomic<uint64_t>[nw]);
+    vis.resize(nw);
+    own = (int32_t)((((int64_t)g->n + t - 1) / t + 511) / 512 * 512);
+    for (auto& o : out) o.bucket.resize((size_t)t);
     front.resize((size_t)g->n);
     next.resize((size_t)g->n);
     fpre.resize((size_t)g->n);
@@ -124,12 +136,12 @@ struct Team {
       const size_t lo = (size_t)n * tid / nthreads, hi = (size_t)n * (tid + 1) / nthreads;
       for (size_t i = lo; i < hi; ++i) dist[i] = -1;
       const size_t wlo = nw * tid / nthreads, whi = nw * (tid + 1) / nthreads;
-      for (size_t i = wlo; i < whi; ++i) vis[i].store(0, std::memory_order_relaxed);
+      for (size_t i = wlo; i < whi; ++i) vis[i] = 0;
     }
     bar.wait();
     if (tid == 0) {
       dist[source] = 0;
-      vis[source >> 6].fetch_or(1ull << (source & 63), std::memory_order_relaxed);
+      vis[source >> 6] |= 1ull << (source & 63);
       front[0] = source;
       fpre[0] = 0;
       fsize = 1;
@@ -146,7 +158,9 @@ struct Team {
       me.next.clear();
       me.deg.clear();
       me.level_edges = 0;
-      // expand: blocks of the frontier's edge range taken in turn
+      for (auto& b : me.bucket) b.clear();
+      // 1. expand: blocks of the frontier's edge range taken in turn; the
+      // bitmap is read-only until the barrier
       for (;;) {
         const int64_t x = cursor.fetch_add(kEdgeBlock, std::memory_order_relaxed);
         if (x >= ftotal) break;
@@ -162,18 +176,25 @@ struct Team {
           const int32_t base = g->rp[u] - (int32_t)fpre[i];
           for (int64_t p = pos; p < stop; ++p) {
             const int32_t v = g->col[base + p];
-            const uint64_t bit = 1ull << (v & 63);
-            std::atomic<uint64_t>& w = vis[v >> 6];
-            if (w.load(std::memory_order_relaxed) & bit) continue;
-            if (w.fetch_or(bit, std::memory_order_relaxed) & bit) continue;
-            dist[v] = L;
-            const int32_t d = g->rp[v + 1] - g->rp[v];
-            me.next.push_back(v);
-            me.deg.push_back(d);
-            me.level_edges += d;
+            if (vis[v >> 6] & (1ull << (v & 63))) continue;
+            me.bucket[(size_t)(v / own)].push_back(v);
           }
           pos = stop;
           ++i;
+        }
+      }
+      bar.wait();
+      // 2. claim the targets in this thread's range (its own bitmap lines)
+      for (int t = 0; t < nthreads; ++t) {
+        for (const int32_t v : out[(size_t)t].bucket[(size_t)tid]) {
+          const uint64_t bit = 1ull << (v & 63);
+          if (vis[v >> 6] & bit) continue;
+          vis[v >> 6] |= bit;
+          dist[v] = L;
+          const int32_t d = g->rp[v + 1] - g->rp[v];
+          me.next.push_back(v);
+          me.deg.push_back(d);
+          me.level_edges += d;
         }
       }
       me.reached += (int64_t)me.next.size();

@@ -56,3 +56,25 @@ int main(void) {
             ctypes.sizeof(D.GraphInfo), D.GraphInfo.device_bytes.offset,
             ctypes.sizeof(D.QueryStats), D.QueryStats.batch_peak.offset]
     assert got == want
+
+
+def test_output_buffers_checked_before_any_call():
+    """A buffer that does not hold exactly what the call writes is refused by
+    the binding (the C ABI has no length argument to catch it)."""
+    import numpy as np
+    ptr, flags, _ = D.check_out(np.empty((3, 5), np.int32), (3, 5))
+    assert flags == 0 and ptr
+    D.check_out(np.empty(15, np.int32), (3, 5))           # flat of the same size
+    bad = [np.empty((2, 5), np.int32),                    # too short
+           np.empty((3, 6), np.int32),                    # too long
+           np.empty((5, 3), np.int32),                    # same size, other shape
+           np.empty((3, 5), np.int64),                    # wrong dtype
+           np.empty((5, 3), np.int32).T,                  # not C-contiguous
+           [0] * 15]
+    for b in bad:
+        with pytest.raises(ValueError):
+            D.check_out(b, (3, 5))
+    ro = np.empty((3, 5), np.int32)
+    ro.flags.writeable = False
+    with pytest.raises(ValueError):
+        D.check_out(ro, (3, 5))

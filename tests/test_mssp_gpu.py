@@ -169,10 +169,8 @@ def test_mssp_matches_sssp(ctx, upload):
 
 
 def test_full_size_rmat18_4096(ctx, upload):
-    """The batched workload at full size: R-MAT 18, 4096 sources in one launch.
-
-    The oracle runs 64 sampled rows (all 4096 would take minutes of CPU); every
-    row is also checked against properties that hold at any size."""
+    """The batched workload at full size: R-MAT 18, 4096 sources in one launch,
+    every one of the 4096 rows compared with the oracle (16 host threads)."""
     import torch
     h, g, src = upload("rmat18")
     assert src.size == 4096
@@ -182,17 +180,130 @@ def test_full_size_rmat18_4096(ctx, upload):
     torch.cuda.synchronize()
     _say(f"  levels {st['levels']} push {st['push_levels']} pull {st['pull_levels']} "
          f"kernel {st['kernel_ms']:.2f} ms GTEPS {st['source_edges'] / st['kernel_ms'] / 1e6:.1f}")
-    pick = np.random.default_rng(11).choice(4096, size=64, replace=False)
-    sub = out[torch.as_tensor(pick, device="cuda")].cpu().numpy()
-    _check_rows(g, src[pick], sub)
-    # any-size properties on every row: dist[s] = 0, and the reached set is the
-    # source's WCC (the graph is symmetric), so every row reaches the same set
-    full = out.cpu().numpy()
-    assert (full[np.arange(4096), src] == 0).all()
-    reach = full >= 0
-    assert (reach == reach[0]).all()
-    wcc = np.zeros(g.n, bool)
-    wcc[g.meta["wcc_nodes"]] = True
-    assert np.array_equal(reach[0], wcc)
-    deg = g.out_degree()
-    assert st["source_edges"] == 4096 * int(deg[wcc].sum())
+    got = out.cpu().numpy()
+    del out
+    _say("  oracle on all 4096 rows")
+    _check_rows(g, src, got, st, threads=16)
+
+
+def test_host_output_untouched_when_a_later_group_fails(dawn_lib):
+    """Host-destination rows are staged on the device and copied out only
+    after every batch has finished: a plane allocation refused in the second
+    group of side-by-side batches leaves the caller's buffer as it was."""
+    import os
+    # two directed-both-ways paths: 40 nodes (sources 0..255 sit on it via
+    # repeats: runs end before level 29, 6 planes) and 100 nodes (a source at
+    # its end needs level 99: a 7th plane, allocated in the second group)
+    a, b = 40, 100
+    e = [(i, i + 1) for i in range(a - 1)] + [(a + i, a + i + 1) for i in range(b - 1)]
+    g = gg.gen_edges(a + b, np.array(e, np.int64), symmetrize=True)
+    srcs = np.concatenate([np.resize(np.arange(a), 64 * 4), [a] * 10]).astype(np.int32)
+    os.environ["DAWN_FAIL_PLANE_AFTER"] = str(4 * 6)
+    try:
+        c = D.dawn_create(0, 0)
+    finally:
+        del os.environ["DAWN_FAIL_PLANE_AFTER"]
+    try:
+        h = D.dawn_graph_upload(c, g.row_ptr, g.col)
+        D.dawn_set_params(c, h, batch_lanes=64)
+        out = np.full((srcs.size, g.n), 55, np.int32)
+        with pytest.raises(D.DawnError) as ei:
+            D.dawn_mssp(c, h, srcs, out=out)
+        assert ei.value.status == D.DAWN_E_NO_MEMORY
+        assert (out == 55).all(), "a failed call wrote the caller's rows"
+        got, st = D.dawn_mssp(c, h, srcs, out=out)      # the injection fired once
+        _check_rows(g, srcs, got, st)
+    finally:
+        D.dawn_destroy(c)
+
+
+# ------------------------------------------------------- device-ordered runs --
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x, np.int32), device="cuda")
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid128ns", "uniform4096"])
+def test_device_ordered_rows(ctx, dawn_lib, name):
+    """dawn_mssp_device queues everything on the caller's stream: a fresh
+    graph queues 8 levels as launches and leaves the rest (grid128ns: about
+    250 levels) to the cooperative kernel; the next call queues the depth of
+    the finished run.  Rows and status are read after the stream only."""
+    import torch
+    g, _ = gg.load_config(name)
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)      # fresh: no depth hint yet
+    try:
+        for k, seed in ((100, 1), (64, 2), (1, 3)):
+            srcs = gg.sample_sources(g.n, k, 500 + seed)
+            out = torch.full((k, g.n), 9, dtype=torch.int32, device="cuda")
+            status = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                d_src = _dev(srcs)
+                _say(f"[mssp_device] {name} k={k}")
+                D.dawn_mssp_device(ctx, h, d_src, out, status)
+                res = out.clone()          # ordered after the queued run on s
+            s.synchronize()
+            assert int(status.item()) == D.DAWN_OK
+            _check_rows(g, srcs, res.cpu().numpy())
+    finally:
+        D.dawn_graph_release(ctx, h)
+
+
+def test_device_ordered_many_batches_and_streams(ctx, upload, params):
+    """Sources beyond one batch run batch after batch on the stream; two
+    streams share the graph's workspaces through events."""
+    import torch
+    h, g, _ = upload("rmat12")
+    params(h, batch_lanes=64)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a_src = gg.sample_sources(g.n, 64 * 3 + 5, 41)
+    b_src = gg.sample_sources(g.n, 70, 42)
+    a_out = torch.empty((a_src.size, g.n), dtype=torch.int32, device="cuda")
+    b_out = torch.empty((b_src.size, g.n), dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s1):
+        D.dawn_mssp_device(ctx, h, _dev(a_src), a_out)
+    with torch.cuda.stream(s2):
+        D.dawn_mssp_device(ctx, h, _dev(b_src), b_out)
+    torch.cuda.synchronize()
+    _check_rows(g, a_src, a_out.cpu().numpy())
+    _check_rows(g, b_src, b_out.cpu().numpy())
+    # the synchronous call after device-ordered ones on the same workspaces
+    got, st = D.dawn_mssp(ctx, h, b_src)
+    _check_rows(g, b_src, got, st)
+
+
+def test_device_ordered_errors(ctx, upload):
+    """An invalid source is found on the device: status INVALID_ARG and no row
+    written; host-side errors return at once; k == 0 writes only the status."""
+    import torch
+    h, g, src = upload("rmat12")
+    srcs = src[:10].copy()
+    srcs[7] = g.n
+    out = torch.full((10, g.n), 5, dtype=torch.int32, device="cuda")
+    status = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    D.dawn_mssp_device(ctx, h, _dev(srcs), out, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == D.DAWN_E_INVALID_ARG
+    assert bool((out == 5).all())
+    # the workspace is usable afterwards
+    D.dawn_mssp_device(ctx, h, _dev(src[:10]), out, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == D.DAWN_OK
+    _check_rows(g, src[:10], out.cpu().numpy())
+    empty = torch.empty((0, g.n), dtype=torch.int32, device="cuda")
+    D.dawn_mssp_device(ctx, h, _dev(np.empty(0, np.int32)), empty, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == D.DAWN_OK
+    lib = D.load()
+    host = np.zeros((10, g.n), np.int32)
+    d_src = _dev(src[:10])
+    st = lib.dawn_mssp_device(ctx, h, d_src.data_ptr(), 10, host.ctypes.data, None, None)
+    assert st == D.DAWN_E_INVALID_ARG and "device memory" in D.dawn_last_error()
+    small = torch.empty((9, g.n), dtype=torch.int32, device="cuda")
+    big_k = 1 << 20
+    st = lib.dawn_mssp_device(ctx, h, d_src.data_ptr(), big_k, small.data_ptr(), None, None)
+    assert st == D.DAWN_E_INVALID_ARG
+    st = lib.dawn_mssp_device(ctx, 987654, d_src.data_ptr(), 10, out.data_ptr(), None, None)
+    assert st == D.DAWN_E_NOT_FOUND

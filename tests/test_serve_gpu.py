@@ -181,3 +181,67 @@ def test_budget_queues_and_never_fits(dawn_lib):
         assert used <= budget
     finally:
         D.dawn_destroy(ctx)
+
+
+def test_engine_failure_releases_lanes(dawn_lib):
+    """A level plane refused in the middle of a served query ends that query
+    with DAWN_E_NO_MEMORY; its lanes are released (the engine is rebuilt), so
+    a query that needs every lane is still admitted and exact."""
+    import os
+    n = 300
+    g = gg.gen_edges(n, np.array([(i, i + 1) for i in range(n - 1)], np.int64), symmetrize=True)
+    os.environ["DAWN_FAIL_PLANE_AFTER"] = "3"      # the 4th plane: level 8 of the first query
+    try:
+        c = D.dawn_create(0, 0)
+    finally:
+        del os.environ["DAWN_FAIL_PLANE_AFTER"]
+    try:
+        h = D.dawn_graph_upload(c, g.row_ptr, g.col)
+        D.dawn_set_params(c, h, batch_lanes=64)
+        out = np.full((2, n), -3, np.int32)
+        t = D.dawn_serve_submit(c, h, np.array([0, n - 1], np.int32), out)
+        with pytest.raises(D.DawnError) as ei:
+            D.dawn_serve_wait(c, t, 60000)
+        assert ei.value.status == D.DAWN_E_NO_MEMORY
+        srcs = np.random.default_rng(4).integers(0, n, size=64).astype(np.int32)
+        full = np.empty((64, n), np.int32)
+        t = D.dawn_serve_submit(c, h, srcs, full)
+        _wait(c, t)
+        assert np.array_equal(full, oracle.mssp(g, srcs))
+    finally:
+        D.dawn_destroy(c)
+
+
+def test_served_mix_config_graphs(ctx, upload):
+    """The serving workload's own graphs at full size (R-MAT 16, R-MAT 20,
+    grid 1024^2, resident together): queries of 1..1024 sources (log-uniform)
+    from each graph's largest WCC arrive at random intervals and share the
+    batches.  Every row of every query equals the same query run alone
+    through dawn_mssp, and up to 8 rows per query equal the oracle's."""
+    import torch
+    graphs = [upload(name) for name in ("rmat16", "rmat20", "grid1024")]
+    rng = np.random.default_rng(2026)
+    work = []
+    for i in range(36):
+        gi = int(rng.integers(0, 3))
+        h, g, _ = graphs[gi]
+        k = _log_uniform_k(rng, 1024)
+        srcs = rng.choice(g.meta["wcc_nodes"], size=k, replace=False).astype(np.int32)
+        out = torch.full((k, g.n), -5, dtype=torch.int32, device="cuda")
+        work.append((gi, srcs, out, D.dawn_serve_submit(ctx, h, srcs, out)))
+        time.sleep(float(rng.exponential(0.002)))
+    peak = 0
+    for gi, srcs, out, t in work:
+        q = _wait(ctx, t, timeout_s=300)
+        peak = max(peak, q["batch_peak"])
+    torch.cuda.synchronize()
+    _say(f"[serve] config graphs: 36 queries, {sum(w[1].size for w in work)} sources, "
+         f"largest batch {peak}")
+    for gi, srcs, out, t in work:
+        h, g, _ = graphs[gi]
+        alone = torch.empty_like(out)
+        D.dawn_mssp(ctx, h, srcs, out=alone)
+        torch.cuda.synchronize()
+        assert torch.equal(out, alone), f"graph {g.name}: served rows differ from the alone run"
+        pick = srcs[:8]
+        assert np.array_equal(out[:8].cpu().numpy(), oracle.mssp(g, pick, threads=16))
