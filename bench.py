@@ -132,25 +132,29 @@ def run_plain(D, ctx, h, src, out, steps, warmup):
 def level_kernel_timing(D, ctx, h, src, out):
     """Per-launch time of the level-step kernel, measured with HIP events that
     bracket each launch on the stream it runs on (library timing mode 1, which
-    issues the same level launches one per host check).
-    Returns (total ms, launches, levels per source)."""
+    issues the same level launches one per host check).  The same pass also
+    sums each launch's own duration by the GPU's wall clock (first workgroup
+    start to last workgroup end, no dispatch gap).
+    Returns (total event ms, launches, levels per source, total clock ms)."""
     p = D.dawn_get_params(ctx, h)
     D.dawn_set_params(ctx, h, driver=2, timing=1)
-    ms, launches, levels = 0.0, 0, []
+    ms, launches, levels, clk = 0.0, 0, [], 0.0
     try:
         for i, s in enumerate(src):
             _, st = D.dawn_sssp(ctx, h, int(s), out=out[i])
             ms += st["kernel_ms"]
+            clk += st["kernel_clock_ms"]
             launches += st["launches"]
             levels.append(st["levels"])
     finally:
         D.dawn_set_params(ctx, h, **p)
-    return ms, launches, levels
+    return ms, launches, levels, clk
 
 
-def roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs):
+def roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs, lk_clock_ms=0.0):
     alg = plain_alg_bytes(g, dist_rows, lk_levels)
     achieved = alg / (lk_ms / 1e3) / 1e9
+    achieved_clk = alg / (lk_clock_ms / 1e3) / 1e9 if lk_clock_ms > 0 else None
     rec = traffic_record()
     traffic, note = None, "no counter record"
     if rec is not None:
@@ -166,6 +170,11 @@ def roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs):
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
         "kernel": "sssp_level", "launches": lk_launches,
         "avg_launch_us": round(lk_ms / lk_launches * 1e3, 3),
+        # the launches' own time (GPU wall clock in the kernel; what a
+        # profiler's kernel trace reports) and the fraction it gives
+        "avg_kernel_clock_us": round(lk_clock_ms / lk_launches * 1e3, 3) if lk_clock_ms else None,
+        "achieved_kernel_clock": round(achieved_clk, 2) if achieved_clk else None,
+        "frac_kernel_clock": round(achieved_clk / HBM_PEAK_GBS, 5) if achieved_clk else None,
         "alg_bytes_per_launch": round(alg / lk_launches, 1),
         "traffic_note": note,
     }
@@ -277,7 +286,6 @@ def uniform_bench(D, ctx, reps=20):
     hundred nodes)."""
     import torch
     import graphgen as gg
-    import oracle
     g, src = gg.load_config("uniform4096")
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
@@ -296,15 +304,14 @@ def uniform_bench(D, ctx, reps=20):
             lv += st["levels"]
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    same = bool(np.array_equal(out.cpu().numpy(), oracle.mssp(g, src)))
+    rows = out.cpu().numpy()
     D.dawn_graph_release(ctx, h)
-    return {"workload": "uniform4096_m32768_directed_8src_plain_sssp", "n": g.n, "m": g.m,
+    return rows, {"workload": "uniform4096_m32768_directed_8src_plain_sssp", "n": g.n, "m": g.m,
             "sources": int(src.size), "gteps": round(se / t / 1e9, 4),
             "gteps_device": round(se / ks / 1e6, 4),
             "us_per_source_p50": round(float(np.percentile(calls, 50)), 1),
             "us_per_source_p99": round(float(np.percentile(calls, 99)), 1),
-            "us_per_level": round(t / lv * 1e6, 2), "levels_per_source": round(lv / reps / src.size, 2),
-            "bit_exact": same}
+            "us_per_level": round(t / lv * 1e6, 2), "levels_per_source": round(lv / reps / src.size, 2)}
 
 
 def small_component_bench(D, ctx):
@@ -367,14 +374,20 @@ def grid_bench(D, ctx, k_src=4):
     return res
 
 
-def serve_run(D, ctx, graphs, queries, arrivals=None, window=48):
+def serve_run(D, ctx, graphs, queries, arrivals=None, window=48, host_out=False, keep_rows=0,
+              skip=0):
     """Submit `queries` [(graph index, sources)], at `arrivals` (seconds from
-    start; None = keep `window` queries in flight), and collect latencies."""
+    start; None = keep `window` queries in flight), and collect latencies
+    (submit -> done) of every query after the first `skip`.  host_out: rows
+    go to host arrays.  keep_rows: the first rows of each query are kept
+    (host copies) for a parity check.  Returns (seconds, latencies ms, source
+    edges, sources, graph index per latency, kept rows)."""
     import torch
     t0 = time.perf_counter()
     inflight = {}
-    lat, gis, se, ks = [], [], 0, 0
+    lat, gis, se, ks, kept = [], [], 0, 0, []
     i = 0
+    t_first = None
     while i < len(queries) or inflight:
         now = time.perf_counter() - t0
         while i < len(queries) and (
@@ -382,24 +395,38 @@ def serve_run(D, ctx, graphs, queries, arrivals=None, window=48):
                 (arrivals is not None and arrivals[i] <= now)):
             gi, srcs = queries[i]
             h, g, esum = graphs[gi]
-            out = torch.empty((srcs.size, g.n), dtype=torch.int32, device="cuda")
+            if host_out:
+                out = np.empty((srcs.size, g.n), np.int32)
+            else:
+                out = torch.empty((srcs.size, g.n), dtype=torch.int32, device="cuda")
             t = D.dawn_serve_submit(ctx, h, srcs, out)
-            inflight[t] = (out, int(esum[srcs].sum()), srcs.size, gi)
+            inflight[t] = (out, int(esum[srcs].sum()), srcs.size, gi, i)
             i += 1
         progressed = False
         for t in list(inflight):
             st, q = D.dawn_serve_poll(ctx, t)
             if st == D.DAWN_OK:
-                out, e, k, gi = inflight.pop(t)
-                lat.append((q["done_ns"] - q["submit_ns"]) / 1e6)
-                gis.append(gi)
-                se += e
-                ks += k
+                out, e, k, gi, qi = inflight.pop(t)
+                if qi >= skip:
+                    if t_first is None:
+                        t_first = q["submit_ns"]
+                    lat.append((q["done_ns"] - q["submit_ns"]) / 1e6)
+                    gis.append(gi)
+                    se += e
+                    ks += k
+                if keep_rows:
+                    # a device-side copy: no host wait inside the timed loop
+                    r = out[:keep_rows]
+                    kept.append((qi, r.copy() if host_out else r.clone()))
                 progressed = True
         if not progressed:
             time.sleep(0.0002)
     dt = time.perf_counter() - t0
-    return dt, np.array(lat), se, ks, np.array(gis)
+    kept = [(qi, r if isinstance(r, np.ndarray) else r.cpu().numpy()) for qi, r in kept]
+    # the served rows were torch allocations: hand their cached blocks back so
+    # that the library's own allocations (host-output staging) find the memory
+    torch.cuda.empty_cache()
+    return dt, np.array(lat), se, ks, np.array(gis), kept
 
 
 def _per_graph(names, lat, gis):
@@ -409,10 +436,14 @@ def _per_graph(names, lat, gis):
             for i, name in enumerate(names) if (gis == i).any()}
 
 
-def serving_bench(D, ctx, nq=200, seed=105):
-    """Three resident graphs, queries of 1..1024 sources (log-uniform), first
-    saturated (a window of queries in flight), then Poisson arrivals at 0.5
-    and 0.9 of the saturated query rate."""
+def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2):
+    """Three resident graphs, queries of 1..1024 sources (log-uniform) on a
+    uniformly chosen graph, sources from its largest WCC: first saturated (a
+    window of queries in flight) to find the capacity, then Poisson arrivals
+    at 0.5 and 0.9 of that query rate, and at 0.5 with host-destination rows.
+    Each run submits `nq` queries and discards the first `skip` as warm-up.
+    The first `keep` rows of every query of the saturated run are returned
+    for the oracle check."""
     import graphgen as gg
     graphs = []
     names = ("rmat16", "rmat20", "grid1024")
@@ -428,30 +459,50 @@ def serving_bench(D, ctx, nq=200, seed=105):
         k = max(1, min(k, 1024))
         pool = graphs[gi][1].meta["wcc_nodes"]
         queries.append((gi, rng.choice(pool, size=k, replace=False).astype(np.int32)))
-    warm = queries[:20]
-    serve_run(D, ctx, graphs, warm)
-    dt, lat, se, ks, gis = serve_run(D, ctx, graphs, queries)
+    serve_run(D, ctx, graphs, queries[:20])
+    dt, lat, se, ks, gis, kept = serve_run(D, ctx, graphs, queries, skip=skip, keep_rows=keep)
     cap_qps = len(queries) / dt
-    res = {"graphs": list(names), "queries": nq,
+    res = {"graphs": list(names), "queries": nq, "warmup_discarded": skip,
            "mean_k": round(float(np.mean([q[1].size for q in queries])), 1),
            "saturated": {"qps": round(cap_qps, 1), "sources_per_s": round(ks / dt, 1),
                          "gteps": round(se / dt / 1e9, 2),
                          "p50_ms": round(float(np.percentile(lat, 50)), 3),
                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
                          "per_graph": _per_graph(names, lat, gis)}}
-    for frac in (0.5, 0.9):
+    for label, frac, host in (("load_0.5", 0.5, False), ("load_0.9", 0.9, False),
+                              ("load_0.5_host_output", 0.5, True)):
         lam = frac * cap_qps
         arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
-        dt, lat, se, ks, gis = serve_run(D, ctx, graphs, queries, arrivals=arr)
-        res[f"load_{frac}"] = {"offered_qps": round(lam, 1), "gteps": round(se / dt / 1e9, 2),
-                               "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                               "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                               "per_graph": _per_graph(names, lat, gis)}
+        dt, lat, se, ks, gis, _ = serve_run(D, ctx, graphs, queries, arrivals=arr, skip=skip,
+                                            host_out=host)
+        res[label] = {"offered_qps": round(lam, 1), "gteps": round(se / dt / 1e9, 2),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                      "per_graph": _per_graph(names, lat, gis)}
     used, budget = D.dawn_memory(ctx)
     res["hbm_used_gb"] = round(used / 1e9, 2)
     for h, _, _ in graphs:
         D.dawn_graph_release(ctx, h)
-    return res
+    check = [(graphs[queries[qi][0]][1], queries[qi][1][:keep], rows) for qi, rows in kept]
+    return res, check
+
+
+def served_parity(check):
+    """The kept served rows against the oracle's rows for their sources."""
+    import oracle
+    bad, rows = 0, 0
+    by_graph = {}
+    for g, srcs, got in check:
+        by_graph.setdefault(id(g), (g, [], []))
+        by_graph[id(g)][1].append(srcs)
+        by_graph[id(g)][2].append(got)
+    for g, srcs, got in by_graph.values():
+        s = np.concatenate(srcs)
+        want = oracle.mssp(g, s, threads=host_cores())
+        have = np.concatenate(got)
+        bad += int((have != want).any(axis=1).sum())
+        rows += int(s.size)
+    return {"rows_checked": rows, "rows_differing": bad, "bit_exact": bad == 0}
 
 
 def cpu_baseline(g, src):
@@ -520,9 +571,9 @@ def roofline_only(D, ctx, params_json):
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
     p = json.loads(params_json) if params_json else dict(PLAIN_KNOBS)
     D.dawn_set_params(ctx, h, **p)
-    lk_ms, lk_launches, levels = level_kernel_timing(D, ctx, h, src, out)
+    lk_ms, lk_launches, levels, lk_clk = level_kernel_timing(D, ctx, h, src, out)
     torch.cuda.synchronize()
-    roof = roofline_entry(g, out.cpu().numpy(), lk_ms, lk_launches, levels, p)
+    roof = roofline_entry(g, out.cpu().numpy(), lk_ms, lk_launches, levels, p, lk_clk)
     # counter calibration: 1 GiB written, then copied (read 1 GiB, write 1 GiB);
     # the source is 4x the 256 MiB memory-side cache, so the copy reads HBM
     a = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
@@ -606,10 +657,10 @@ def main():
     gteps_host = se_h / (time.perf_counter() - t0) / 1e9
 
     _log("[bench] level kernel per-launch timing")
-    lk_ms, lk_launches, lk_levels = level_kernel_timing(D, ctx, h, src, out)
+    lk_ms, lk_launches, lk_levels, lk_clk = level_kernel_timing(D, ctx, h, src, out)
     torch.cuda.synchronize()
     dist_rows = out.cpu().numpy()           # the rows of the per-launch timing pass
-    roofline = roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs)
+    roofline = roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs, lk_clk)
     bytes_full = D.dawn_graph_get_info(ctx, h)["device_bytes"]
     D.dawn_graph_release(ctx, h)
 
@@ -630,7 +681,7 @@ def main():
         extra["batched"] = batched_bench(D, ctx)
     if not args.no_extra:
         _log("[bench] uniform n = 4096, 8 sources")
-        extra["uniform4096"] = uniform_bench(D, ctx)
+        uniform_rows, extra["uniform4096"] = uniform_bench(D, ctx)
         _log("[bench] APSP over the largest WCC of R-MAT 14")
         extra["apsp"] = apsp_bench(D, ctx)
         _log("[bench] grid 2048^2 level-loop drivers")
@@ -639,7 +690,7 @@ def main():
         extra["small_components"] = small_component_bench(D, ctx)
     if not args.no_serve:
         _log("[bench] serving: R-MAT 16, R-MAT 20, grid 1024^2")
-        extra["served"] = serving_bench(D, ctx)
+        extra["served"], served_check = serving_bench(D, ctx)
 
     cpu = None
     if not args.no_cpu:
@@ -648,6 +699,14 @@ def main():
         extra["cpu_parallel"] = cpu_par
         # the oracle's rows against the rows of the timed pass itself, the
         # per-launch timing pass and the host-destination pass
+        if not args.no_extra:
+            import oracle
+            gu, su = gg.load_config("uniform4096")
+            extra["uniform4096"]["bit_exact"] = bool(np.array_equal(uniform_rows,
+                                                                    oracle.mssp(gu, su)))
+        if not args.no_serve:
+            _log("[bench] oracle on the kept served rows")
+            extra["served"]["parity"] = served_parity(served_check)
         extra["parity"] = {"timed_pass_bit_exact": bool(np.array_equal(ref, timed_rows)),
                            "timing_pass_bit_exact": bool(np.array_equal(ref, dist_rows)),
                            "host_output_bit_exact": bool(np.array_equal(ref, host_rows)),

@@ -87,6 +87,10 @@ typedef struct dawn_run_stats {
   int32_t *frontier_sizes;
   uint8_t *directions;
   int32_t frontier_cap;
+  /* dawn_sssp with timing 1 only (output): the level launches' own durations,
+   * each from its earliest workgroup start to its latest workgroup end by the
+   * GPU's wall clock, summed (kernel_ms adds each launch's dispatch gap) */
+  double kernel_clock_ms;
 } dawn_run_stats;
 
 /* Tuning knobs of one resident graph.  Every setting gives identical

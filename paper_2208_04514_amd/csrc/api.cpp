@@ -182,6 +182,8 @@ dawn_status dawn_create(int32_t device, uint64_t hbm_budget_bytes, dawn_ctx** ou
   ctx->num_cu = prop.multiProcessorCount;
   ctx->coop = prop.cooperativeLaunch;
   ctx->lds_per_block = prop.sharedMemPerBlock;
+  if (hipDeviceGetAttribute(&ctx->wall_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess)
+    ctx->wall_khz = 0;
   uint64_t budget = hbm_budget_bytes;
   if (budget == 0) {
     const char* env = getenv("DAWN_HBM_BUDGET");
@@ -349,7 +351,7 @@ dawn_status dawn_mssp(dawn_ctx* c, int32_t graph, const int32_t* sources, int32_
     if (stats) {
       stats->levels = stats->push_levels = stats->pull_levels = stats->launches = 0;
       stats->edges_examined = stats->source_edges = stats->reached = 0;
-      stats->kernel_ms = stats->total_ms = 0;
+      stats->kernel_ms = stats->total_ms = stats->kernel_clock_ms = 0;
     }
     return DAWN_OK;
   }

@@ -82,6 +82,8 @@ struct BatchArgs {
   int32_t nplanes;              // planes in use (levels < 2^nplanes)
   u64* touched[2];              // one bit per node with new bits at a level of that
                                 //   parity: the frontier of the next level
+  u64* vmap;                    // [n] bit w set when word w of the node's vis row may be
+                                //   nonzero (set by merges and live seeds; cleared with vis)
   u64* fmap[2];                 // [n] bit w set iff word w of the node's nxt row of
                                 //   that parity is nonzero (W <= 64)
   int32_t* cu[2];               // out-edge chunks of big-degree frontier nodes: node
@@ -118,6 +120,7 @@ struct BatchWs {
   size_t plane_reserve = 0;     // budget set aside for planes not yet allocated
   u64* touched[2] = {nullptr, nullptr};
   u64* fmap[2] = {nullptr, nullptr};
+  u64* vmap = nullptr;
   int32_t* cu[2] = {nullptr, nullptr};
   int32_t* ck[2] = {nullptr, nullptr};
   BatchCtrl* ctrl = nullptr;
@@ -157,7 +160,7 @@ dawn_status batch_launch_emit(Ctx* ctx, const BatchArgs& a, int nplanes_used, co
                               int mode, hipStream_t s);
 dawn_status batch_launch_zero(Ctx* ctx, u64* p, size_t count, hipStream_t s);
 // Clear up to kZeroMax arrays in one launch.
-constexpr int kZeroMax = 24;
+constexpr int kZeroMax = 26;
 struct ZeroList {
   u64* p[kZeroMax];
   size_t count[kZeroMax];

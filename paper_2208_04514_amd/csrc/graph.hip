@@ -300,6 +300,9 @@ static dawn_status finish_noin(Ctx* ctx, GraphRec* g, hipStream_t s) {
 // over the edges agree (two independent 64-bit mixes; a non-symmetric graph
 // passes with probability ~2^-128), and every node's out-degree equals its
 // in-degree.
+// SplitMix64's output function (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014): the golden-ratio increment,
+// then two xor-shift-multiply rounds.
 static u64 mix64(u64 x) {
   x += 0x9e3779b97f4a7c15ull;
   x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;

@@ -136,6 +136,8 @@ struct SsspArgs {
   int32_t lrec;
   int32_t lds_words;          // pull levels copy the visited bitmap (this many words,
                               //   = nw) into LDS; 0 = read it from global memory
+  unsigned long long* clk;    // timing mode: [0] earliest workgroup start, [1] latest
+                              //   workgroup end of this launch (GPU wall clock); null otherwise
 };
 
 // ----------------------------------------------------------- host objects --
@@ -167,6 +169,7 @@ struct SsspWs {
   int32_t* dist = nullptr;      // internal output for host-destination calls
   int32_t* level_nf = nullptr;
   uint8_t* level_dir = nullptr;
+  unsigned long long* clk = nullptr;   // timing mode: two wall-clock stamps per level launch
   int32_t lrec = 0;
   bool poisoned = false;        // a launch failed: never reuse these buffers
   size_t chunk_cap = 0;
@@ -233,6 +236,7 @@ struct Ctx {
   int device = 0;
   int num_cu = 0;
   int coop = 0;
+  int wall_khz = 0;                        // the GPU wall clock's rate (timing mode)
   size_t lds_per_block = 0;                // LDS bytes a workgroup may use
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};

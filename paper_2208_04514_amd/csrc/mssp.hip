@@ -190,19 +190,22 @@ __device__ __forceinline__ u64 group_read64(u64 x, int gb, int i) {
   return ((u64)hi << 32) | lo;
 }
 
-// OR into acc the previous level's new bits of in-edges [s, e) that lie in
-// `need`, stopping once every lane of the group has all of its word's needed
-// bits (group-uniform call; gb = the group's first lane).  Returns the number
-// of in-edges read.
+// OR into acc the visited bits of in-edges [s, e) that lie in `need`,
+// stopping once every lane of the group has all of its word's needed bits
+// (group-uniform call; gb = the group's first lane).  Returns the number of
+// in-edges read.
 //
-// Per lane r, an unvisited v has an in-neighbour visited in r iff it has one
-// whose bit r is new at level L - 1, and the two give the same bits of
-// `need`: the scan reads the previous level's new rows, and only the words
-// that the frontier word map marks nonzero.  The group reads EPL x P in-edges
-// and their map words at a time (lane i takes edges i, i + P, ...: narrow
-// groups take several, so a short row still keeps loads in flight), then
-// walks the edges whose source is on the frontier, each lane loading its own
-// word of those rows.
+// Per lane r, a node v not yet visited in r after level L - 1 lies at
+// distance >= L, and an in-neighbour visited in r lies at <= L - 1, so v is
+// at exactly L iff such an in-neighbour exists (the BOVM test of Algorithm 1
+// on the visited set, per bit).  The visited rows saturate `need` sooner than
+// the last level's new bits would (a hub reached early covers most lanes at
+// once; in-lists list high-degree sources first), so the scan stops after
+// fewer row reads.  Only the words that the visited word map marks nonzero
+// are loaded.  The group reads EPL x P in-edges and their map words at a time
+// (lane i takes edges i, i + P, ...: narrow groups take several, so a short
+// row still keeps loads in flight), then walks the edges whose source has
+// visited bits, each lane loading its own word of those rows.
 template <int P>
 __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, const u64* fm, int s,
                                          int e, u64 need, int w, int gb, u64 gm, u64& acc) {
@@ -326,8 +329,10 @@ __device__ __forceinline__ void pull_level(const BatchArgs& a, int L) {
   const int gb = P == 64 ? 0 : (lane & ~(P - 1));
   const u64 actw = wok ? a.act[w] : 0ull;
   const size_t W = (size_t)a.Ws;
-  const u64* front = a.nxt[(L - 1) & 1];
-  const u64* fm = a.fmap[(L - 1) & 1];
+  // the in-neighbours' visited rows (vis is only written by the merge, after
+  // this step) and the map of their possibly nonzero words
+  const u64* front = a.vis;
+  const u64* fm = a.vmap;
   u64* nxt = a.nxt[L & 1];
   u64* T = a.touched[L & 1];
   u64 edges = 0;
@@ -774,6 +779,9 @@ __device__ __forceinline__ void merge_level(const BatchArgs& a, int L) {
         if (okq[q] && w == 0) {
           fmap[v0 + jq[q]] = fm;
           mfw += (u64)__popcll(fm) * (u64)dq[q];
+          // words of the visited row that may now be nonzero
+          const u64 vm = a.vmap[v0 + jq[q]];
+          if (fm & ~vm) atom_or(&a.vmap[v0 + jq[q]], fm);
         }
       }
       // vis and the planes take their bits with atomic ORs that return
@@ -1015,10 +1023,15 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
           for (int d = 0; d < DMAX; ++d) pe[d] = pl[d][k];
         }
       if (clear && live) {
-        a.vis[base + e] = xe & ~em;
+        const u64 rem = xe & ~em;
+        a.vis[base + e] = rem;
 #pragma unroll
         for (int d = 0; d < DMAX; ++d)
           if (d < D) a.planes[d][base + e] = pe[d] & ~em;
+        // a word left empty by a partial emission leaves the visited map
+        // (a whole emission clears the node's map below)
+        if (!rem && xe && !(mode & kEmitMarkClean))
+          atomicAnd(&a.vmap[v], ~(1ull << (w0 + e)));
       }
       // lane b holds source (64 w + b)'s row pointer; each row is read from
       // that lane
@@ -1048,6 +1061,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
         }
       }
     }
+    // every lane of the batch was emitted: the node's visited map is clear too
+    if ((mode & kEmitMarkClean) && clear && w0 == 0 && live) a.vmap[v] = 0;
   }
 }
 
@@ -1192,6 +1207,7 @@ __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane,
       const u64 old = atom_or(&a.touched[L & 1][s >> 6], sbit);
       if (live) {
         atom_or(&a.vis[idx], bit);
+        atom_or(&a.vmap[s], 1ull << (l >> 6));
         deg = a.rp[s + 1] - a.rp[s];
         first = !(old & sbit);
       }
@@ -1284,6 +1300,7 @@ void batch_ws_destroy(BatchWs* w) {
   for (int i = 0; i < 2; ++i) {
     dev_free(ctx, w->touched[i], 0);
     dev_free(ctx, w->fmap[i], 0);
+    dev_free(ctx, i == 0 ? w->vmap : nullptr, 0);
     dev_free(ctx, w->cu[i], 0);
     dev_free(ctx, w->ck[i], 0);
   }
@@ -1334,6 +1351,7 @@ dawn_status batch_ws_create(Ctx* ctx, const GraphRec* g, int lanes, BatchWs** ou
     alloc((void**)&w->cu[i], chunk_cap * 4);
     alloc((void**)&w->ck[i], chunk_cap * 4);
   }
+  alloc((void**)&w->vmap, n * 8);
   alloc((void**)&w->ctrl, sizeof(BatchCtrl));
   alloc((void**)&w->act, 64 * 8);
   alloc((void**)&w->emask, 64 * 8);
@@ -1411,6 +1429,7 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W) {
   for (int i = 0; i < 2; ++i) {
     a.touched[i] = w->touched[i];
     a.fmap[i] = w->fmap[i];
+  a.vmap = w->vmap;
     a.cu[i] = w->cu[i];
     a.ck[i] = w->ck[i];
   }
@@ -1613,13 +1632,14 @@ static ZeroList prepare_list(const GraphRec* g, const BatchWs* w) {
   add(w->touched[1], nwords);
   add(w->fmap[0], (size_t)g->n);
   add(w->fmap[1], (size_t)g->n);
+  add(w->vmap, (size_t)g->n);
   for (int b = 0; b < w->nplanes; ++b) add(w->planes[b], nW);
   return z;
 }
 
 static dawn_status batch_launch_prepare(Ctx* ctx, const GraphRec* g, BatchWs* w, bool clear_status,
                                         hipStream_t s) {
-  static_assert(8 + kMaxPlanes <= kZeroMax, "prepare list too long");
+  static_assert(9 + kMaxPlanes <= kZeroMax, "prepare list too long");
   const ZeroList z = prepare_list(g, w);
   const size_t most = (size_t)g->n * (size_t)w->Wmax;
   const int gx = (int)std::max<size_t>(
@@ -1926,6 +1946,7 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
     stats->reached = (int64_t)tot.reached;
     stats->kernel_ms = tot.kernel_ms;
     stats->total_ms = (now_ns() - t0) / 1e6;
+    stats->kernel_clock_ms = 0.0;
   }
   return DAWN_OK;
 }

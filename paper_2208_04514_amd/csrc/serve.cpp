@@ -190,6 +190,7 @@ static dawn_status engine_create(Server* S, const std::shared_ptr<GraphRec>& g, 
   if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->touched[1], ((size_t)g->n + 63) / 64, w->stream);
   if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->fmap[0], (size_t)g->n, w->stream);
   if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->fmap[1], (size_t)g->n, w->stream);
+  if (z == DAWN_OK) z = batch_launch_zero(S->ctx, w->vmap, (size_t)g->n, w->stream);
   if (z == DAWN_OK) {
     he = hipMemcpyAsync(w->base, e->h_base, (size_t)e->capacity * 4, hipMemcpyHostToDevice, w->stream);
     if (he == hipSuccess)

@@ -755,7 +755,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0, int32_t* dist, i
 // Workgroup 0 stores the new state in st[p].  Once the loop is done, later
 // launches only carry the final state forward.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
+__device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   SsspArgs a = a0;
   a.dist = a0.ctrl->dist;
   __shared__ int32_t qbuf[BLOCK / kWave][kWaveBuf];
@@ -841,6 +841,25 @@ __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
   finish_level<BLOCK>(a, L, c, q);
 }
 
+// In timing mode (a.clk set) every workgroup stamps its start and end with
+// the GPU wall clock: the launch's own duration, without its dispatch gap.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
+  if (a0.clk && threadIdx.x == 0) atomicMin(&a0.clk[0], (unsigned long long)wall_clock64());
+  level_step<BLOCK>(a0, parity);
+  if (a0.clk) {
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&a0.clk[1], (unsigned long long)wall_clock64());
+  }
+}
+
+__global__ void clk_reset(unsigned long long* clk, int launches) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < launches; i += gridDim.x * blockDim.x) {
+    clk[2 * i] = ~0ull;
+    clk[2 * i + 1] = 0ull;
+  }
+}
+
 // ------------------------------------------------------------------ host --
 SsspWs::~SsspWs() {
   if (gexec) hipGraphExecDestroy(gexec);
@@ -855,6 +874,7 @@ SsspWs::~SsspWs() {
   dev_free(ctx, dist, 0);
   dev_free(ctx, level_nf, 0);
   dev_free(ctx, level_dir, 0);
+  dev_free(ctx, clk, 0);
   if (ctx) ctx->used -= bytes;
   if (h_ctrl) hipHostFree(h_ctrl);
   if (ev0) hipEventDestroy(ev0);
@@ -891,6 +911,7 @@ static dawn_status ws_create(Ctx* ctx, GraphRec* g, std::unique_ptr<SsspWs>* out
   if (s == DAWN_OK) s = alloc((void**)&w->dist, (size_t)n * 4);
   if (s == DAWN_OK) s = alloc((void**)&w->level_nf, (size_t)w->lrec * 4);
   if (s == DAWN_OK) s = alloc((void**)&w->level_dir, (size_t)w->lrec);
+  if (s == DAWN_OK) s = alloc((void**)&w->clk, (size_t)w->lrec * 16);
   // the destructor frees each buffer and returns `bytes` to the budget at once
   if (s != DAWN_OK) return s;
   DAWN_HIP(hipMemset(w->ctrl, 0, sizeof(SsspCtrl)));
@@ -976,19 +997,27 @@ static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStre
 template <int BLOCK>
 static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& a, int grid,
                               size_t shmem, int driver, int graph_levels, int32_t* d_dist,
-                              int source, int* launches, double* level_ms, int* final_parity) {
+                              int source, int* launches, double* level_ms, int* final_parity,
+                              double* clock_ms) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
   const long long max_launch = (long long)a.n + 2;
   if (driver == 2) {
     hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
                        source);
     DAWN_HIP(hipGetLastError());
+    if (level_ms) {
+      hipLaunchKernelGGL(clk_reset, dim3(std::max(1, (w->lrec + 255) / 256)), dim3(256), 0,
+                         w->stream, w->clk, w->lrec);
+      DAWN_HIP(hipGetLastError());
+    }
     *launches = 1;
     int level_launches = 0;
     for (long long it = 0; it <= max_launch; ++it) {
       const int parity = (int)(it & 1);
+      SsspArgs al = a;
+      if (level_ms && it < w->lrec) al.clk = w->clk + 2 * it;
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
-      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, a, parity);
+      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, al, parity);
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
       DAWN_HIP(hipGetLastError());
       *launches += 1;
@@ -1003,7 +1032,16 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       }
       if (w->h_ctrl->st[parity].done) {
         *final_parity = parity;
-        if (level_ms) *launches = level_launches;
+        if (level_ms) {
+          *launches = level_launches;
+          const int nl = std::min(level_launches, w->lrec);
+          std::vector<unsigned long long> stamps((size_t)nl * 2);
+          DAWN_HIP(hipMemcpy(stamps.data(), w->clk, stamps.size() * 8, hipMemcpyDeviceToHost));
+          double ticks = 0.0;
+          for (int i = 0; i < nl; ++i)
+            if (stamps[2 * i + 1] > stamps[2 * i]) ticks += (double)(stamps[2 * i + 1] - stamps[2 * i]);
+          if (clock_ms && ctx->wall_khz > 0) *clock_ms = ticks / (double)ctx->wall_khz;
+        }
         return DAWN_OK;
       }
     }
@@ -1094,7 +1132,7 @@ static bool small_component(const GraphRec* g, const dawn_params& p, int32_t sou
 template <int BLOCK>
 static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_params& p,
                                  SsspArgs& a, int32_t source, int32_t* d_dist, int* launches,
-                                 double* level_ms, int* final_parity) {
+                                 double* level_ms, int* final_parity, double* clock_ms) {
   if (small_component(g, p, source)) {
     const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
     hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
@@ -1127,7 +1165,7 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
   int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
   return run_levels<BLOCK>(ctx, g, w, a, per_cu * ctx->num_cu, shmem, p.driver,
                            std::max(p.graph_levels, 1), d_dist, source, launches, level_ms,
-                           final_parity);
+                           final_parity, clock_ms);
 }
 
 dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source, int32_t* dist,
@@ -1159,7 +1197,7 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   int launches = 0;
   const bool small = small_component(g, p, source);
   const bool level_timing = p.timing == 1 && p.driver == 2 && !small;
-  double level_ms = 0.0;
+  double level_ms = 0.0, clock_ms = 0.0;
   double* lm = level_timing ? &level_ms : nullptr;
   int fp = 1;
   const uint64_t t_setup = now_ns();
@@ -1174,9 +1212,9 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
-    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp); break;
-    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp); break;
-    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp); break;
+    case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
+    case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
+    default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
   }
   if (!level_timing) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
@@ -1226,6 +1264,7 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     stats->source_edges = (int64_t)rs.source_edges;
     stats->reached = (int64_t)rs.reached;
     stats->kernel_ms = ms;
+    stats->kernel_clock_ms = level_timing ? clock_ms : 0.0;
     const int32_t nl = std::min(cap, stats->levels);
     if (cap > 0 && stats->frontier_sizes)
       for (int i = 0; i < nl; ++i) stats->frontier_sizes[i] = lnf[i];

@@ -58,10 +58,13 @@ class RunStats(ctypes.Structure):
         ("reached", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
         ("total_ms", ctypes.c_double), ("frontier_sizes", _i32p),
         ("directions", _u8p), ("frontier_cap", ctypes.c_int32),
+        ("kernel_clock_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_[:9]}
+        d = {f: getattr(self, f) for f, _ in self._fields_[:9]}
+        d["kernel_clock_ms"] = self.kernel_clock_ms
+        return d
 
 
 class Params(ctypes.Structure):

@@ -36,7 +36,9 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "dawn.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(dawn_run_stats), offsetof(dawn_run_stats, frontier_cap),
+  printf("%zu %zu %zu\n", sizeof(dawn_run_stats), offsetof(dawn_run_stats, frontier_cap),
+         offsetof(dawn_run_stats, kernel_clock_ms));
+  printf("%zu %zu\n",
          sizeof(dawn_params), offsetof(dawn_params, timing));
   printf("%zu %zu %zu %zu\n", sizeof(dawn_graph_info), offsetof(dawn_graph_info, device_bytes),
          sizeof(dawn_query_stats), offsetof(dawn_query_stats, batch_peak));
@@ -52,7 +54,7 @@ int main(void) {
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     got = list(map(int, out))
     want = [ctypes.sizeof(D.RunStats), D.RunStats.frontier_cap.offset,
-            ctypes.sizeof(D.Params), D.Params.timing.offset,
+            D.RunStats.kernel_clock_ms.offset, ctypes.sizeof(D.Params), D.Params.timing.offset,
             ctypes.sizeof(D.GraphInfo), D.GraphInfo.device_bytes.offset,
             ctypes.sizeof(D.QueryStats), D.QueryStats.batch_peak.offset]
     assert got == want
