@@ -187,6 +187,22 @@ dawn_status dawn_set_params(dawn_ctx *ctx, int32_t graph, const dawn_params *in)
 dawn_status dawn_sssp(dawn_ctx *ctx, int32_t graph, int32_t source, int32_t *dist,
                       uint32_t flags, dawn_run_stats *stats);
 
+/* Single-source run that allocates nothing, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same distances as dawn_sssp.  Every buffer of the
+ * traversal lives in a static device array of 64 MiB that libdawn holds on
+ * each GPU it runs on until the process ends; a graph whose traversal needs
+ * more (about 128 n + m / 2 + 64 Ki bytes: n up to ~480,000 on sparse graphs)
+ * is refused with INVALID_ARG.  d_dist: n int32 of device memory on the
+ * context's GPU.  Work is queued on `hip_stream` (NULL: the null stream) and
+ * the call returns when the distances are written (it reads the level state
+ * back into host stack memory once per batch of level launches).  Calls that
+ * overlap on one GPU share the array and race: the caller serialises them.
+ * stats (may be NULL): as dawn_sssp, except kernel_ms = 0 (no events).
+ * Errors: INVALID_ARG, NOT_FOUND, DEVICE. */
+dawn_status dawn_sssp_noalloc(dawn_ctx *ctx, int32_t graph, int32_t source, int32_t *d_dist,
+                              void *hip_stream, dawn_run_stats *stats);
+
 /* Multi-source: row r of dist (k x n int32, row-major) holds the distances
  * from sources[r] (host array of k ids; repeats allowed and give equal rows).
  * Up to `batch_lanes` sources share one bitmask batch: one bit per source in

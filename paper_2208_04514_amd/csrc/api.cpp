@@ -175,6 +175,7 @@ dawn_status dawn_create(int32_t device, uint64_t hbm_budget_bytes, dawn_ctx** ou
   DAWN_HIP(hipSetDevice(device));
   hipDeviceProp_t prop;
   DAWN_HIP(hipGetDeviceProperties(&prop, device));
+  DAWN_TRY(scratch_init(device));
   size_t freeb = 0, totalb = 0;
   DAWN_HIP(hipMemGetInfo(&freeb, &totalb));
   Ctx* ctx = new Ctx();
@@ -336,6 +337,26 @@ dawn_status dawn_sssp(dawn_ctx* c, int32_t graph, int32_t source, int32_t* dist,
     p = g->params;
   }
   return sssp_run(ctx, g.get(), p, source, dist, (flags & DAWN_DEVICE_OUT) != 0, stats);
+}
+
+dawn_status dawn_sssp_noalloc(dawn_ctx* c, int32_t graph, int32_t source, int32_t* d_dist,
+                              void* hip_stream, dawn_run_stats* stats) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!d_dist) return fail(DAWN_E_INVALID_ARG, "null dist");
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  if (source < 0 || source >= g->n)
+    return fail(DAWN_E_INVALID_ARG, "source %d outside [0, %d)", source, g->n);
+  DAWN_HIP(hipSetDevice(ctx->device));
+  dawn_params p;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    p = g->params;
+  }
+  return sssp_run_noalloc(ctx, g.get(), p, source, d_dist,
+                          reinterpret_cast<hipStream_t>(hip_stream), stats);
 }
 
 dawn_status dawn_mssp(dawn_ctx* c, int32_t graph, const int32_t* sources, int32_t k, int32_t* dist,

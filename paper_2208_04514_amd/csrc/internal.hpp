@@ -262,6 +262,11 @@ dawn_status graph_wcc(Ctx* ctx, GraphRec* g, hipStream_t stream);
 // sssp.hip
 dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source,
                      int32_t* dist, bool device_out, dawn_run_stats* stats);
+// The no-allocation variant: buffers from the file-scope scratch array of
+// sssp.hip, whose per-device address scratch_init (device current) looks up.
+dawn_status scratch_init(int device);
+dawn_status sssp_run_noalloc(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source,
+                             int32_t* d_dist, hipStream_t s, dawn_run_stats* stats);
 
 // mssp.hip
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources,

@@ -1281,4 +1281,184 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   return DAWN_OK;
 }
 
+// ------------------------------------------------ no-allocation variant --
+// Callers that cannot allocate device memory (code under stream capture,
+// tight serving loops, harnesses that forbid it) run a single source with
+// every buffer of the traversal carved out of this file-scope array: one per
+// GPU, held until the process ends.  Calls that overlap on one GPU share it
+// and race.  The host never uses the array's name as an address: each
+// device's address comes from hipGetSymbolAddress at set-up.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[kScratchDevices] = {};
+
+// With `device` current: look up this GPU's copy of the array (once).
+dawn_status scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices)
+    return fail(DAWN_E_INVALID_ARG, "device %d beyond the scratch table", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DAWN_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(DAWN_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch_ptr[device] = (unsigned char*)ptr;
+  return DAWN_OK;
+}
+
+// Bytes of scratch a graph's traversal takes, and its layout.
+struct ScratchLayout {
+  size_t ctrl, vis0, vis1, qs0, qs1, cu0, cu1, ck0, ck1, lnf, ldir, total;
+};
+
+static ScratchLayout scratch_layout(const GraphRec* g) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t n = (size_t)g->n, nw = (n + 63) / 64;
+  const size_t chunk_cap = (size_t)(g->m / 32) + 64;
+  const size_t lrec = std::min<size_t>(n + 1, 1 << 16);
+  ScratchLayout L;
+  size_t o = 0;
+  L.ctrl = o;  o += up(sizeof(SsspCtrl));
+  L.vis0 = o;  o += up(nw * 8 + 256);
+  L.vis1 = o;  o += up(nw * 8 + 256);
+  L.qs0 = o;   o += up((size_t)kStripes * n * 4 + 256);
+  L.qs1 = o;   o += up((size_t)kStripes * n * 4 + 256);
+  L.cu0 = o;   o += up(chunk_cap * 4);
+  L.cu1 = o;   o += up(chunk_cap * 4);
+  L.ck0 = o;   o += up(chunk_cap * 4);
+  L.ck1 = o;   o += up(chunk_cap * 4);
+  L.lnf = o;   o += up(lrec * 4);
+  L.ldir = o;  o += up(lrec);
+  L.total = o;
+  return L;
+}
+
+template <int BLOCK>
+static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, SsspArgs& a,
+                                  int32_t source, int32_t* d_dist, hipStream_t s,
+                                  LevelState* fin, int* launches) {
+  const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
+  hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, s, a, d_dist, source);
+  DAWN_HIP(hipGetLastError());
+  *launches = 1;
+  if (small_component(g, p, source)) {
+    hipLaunchKernelGGL(sssp_component<BLOCK>, dim3(1), dim3(BLOCK), 0, s, a);
+    DAWN_HIP(hipGetLastError());
+    *launches = 2;
+    DAWN_HIP(hipMemcpyAsync(fin, &a.ctrl->st[1], sizeof(LevelState), hipMemcpyDeviceToHost, s));
+    DAWN_HIP(hipStreamSynchronize(s));
+    return DAWN_OK;
+  }
+  hipFuncAttributes fa;
+  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
+  const size_t bitmap = (size_t)a.nw * 8;
+  size_t shmem = 0;
+  if (fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
+    shmem = bitmap;
+    a.lds_words = a.nw;
+    DAWN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sssp_level<BLOCK>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  }
+  int occ = 0;
+  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, shmem));
+  const int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1))
+                                         : std::max(occ, 1);
+  const int grid = per_cu * ctx->num_cu;
+  // level launches queued per host check, as the direct-launch driver does
+  const int hint = g->launch_hint.load(std::memory_order_relaxed);
+  const int gl = std::max(p.graph_levels, 1) + (std::max(p.graph_levels, 1) & 1);
+  int batch = hint > 0 ? std::min(hint + 1, gl * 4) : gl;
+  batch += batch & 1;
+  for (long long queued = 0; queued <= (long long)a.n + 2;) {
+    for (int i = 0; i < batch; ++i)
+      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, s, a, i & 1);
+    DAWN_HIP(hipGetLastError());
+    *launches += batch;
+    queued += batch;
+    // pageable host memory: the copy returns once the stream has reached it
+    DAWN_HIP(hipMemcpyAsync(fin, &a.ctrl->st[1], sizeof(LevelState), hipMemcpyDeviceToHost, s));
+    DAWN_HIP(hipStreamSynchronize(s));
+    if (fin->done) {
+      g->launch_hint.store(std::max(fin->last_nonempty + 2, hint - 1), std::memory_order_relaxed);
+      return DAWN_OK;
+    }
+    batch = gl;
+  }
+  return fail(DAWN_E_DEVICE, "level loop did not terminate");
+}
+
+dawn_status sssp_run_noalloc(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source,
+                             int32_t* d_dist, hipStream_t s, dawn_run_stats* stats) {
+  const uint64_t t0 = now_ns();
+  const ScratchLayout L = scratch_layout(g);
+  if (L.total > kScratchBytes)
+    return fail(DAWN_E_INVALID_ARG, "graph needs %zu bytes of traversal buffers; the "
+                "no-allocation entry point holds %zu (n = %d, m = %lld)", L.total, kScratchBytes,
+                g->n, (long long)g->m);
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = ctx->device < kScratchDevices ? g_scratch_ptr[ctx->device] : nullptr;
+  }
+  if (!base) return fail(DAWN_E_DEVICE, "scratch of device %d not set up", ctx->device);
+  SsspArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = g->n;
+  a.nw = (g->n + 63) / 64;
+  a.m = g->m;
+  a.rp = g->rp;
+  a.col = g->col;
+  a.ip = g->ip;
+  a.isrc = g->isrc;
+  a.noin = g->noin;
+  a.ctrl = (SsspCtrl*)(base + L.ctrl);
+  a.vis0 = (u64*)(base + L.vis0);
+  a.vis1 = (u64*)(base + L.vis1);
+  a.qs0 = (int32_t*)(base + L.qs0);
+  a.qs1 = (int32_t*)(base + L.qs1);
+  a.cu0 = (int32_t*)(base + L.cu0);
+  a.cu1 = (int32_t*)(base + L.cu1);
+  a.ck0 = (int32_t*)(base + L.ck0);
+  a.ck1 = (int32_t*)(base + L.ck1);
+  a.level_nf = (int32_t*)(base + L.lnf);
+  a.level_dir = (uint8_t*)(base + L.ldir);
+  a.lrec = (int32_t)std::min<size_t>((size_t)g->n + 1, 1 << 16);
+  a.mode = p.direction;
+  a.alpha = p.alpha;
+  a.beta = p.beta;
+  a.big_degree = std::max(p.big_degree, 64);
+  a.lane_edges = std::max(p.pull_lane_edges, 1);
+  LevelState fin;
+  memset(&fin, 0, sizeof(fin));
+  int launches = 0;
+  dawn_status st;
+  switch (p.block) {
+    case 512: st = noalloc_levels<512>(ctx, g, p, a, source, d_dist, s, &fin, &launches); break;
+    case 1024: st = noalloc_levels<1024>(ctx, g, p, a, source, d_dist, s, &fin, &launches); break;
+    default: st = noalloc_levels<256>(ctx, g, p, a, source, d_dist, s, &fin, &launches); break;
+  }
+  if (st != DAWN_OK) {
+    hipStreamSynchronize(s);
+    return st;
+  }
+  if (fin.done == 2) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
+  if (fin.done != 1) return fail(DAWN_E_DEVICE, "level loop ended without finishing");
+  if (stats) {
+    stats->levels = fin.last_nonempty + 1;
+    stats->push_levels = fin.push_levels;
+    stats->pull_levels = fin.pull_levels;
+    stats->launches = launches;
+    stats->edges_examined = (int64_t)fin.edges_total;
+    stats->source_edges = (int64_t)fin.source_edges;
+    stats->reached = (int64_t)fin.reached;
+    stats->kernel_ms = 0.0;
+    stats->total_ms = (now_ns() - t0) / 1e6;
+    stats->kernel_clock_ms = 0.0;
+  }
+  return DAWN_OK;
+}
+
 }  // namespace dawn

@@ -36,7 +36,7 @@ EXPORTED = (
     "dawn_create", "dawn_destroy", "dawn_last_error", "dawn_memory", "dawn_graph_upload",
     "dawn_graph_release", "dawn_graph_get_info", "dawn_get_params", "dawn_set_params",
     "dawn_sssp", "dawn_mssp", "dawn_apsp_wcc", "dawn_autotune", "dawn_serve_submit",
-    "dawn_serve_poll", "dawn_serve_wait", "dawn_mssp_device",
+    "dawn_serve_poll", "dawn_serve_wait", "dawn_mssp_device", "dawn_sssp_noalloc",
 )
 
 
@@ -137,6 +137,7 @@ def load(path: str | None = None):
         "dawn_serve_poll": [V, U64, ctypes.POINTER(QueryStats)],
         "dawn_serve_wait": [V, U64, I32, ctypes.POINTER(QueryStats)],
         "dawn_mssp_device": [V, I32, V, I32, V, V, V],
+        "dawn_sssp_noalloc": [V, I32, I32, V, V, ctypes.POINTER(RunStats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -315,6 +316,23 @@ def dawn_sssp(ctx, graph: int, source: int, out=None, frontier_cap: int = 0):
         d["frontier_sizes"] = fs[:L].tolist()
         d["directions"] = dr[:L].tolist()
     return out, d
+
+
+def dawn_sssp_noalloc(ctx, graph: int, source: int, out, stream=None):
+    """Distances from `source` into the int32 CUDA tensor `out` [n], with no
+    device allocation by the library (its static scratch array); the work is
+    queued on `stream` (default: torch's current stream) and finished on
+    return.  Returns ``(out, stats)``."""
+    import torch
+    ptr, _flags, _keep = check_out(out, (_graph_n(ctx, graph),), _CTX_DEVICE.get(_ctx_key(ctx)))
+    if not _is_torch_cuda(out):
+        raise ValueError("dawn_sssp_noalloc writes device memory: pass an int32 CUDA tensor")
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    st = RunStats()
+    _check(load().dawn_sssp_noalloc(ctx, graph, int(source), ptr,
+                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(st)))
+    return out, st.as_dict()
 
 
 def dawn_mssp(ctx, graph: int, sources, out=None):
