@@ -34,10 +34,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Knobs of the plain level loop on R-MAT 20, as chosen by dawn_autotune on
-# eight other sources of the same graph (bench.py --autotune re-tunes live).
-PLAIN_KNOBS = {"driver": 3, "graph_levels": 16, "big_degree": 128, "alpha": 60.0, "beta": 24.0,
-               "block": 1024, "blocks_per_cu": 0, "pull_lane_edges": 32}
+# The knobs of the plain level loop that the bench takes from the tuning
+# cache (paper_2208_04514_amd/tuned_params.json, written by dawn_autotune on
+# eight other sources of the same graph; --autotune searches again live).
+PLAIN_KNOB_NAMES = ("driver", "graph_levels", "big_degree", "alpha", "beta", "block",
+                    "blocks_per_cu", "pull_lane_edges")
+BATCH_KNOB_NAMES = ("batch_alpha", "batch_big_degree", "batch_wide_scan", "batch_sparse_words")
 
 # Sources that define the level-step kernel: the HBM counter record under
 # profiles/ holds their digest and is used only while it matches.
@@ -195,11 +197,12 @@ def component_edge_sums(g):
 
 def batched_only(D, ctx):
     """R-MAT 18, the 4096 bench sources in one dawn_mssp call, three times with
-    the library's default knobs: the batched kernels alone, for a profiler."""
+    the cached tuned knobs: the batched kernels alone, for a profiler."""
     import torch
     import graphgen as gg
     g, src = gg.load_config("rmat18")
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    cached_knobs(D, ctx, h, g, 4096, PLAIN_KNOB_NAMES + BATCH_KNOB_NAMES, 3, 9002, 4096, False, None)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
     runs = []
     for _ in range(3):
@@ -212,7 +215,26 @@ def batched_only(D, ctx):
                                        "pull_levels": st["pull_levels"]}}), flush=True)
 
 
-def batched_bench(D, ctx):
+def cached_knobs(D, ctx, h, g, width, names, what, seed, k_tune, live, tune_file):
+    """Knob settings for graph h from the tuning cache, or from a live
+    dawn_autotune run (on k_tune other sources of the graph) that is then
+    recorded.  Returns (knobs, where they came from, seconds spent tuning)."""
+    import graphgen as gg
+    from paper_2208_04514_amd import tune_cache as T
+    arch, sig = T.device_arch(0), T.graph_signature(g.row_ptr, g.col)
+    cached = None if live else T.lookup(arch, sig, width, tune_file)
+    if cached is not None and all(n in cached for n in names):
+        knobs = {n: cached[n] for n in names}
+        D.dawn_set_params(ctx, h, **knobs)
+        return knobs, f"tuning cache {os.path.basename(tune_file or T.DEFAULT_PATH)}", 0.0
+    t0 = time.perf_counter()
+    tuned = D.dawn_autotune(ctx, h, gg.sample_sources(g.meta["wcc_nodes"], k_tune, seed), what=what)
+    tune_s = time.perf_counter() - t0
+    T.store(arch, sig, width, tuned, tune_file, note=f"{g.name}: dawn_autotune what={what}")
+    return {n: tuned[n] for n in names}, "autotune (live)", tune_s
+
+
+def batched_bench(D, ctx, live=False, tune_file=None):
     """R-MAT 18, 4096 sources in one dawn_mssp launch, and the same sources
     one at a time through dawn_sssp."""
     import torch
@@ -220,9 +242,9 @@ def batched_bench(D, ctx):
     g, src = gg.load_config("rmat18")
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
-    t0 = time.perf_counter()
-    tuned = D.dawn_autotune(ctx, h, gg.sample_sources(g.meta["wcc_nodes"], 4096, 9002), what=3)
-    tune_s = time.perf_counter() - t0
+    tuned, tuned_from, tune_s = cached_knobs(D, ctx, h, g, 4096,
+                                             PLAIN_KNOB_NAMES + BATCH_KNOB_NAMES, 3, 9002, 4096,
+                                             live, tune_file)
     D.dawn_mssp(ctx, h, src, out=out)
     torch.cuda.synchronize()
     times, st_b = [], None
@@ -252,8 +274,7 @@ def batched_bench(D, ctx):
         "plain_same_sources_gteps": round(sep / tp / 1e9, 2),
         "plain_same_sources_ms": round(tp * 1e3, 1),
         "speedup_vs_plain": round(tp / tb, 2),
-        "tuned": {k: tuned[k] for k in ("driver", "big_degree", "alpha", "beta", "block",
-                                        "batch_alpha")},
+        "tuned": tuned, "tuned_from": tuned_from,
         "autotune_s": round(tune_s, 2),
     }
 
@@ -436,12 +457,15 @@ def _per_graph(names, lat, gis):
             for i, name in enumerate(names) if (gis == i).any()}
 
 
-def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2):
+def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2, nq_host=300):
     """Three resident graphs, queries of 1..1024 sources (log-uniform) on a
     uniformly chosen graph, sources from its largest WCC: first saturated (a
     window of queries in flight) to find the capacity, then Poisson arrivals
     at 0.5 and 0.9 of that query rate, and at 0.5 with host-destination rows.
-    Each run submits `nq` queries and discards the first `skip` as warm-up.
+    Each run submits `nq` queries and discards the first `skip` as warm-up
+    (the host-destination run: the first `nq_host` of them, discarding a
+    tenth; its rows, ~0.6 GB per query on the 2^20-node graphs, cross PCIe
+    into fresh host pages).
     The first `keep` rows of every query of the saturated run are returned
     for the oracle check."""
     import graphgen as gg
@@ -462,6 +486,7 @@ def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2):
     serve_run(D, ctx, graphs, queries[:20])
     dt, lat, se, ks, gis, kept = serve_run(D, ctx, graphs, queries, skip=skip, keep_rows=keep)
     cap_qps = len(queries) / dt
+    _log(f"[bench]   saturated: {len(queries)} queries in {dt:.1f} s")
     res = {"graphs": list(names), "queries": nq, "warmup_discarded": skip,
            "mean_k": round(float(np.mean([q[1].size for q in queries])), 1),
            "saturated": {"qps": round(cap_qps, 1), "sources_per_s": round(ks / dt, 1),
@@ -472,10 +497,13 @@ def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2):
     for label, frac, host in (("load_0.5", 0.5, False), ("load_0.9", 0.9, False),
                               ("load_0.5_host_output", 0.5, True)):
         lam = frac * cap_qps
-        arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
-        dt, lat, se, ks, gis, _ = serve_run(D, ctx, graphs, queries, arrivals=arr, skip=skip,
-                                            host_out=host)
-        res[label] = {"offered_qps": round(lam, 1), "gteps": round(se / dt / 1e9, 2),
+        nrun = nq_host if host else nq
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nrun))
+        dt, lat, se, ks, gis, _ = serve_run(D, ctx, graphs, queries[:nrun], arrivals=arr,
+                                            skip=nrun // 20 if host else skip, host_out=host)
+        _log(f"[bench]   {label}: {nrun} queries in {dt:.1f} s")
+        res[label] = {"queries": nrun, "offered_qps": round(lam, 1),
+                      "gteps": round(se / dt / 1e9, 2),
                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
                       "per_graph": _per_graph(names, lat, gis)}
@@ -569,8 +597,11 @@ def roofline_only(D, ctx, params_json):
     g, src = gg.load_config("rmat20")
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
-    p = json.loads(params_json) if params_json else dict(PLAIN_KNOBS)
-    D.dawn_set_params(ctx, h, **p)
+    if params_json:
+        p = json.loads(params_json)
+        D.dawn_set_params(ctx, h, **p)
+    else:
+        p, _, _ = cached_knobs(D, ctx, h, g, 1, PLAIN_KNOB_NAMES, 1, 9001, 8, False, None)
     lk_ms, lk_launches, levels, lk_clk = level_kernel_timing(D, ctx, h, src, out)
     torch.cuda.synchronize()
     roof = roofline_entry(g, out.cpu().numpy(), lk_ms, lk_launches, levels, p, lk_clk)
@@ -596,7 +627,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--autotune", action="store_true",
-                    help="re-tune the plain knobs live instead of the committed ones")
+                    help="search the knobs live (and record them) instead of loading the cache")
+    ap.add_argument("--tune-file", default=None,
+                    help="tuning cache to read and write (default: the package's tuned_params.json)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the level-kernel timing pass (for rocprofv3)")
     ap.add_argument("--params", default="", help="JSON knobs for --roofline-only")
@@ -632,14 +665,8 @@ def main():
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
 
-    knobs, tune_s = dict(PLAIN_KNOBS), 0.0
-    if args.autotune:
-        _log("[bench] autotune")
-        t0 = time.perf_counter()
-        tuned = D.dawn_autotune(ctx, h, gg.sample_sources(g.meta["wcc_nodes"], 8, 9001), what=1)
-        tune_s = time.perf_counter() - t0
-        knobs = {k: tuned[k] for k in PLAIN_KNOBS}
-    D.dawn_set_params(ctx, h, **knobs)
+    knobs, knobs_from, tune_s = cached_knobs(D, ctx, h, g, 1, PLAIN_KNOB_NAMES, 1, 9001, 8,
+                                             args.autotune, args.tune_file)
 
     _log("[bench] plain SSSP timed region")
     se, dt, ks, levels, calls = run_plain(D, ctx, h, src, out, args.steps, args.warmup)
@@ -678,7 +705,7 @@ def main():
 
     if not args.no_batched:
         _log("[bench] batched R-MAT 18, 4096 sources")
-        extra["batched"] = batched_bench(D, ctx)
+        extra["batched"] = batched_bench(D, ctx, args.autotune, args.tune_file)
     if not args.no_extra:
         _log("[bench] uniform n = 4096, 8 sources")
         uniform_rows, extra["uniform4096"] = uniform_bench(D, ctx)
@@ -727,7 +754,7 @@ def main():
                    "ms_per_source_p50": round(float(np.percentile(calls, 50)), 4),
                    "ms_per_source_p99": round(float(np.percentile(calls, 99)), 4),
                    "levels": int(np.max(levels)), "knobs": knobs,
-                   "knobs_from": "autotune (live)" if args.autotune else "committed",
+                   "knobs_from": knobs_from,
                    "autotune_s": round(tune_s, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -117,6 +117,13 @@ typedef struct dawn_params {
   int32_t timing;             /* 1: kernel_ms/launches of dawn_sssp cover only the level-step
                                  kernels, each bracketed by HIP events (driver 2 only);
                                  2 (default): every kernel of the call */
+  int32_t batch_big_degree;   /* batched push: out-degree from which a frontier node's
+                                 out-list is cut into 64-edge chunks spread over the grid
+                                 (>= 64; default 64) */
+  int32_t batch_wide_scan;    /* batched pull with rows of <= 8 words: in-list length above
+                                 which the whole wave scans the list (1..512; default 48) */
+  int32_t batch_sparse_words; /* batched push: a frontier node with at most this many nonzero
+                                 64-lane words goes one edge per lane (1..4; default 4) */
 } dawn_params;
 
 typedef struct dawn_graph_info {

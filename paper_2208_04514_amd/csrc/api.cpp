@@ -97,6 +97,9 @@ dawn_params default_params(const GraphRec& g) {
   p.batch_alpha = 4.0f;
   p.batch_lanes = 4096;
   p.timing = 2;
+  p.batch_big_degree = 64;
+  p.batch_wide_scan = 48;
+  p.batch_sparse_words = 4;
   (void)g;
   return p;
 }
@@ -118,6 +121,11 @@ dawn_status check_params(const dawn_params& p) {
   if (p.timing < 1 || p.timing > 2) return fail(DAWN_E_INVALID_ARG, "timing must be 1 or 2");
   if (p.timing == 1 && p.driver != 2)
     return fail(DAWN_E_INVALID_ARG, "timing 1 needs driver 2 (one launch per level)");
+  if (p.batch_big_degree < 64) return fail(DAWN_E_INVALID_ARG, "batch_big_degree must be >= 64");
+  if (p.batch_wide_scan < 1 || p.batch_wide_scan > 512)
+    return fail(DAWN_E_INVALID_ARG, "batch_wide_scan must be in [1, 512]");
+  if (p.batch_sparse_words < 1 || p.batch_sparse_words > 4)
+    return fail(DAWN_E_INVALID_ARG, "batch_sparse_words must be in [1, 4]");
   return DAWN_OK;
 }
 
@@ -310,7 +318,7 @@ dawn_status dawn_set_params(dawn_ctx* c, int32_t graph, const dawn_params* in) {
   if (p.f == 0) p.f = d.f
   KEEP(driver); KEEP(direction); KEEP(block); KEEP(big_degree); KEEP(pull_lane_edges);
   KEEP(alpha); KEEP(beta); KEEP(graph_levels); KEEP(batch_alpha); KEEP(batch_lanes);
-  KEEP(timing);
+  KEEP(timing); KEEP(batch_big_degree); KEEP(batch_wide_scan); KEEP(batch_sparse_words);
 #undef KEEP
   DAWN_TRY(check_params(p));
   std::lock_guard<std::mutex> lk(g->mu);

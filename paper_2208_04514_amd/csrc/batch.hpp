@@ -96,6 +96,9 @@ struct BatchArgs {
   int32_t emit_k;               // with a null emission mask: lanes < emit_k are emitted
   const int32_t* base;          // [lanes] level at which each source joined (null: all 0)
   int32_t gated;                // expansion and merge obey ctrl->run (device-driven loop)
+  int32_t big_b;                // push: out-degree from which a node's edges go by chunks
+  int32_t wide_scan;            // narrow rows: in-list length scanned by the whole wave
+  int32_t sparse_words;         // push one edge per lane for nodes with <= this many words
   unsigned* flags;              // [0] the workspace may hold bits (set by the seed, cleared by
                                 //   a complete emission), [1] run status: 0 ok, 1 invalid
                                 //   source, 2 watchdog (device-ordered calls report it)
@@ -150,6 +153,8 @@ dawn_status batch_ensure_planes(BatchWs* w, int need, int W);
 // 0 = Ws).
 BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W = 0);
 BatchLevelSum batch_level_sum(const BatchLevel& l);
+// The batched knobs of dawn_params into the kernels' arguments.
+void batch_knobs(BatchArgs& a, const dawn_params& p);
 dawn_status batch_launch_expand(Ctx* ctx, const BatchArgs& a, bool pull, int L, hipStream_t s);
 dawn_status batch_launch_merge(Ctx* ctx, const BatchArgs& a, int L, hipStream_t s);
 // mode: kEmitClear | kEmitFromRun | kEmitMarkClean (mssp.hip)

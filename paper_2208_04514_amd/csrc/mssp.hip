@@ -43,7 +43,9 @@
 namespace dawn {
 
 constexpr int kBatchBlock = 256;
-constexpr int kBigB = 64;         // out-degree from which a frontier node's edges are chunked
+constexpr int kBigB = 64;         // least out-degree from which a frontier node's edges may be
+                                  //   chunked (the chunk lists are sized for it); the knob
+                                  //   batch_big_degree (a.big_b) picks the threshold
 constexpr int kChunkB = 64;       // out-edges per chunk of a big-degree node
 
 // group of P lanes per node: lane w of the group handles word w
@@ -269,7 +271,7 @@ __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, c
 
 // Narrow batched rows (<= 8 words): an in-list longer than this is scanned
 // by the whole wave, 64 edges per step.
-constexpr int kWideScan = 48;
+// (the knob batch_wide_scan, a.wide_scan; 48 by default)
 
 // Narrow rows (W <= P <= 8 words): the whole wave scans in-edges [s, e) of
 // one node, one edge per lane and step, and ORs each word's bits across the
@@ -406,9 +408,9 @@ __device__ __forceinline__ void pull_level(const BatchArgs& a, int L) {
     const u64 vw = (mine && wok) ? a.vis[(size_t)v * W + w] : ~0ull;
     const u64 need = (mine && wok) ? (actw & ~vw) : 0ull;
     const u64 gneed = __ballot(need != 0) & gm;
-    // narrow rows: in-lists of more than kWideScan entries go to the whole
+    // narrow rows: in-lists of more than a.wide_scan entries go to the whole
     // wave below instead of the node's few lanes
-    const bool wide = P <= 8 && e - s > kWideScan;
+    const bool wide = P <= 8 && e - s > a.wide_scan;
     u64 acc = 0;
     if (gneed != 0 && !wide) {
       const int nr = pull_scan<P>(a, front, fm, s, e, need, w, gb, gm, acc);
@@ -480,7 +482,8 @@ __device__ __forceinline__ void relax4(const BatchArgs& a, u64* out, u64* T, con
   }
 }
 
-// A frontier node with at most kSparseWords nonzero words is pushed one edge
+// A frontier node with at most a.sparse_words (<= kSparseWords, the knob
+// batch_sparse_words) nonzero words is pushed one edge
 // per lane (over those words) instead of one word per lane.
 constexpr int kSparseWords = 4;
 
@@ -552,7 +555,7 @@ __device__ __forceinline__ void push_level(const BatchArgs& a, int L) {
       fmu = fmp[u];
     }
     if (has && w == 0) edges += (u64)(e1 - e0);
-    const bool sparse = has && __popcll(fmu) <= kSparseWords;
+    const bool sparse = has && __popcll(fmu) <= a.sparse_words;
     // chunks with few nonzero words: the wave walks the union of its groups'
     // sparse chunks, one edge per lane
     const int cnt = (sparse && w == 0) ? e1 - e0 : 0;
@@ -598,8 +601,8 @@ __device__ __forceinline__ void push_level(const BatchArgs& a, int L) {
       rs = a.rp[u];
       deg = a.rp[u + 1] - rs;
       fmu = fmp[u];
-      if (deg >= kBigB) deg = 0;
-      if (__popcll(fmu) <= kSparseWords) {
+      if (deg >= a.big_b) deg = 0;
+      if (__popcll(fmu) <= a.sparse_words) {
         sdeg = deg;
         deg = 0;
       }
@@ -755,7 +758,7 @@ __device__ __forceinline__ void merge_level(const BatchArgs& a, int L) {
       nodes += 1;
       mf += (u64)deg;
     }
-    stage_chunks_wave(a, L, cstage, v0 + lane, deg, mine && deg >= kBigB);
+    stage_chunks_wave(a, L, cstage, v0 + lane, deg, mine && deg >= a.big_b);
     __builtin_amdgcn_wave_barrier();
     for (int i0 = ib; i0 < ie; i0 += 4 * npw) {
       int jq[4], dq[4];
@@ -1212,7 +1215,7 @@ __global__ void batch_seed(BatchArgs a, const int32_t* src, const int32_t* lane,
         first = !(old & sbit);
       }
     }
-    push_chunks_wave(a, L, s, deg, first && deg >= kBigB);
+    push_chunks_wave(a, L, s, deg, first && deg >= a.big_b);
   }
 }
 
@@ -1439,6 +1442,12 @@ BatchArgs batch_args(const GraphRec* g, BatchWs* w, int Ws, int W) {
   a.base = w->base;
   a.flags = w->flags;
   return a;
+}
+
+void batch_knobs(BatchArgs& a, const dawn_params& p) {
+  a.big_b = std::max(p.batch_big_degree, kBigB);
+  a.wide_scan = std::max(p.batch_wide_scan, 1);
+  a.sparse_words = std::min(std::max(p.batch_sparse_words, 1), kSparseWords);
 }
 
 BatchLevelSum batch_level_sum(const BatchLevel& l) {
@@ -1672,6 +1681,7 @@ struct BatchJob {
   BatchArgs a;
   int32_t* row_base = nullptr;
   long long row_stride = 0;
+  const dawn_params* p = nullptr;
   int L = 1;        // first level of the next chunk
   int Lend = 0;     // last level of the chunk in flight
   int chunk = 4;
@@ -1689,6 +1699,7 @@ static dawn_status batch_begin(Ctx* ctx, const GraphRec* g, BatchJob& j, const i
   DAWN_HIP(hipEventRecord(w->ev0, s));
   DAWN_TRY(batch_launch_prepare(ctx, g, w, true, s));
   j.a = batch_args(g, w, j.W);
+  batch_knobs(j.a, *j.p);
   set_rows(j.a, j.row_base, j.row_stride, k);
   DAWN_TRY(batch_launch_seed(ctx, j.a, w->src, nullptr, k, 0, false, s));
   DAWN_TRY(batch_launch_merge(ctx, j.a, 0, s));
@@ -1717,6 +1728,7 @@ static dawn_status batch_enqueue(Ctx* ctx, const GraphRec* g, const dawn_params&
   if (need > w->nplanes) {
     DAWN_TRY(batch_ensure_planes(w, need, j.W));
     j.a = batch_args(g, w, j.W);
+    batch_knobs(j.a, p);
     set_rows(j.a, j.row_base, j.row_stride, j.k);
   }
   for (int l = L; l <= Lend; ++l) {
@@ -1877,6 +1889,7 @@ dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t*
       j.w = ws[i];
       j.row_base = device_out ? dist + (size_t)b0 * row_stride : stage + (size_t)b0 * g->n;
       j.row_stride = device_out ? row_stride : g->n;
+      j.p = &p;
       st = batch_begin(ctx, g, j, sources + b0, kb);
     }
     // chunks of levels, all running batches side by side
@@ -2034,6 +2047,7 @@ dawn_status mssp_device_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const i
     const int W = (kb + 63) / 64;
     st = batch_launch_prepare(ctx, g, w, false, s);
     BatchArgs a = batch_args(g, w, W);
+    batch_knobs(a, p);
     set_rows(a, d_dist + (size_t)b0 * g->n, g->n, kb);
     if (st == DAWN_OK) st = batch_launch_seed(ctx, a, d_src + b0, nullptr, kb, 0, false, s);
     if (st == DAWN_OK) st = batch_launch_merge(ctx, a, 0, s);

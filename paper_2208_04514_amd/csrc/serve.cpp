@@ -298,7 +298,13 @@ static dawn_status launch_level(Server* S, Engine* e) {
       Wa = i + 1;
       break;
     }
+  dawn_params p;
+  {
+    std::lock_guard<std::mutex> lk(e->g->mu);
+    p = e->g->params;
+  }
   BatchArgs a = batch_args(g, w, e->W, Wa);
+  batch_knobs(a, p);
   if (e->nseed > 0) {
     const int k = e->nseed;
     DAWN_HIP(hipMemcpyAsync(w->src, e->h_src, (size_t)k * 4, hipMemcpyHostToDevice, s));
@@ -314,6 +320,7 @@ static dawn_status launch_level(Server* S, Engine* e) {
   if (need > w->nplanes) {
     DAWN_TRY(batch_ensure_planes(w, need, e->W));
     a = batch_args(g, w, e->W, Wa);
+    batch_knobs(a, p);
   }
   // the merge writes only the planes a running lane's level can reach
   a.nplanes = std::min(a.nplanes, std::max(need, 1));
@@ -321,11 +328,6 @@ static dawn_status launch_level(Server* S, Engine* e) {
   aw.W = e->W;
   for (int i = 0; i < 64; ++i) aw.w[i] = i < e->W ? e->act[i] : 0ull;
   DAWN_TRY(batch_launch_level_prep(aw, w->act, w->ctrl, (L + 1) & 1, s));
-  dawn_params p;
-  {
-    std::lock_guard<std::mutex> lk(e->g->mu);
-    p = e->g->params;
-  }
   const bool pull = e->have_last ? batch_choose_pull(p, e->last, g->n, Wa) : false;
   DAWN_TRY(batch_launch_expand(S->ctx, a, pull, L + 1, s));
   DAWN_TRY(batch_launch_merge(S->ctx, a, L + 1, s));

@@ -177,9 +177,20 @@ dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, u
     t.batched = true;
     t.k = kb;
     t.elems = (size_t)kb * g->n;
-    // batch_alpha 1e-4 keeps every batched level push, 1e6 every level pull
+    // batch_alpha 1e-4 keeps every batched level push, 1e6 every level pull;
+    // then the push chunking threshold, the narrow-row whole-wave scan length
+    // and the sparse push width, each from the settings chosen so far
     st = search({variants([](dawn_params& p, double v) { p.batch_alpha = (float)v; },
                           {1e-4, 0.25, 1, 4, 16, 64, 1e6})});
+    if (st == DAWN_OK)
+      st = search({variants([](dawn_params& p, double v) { p.batch_big_degree = (int)v; },
+                            {64, 128, 256, 1024})});
+    if (st == DAWN_OK && (kb + 63) / 64 <= 8)
+      st = search({variants([](dawn_params& p, double v) { p.batch_wide_scan = (int)v; },
+                            {16, 32, 48, 96, 192})});
+    if (st == DAWN_OK)
+      st = search({variants([](dawn_params& p, double v) { p.batch_sparse_words = (int)v; },
+                            {1, 2, 4})});
   }
   cleanup();
   if (st != DAWN_OK) return st;

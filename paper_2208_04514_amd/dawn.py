@@ -75,6 +75,8 @@ class Params(ctypes.Structure):
         ("beta", ctypes.c_float), ("graph_levels", ctypes.c_int32),
         ("small_n", ctypes.c_int32), ("batch_alpha", ctypes.c_float),
         ("batch_lanes", ctypes.c_int32), ("timing", ctypes.c_int32),
+        ("batch_big_degree", ctypes.c_int32), ("batch_wide_scan", ctypes.c_int32),
+        ("batch_sparse_words", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

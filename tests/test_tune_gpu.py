@@ -41,8 +41,57 @@ def test_set_params_validation(ctx, upload):
     h, g, src = upload("uniform4096")
     before = D.dawn_get_params(ctx, h)
     for bad in (dict(driver=9), dict(block=128), dict(batch_lanes=100), dict(big_degree=10),
-                dict(timing=1, driver=3)):
+                dict(timing=1, driver=3), dict(batch_big_degree=32), dict(batch_wide_scan=600),
+                dict(batch_sparse_words=5)):
         with pytest.raises(D.DawnError) as ei:
             D.dawn_set_params(ctx, h, **bad)
         assert ei.value.status == D.DAWN_E_INVALID_ARG
     assert D.dawn_get_params(ctx, h) == before
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid128ns"])
+@pytest.mark.parametrize("k", [100, 2000])
+def test_batched_knob_candidates_bit_exact(ctx, upload, name, k):
+    """Every candidate value the autotuner tries for the batched knobs gives
+    the oracle's rows (narrow rows, k = 100, and wide ones, k = 2000)."""
+    h, g, _ = upload(name)
+    srcs = gg.sample_sources(g.n, k, 77 + k)
+    want = oracle.mssp(g, srcs, threads=16)
+    saved = D.dawn_get_params(ctx, h)
+    try:
+        for knob, vals in (("batch_alpha", (1e-4, 0.25, 1, 4, 16, 64, 1e6)),
+                           ("batch_big_degree", (64, 128, 256, 1024)),
+                           ("batch_wide_scan", (16, 32, 48, 96, 192)),
+                           ("batch_sparse_words", (1, 2, 4))):
+            for v in vals:
+                D.dawn_set_params(ctx, h, **{knob: v})
+                got, _ = D.dawn_mssp(ctx, h, srcs)
+                assert np.array_equal(got, want), f"{name} k={k} {knob}={v}"
+            D.dawn_set_params(ctx, h, **saved)
+    finally:
+        D.dawn_set_params(ctx, h, **saved)
+
+
+def test_tuned_settings_round_trip_the_cache(ctx, tmp_path):
+    """Settings found by dawn_autotune go to the on-disk cache under (arch,
+    graph signature, batch width) and come back to give the same rows."""
+    from paper_2208_04514_amd import tune_cache as T
+    g, src = gg.load_config("rmat12")
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    path = str(tmp_path / "tuned.json")
+    try:
+        best = D.dawn_autotune(ctx, h, src[:64], what=2)
+        arch, sig = T.device_arch(0), T.graph_signature(g.row_ptr, g.col)
+        assert arch.startswith("gfx")
+        T.store(arch, sig, 64, best, path)
+        h2 = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+        try:
+            loaded = T.lookup(arch, sig, 64, path)
+            D.dawn_set_params(ctx, h2, **loaded)
+            assert D.dawn_get_params(ctx, h2) == best
+            got, _ = D.dawn_mssp(ctx, h2, src[:64])
+            assert np.array_equal(got, oracle.mssp(g, src[:64]))
+        finally:
+            D.dawn_graph_release(ctx, h2)
+    finally:
+        D.dawn_graph_release(ctx, h)
