@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Graph", "to_csr", "gen_uniform", "gen_rmat", "gen_grid", "gen_edges",
     "gen_islands", "largest_wcc_nodes", "sample_sources", "CONFIGS", "load_config",
-    "reach_edges_from_dist",
+    "reach_edges_from_dist", "gen_weights",
 ]
 
 
@@ -233,6 +233,30 @@ def largest_wcc_nodes(g: Graph) -> np.ndarray:
     np.minimum.at(minid, labels, np.arange(g.n))
     best = max(range(ncomp), key=lambda c: (sizes[c], -minid[c]))
     return np.nonzero(labels == best)[0].astype(np.int32)
+
+
+def gen_weights(g: Graph, lo: int, hi: int, seed: int, symmetric: bool = False) -> np.ndarray:
+    """Seeded integer edge weights, uniform in [lo, hi], one per CSR entry.
+
+    With ``symmetric`` the two directions of an edge get the same weight (a
+    hash of the unordered pair and the seed picks it), as on a road network.
+    The paper's weighted experiments are future work, so this is a plain
+    stand-in: uniform weights on the same synthetic graphs."""
+    if hi < lo or lo < 0:
+        raise ValueError("need 0 <= lo <= hi")
+    span = np.uint64(hi - lo + 1)
+    if not symmetric:
+        rng = np.random.default_rng(seed)
+        return rng.integers(lo, hi + 1, size=g.m).astype(np.int32)
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr.astype(np.int64)))
+    dst = g.col.astype(np.uint64)
+    a, b = np.minimum(src, dst), np.maximum(src, dst)
+    with np.errstate(over="ignore"):
+        x = (a * np.uint64(0x9E3779B97F4A7C15)) ^ (b + np.uint64(seed) * np.uint64(0xBF58476D1CE4E5B9))
+        x ^= x >> np.uint64(31)
+        x *= np.uint64(0x94D049BB133111EB)
+        x ^= x >> np.uint64(29)
+    return (np.uint64(lo) + x % span).astype(np.int32)
 
 
 def sample_sources(pool, k: int, seed: int) -> np.ndarray:

@@ -16,6 +16,13 @@ Contents
     Theorem 1 of the paper (Section 3.1) written out: dist(i, j) is the
     smallest k >= 1 with (A^k)_ij != 0 for i != j; Lemma 1 says (A^k)_ij
     counts length-k paths, so the boolean power suffices.
+``wsssp``, ``wmssp``
+    Weighted graphs (the (min, +) extension the paper leaves to future work):
+    Dijkstra's algorithm with a binary heap over non-negative integer weights
+    (``dijkstra_oracle.c``), int64 distances, -1 where unreachable.
+``floyd_warshall_weighted``, ``check_weighted_invariants``
+    Their pins: the weighted Floyd–Warshall recurrence on tiny graphs, and the
+    properties of exact weighted distances at any size.
 ``check_invariants``
     Properties that hold at any size: dist[s] = 0; on every edge (u, v) with
     u reached, 0 <= dist[v] <= dist[u] + 1 (Fact 1, Section 3.1); every
@@ -35,6 +42,7 @@ from . import build as _build
 
 _LIB = None
 _I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
 
 
 def _ptr(a: np.ndarray):
@@ -52,7 +60,11 @@ def lib():
         L.oracle_mssp.argtypes = [ctypes.c_int32, _I32P, _I32P, _I32P, ctypes.c_int32,
                                   _I32P, ctypes.c_int32]
         L.oracle_largest_wcc.argtypes = [ctypes.c_int32, _I32P, _I32P, _I32P, _I32P]
-        for f in (L.oracle_sssp, L.oracle_mssp, L.oracle_largest_wcc):
+        L.oracle_wsssp.argtypes = [ctypes.c_int32, _I32P, _I32P, _I32P, ctypes.c_int32, _I64P]
+        L.oracle_wmssp.argtypes = [ctypes.c_int32, _I32P, _I32P, _I32P, _I32P, ctypes.c_int32,
+                                   _I64P, ctypes.c_int32]
+        for f in (L.oracle_sssp, L.oracle_mssp, L.oracle_largest_wcc, L.oracle_wsssp,
+                  L.oracle_wmssp):
             f.restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -87,6 +99,93 @@ def mssp(g, sources, threads: int = 1) -> np.ndarray:
                          int(threads)) != 0:
         raise ValueError("oracle_mssp: bad argument")
     return dist
+
+
+def _weights(g, weight):
+    w = np.ascontiguousarray(weight, dtype=np.int32)
+    if w.shape != (g.m,):
+        raise ValueError("one weight per CSR entry")
+    if w.size == 0:
+        w = np.zeros(1, dtype=np.int32)
+    return w
+
+
+def wsssp(g, weight, s: int) -> np.ndarray:
+    """Weighted shortest-path lengths from ``s`` (int64, -1 where unreachable).
+
+    ``weight[e]`` belongs to CSR entry e; weights must be >= 0."""
+    rp, col = _csr(g)
+    w = _weights(g, weight)
+    dist = np.empty(g.n, dtype=np.int64)
+    if lib().oracle_wsssp(g.n, _ptr(rp), _ptr(col), _ptr(w), int(s),
+                          dist.ctypes.data_as(_I64P)) != 0:
+        raise ValueError("oracle_wsssp: bad argument (negative weight?)")
+    return dist
+
+
+def wmssp(g, weight, sources, threads: int = 1) -> np.ndarray:
+    """Row r = ``wsssp(g, weight, sources[r])``, on ``threads`` POSIX threads."""
+    rp, col = _csr(g)
+    w = _weights(g, weight)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    dist = np.empty((src.size, g.n), dtype=np.int64)
+    if src.size == 0:
+        return dist
+    if lib().oracle_wmssp(g.n, _ptr(rp), _ptr(col), _ptr(w), _ptr(src), src.size,
+                          dist.ctypes.data_as(_I64P), int(threads)) != 0:
+        raise ValueError("oracle_wmssp: bad argument")
+    return dist
+
+
+def floyd_warshall_weighted(g, weight) -> np.ndarray:
+    """All-pairs weighted distances by d[i,j] = min(d[i,j], d[i,k] + d[k,j]).
+
+    Tiny graphs only; a repeated edge keeps its lightest weight.  int64 with
+    -1 for unreachable pairs and 0 on the diagonal."""
+    n = g.n
+    inf = np.int64(1) << 60
+    d = np.full((n, n), inf, dtype=np.int64)
+    for u in range(n):
+        for e in range(g.row_ptr[u], g.row_ptr[u + 1]):
+            v = int(g.col[e])
+            d[u, v] = min(d[u, v], int(weight[e]))
+    np.fill_diagonal(d, 0)
+    for k in range(n):
+        d = np.minimum(d, d[:, k:k + 1] + d[k:k + 1, :])
+    return np.where(d >= inf, -1, d)
+
+
+def check_weighted_invariants(g, weight, s: int, dist: np.ndarray,
+                              reach: np.ndarray | None = None) -> None:
+    """Raise AssertionError unless ``dist`` holds exact weighted distances from s:
+    dist[s] = 0; every edge (u, v, w) with u reached has v reached and
+    dist[v] <= dist[u] + w; every reached v != s has an in-edge with
+    dist[u] + w = dist[v] (a tight predecessor); the reached set equals
+    forward reachability.  With positive weights these fix the distances
+    (following tight in-edges from any reached node strictly lowers the value
+    and so ends at s); a cycle of zero-weight edges could hold too small a
+    value, so zero weights are pinned by Dijkstra against Floyd–Warshall."""
+    dist = np.asarray(dist, dtype=np.int64)
+    w = np.asarray(weight, dtype=np.int64)
+    n = g.n
+    assert dist.shape == (n,) and dist[s] == 0
+    assert (dist >= -1).all()
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    src = np.repeat(np.arange(n), deg)
+    dst = g.col.astype(np.int64)
+    du, dv = dist[src], dist[dst]
+    r = du >= 0
+    assert (dv[r] >= 0).all(), "target of a reached node must be reached"
+    assert (dv[r] <= du[r] + w[r]).all(), "dist[v] <= dist[u] + w(u, v)"
+    tight = np.zeros(n, dtype=bool)
+    ok = r & (dv == du + w)
+    tight[dst[ok]] = True
+    need = dist >= 0
+    need[s] = False
+    assert tight[need].all(), "reached node without a tight in-edge"
+    if reach is None:
+        reach = forward_reachable(g, s)
+    assert np.array_equal(dist >= 0, reach), "reached set != forward reachability"
 
 
 def largest_wcc(g) -> np.ndarray:

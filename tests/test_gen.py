@@ -125,3 +125,16 @@ def test_islands_components():
     assert not (src == g.col).any()
     fwd = set(zip(src.tolist(), g.col.tolist()))
     assert all((v, u) in fwd for u, v in fwd)
+
+
+def test_weights_seeded_in_range_and_symmetric():
+    g, _ = gg.load_config("grid128")
+    w = gg.gen_weights(g, 3, 9, seed=5)
+    assert w.dtype == np.int32 and w.shape == (g.m,)
+    assert w.min() >= 3 and w.max() <= 9
+    assert np.array_equal(w, gg.gen_weights(g, 3, 9, seed=5))
+    ws = gg.gen_weights(g, 1, 1000, seed=6, symmetric=True)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    fwd = {(int(a), int(b)): int(x) for a, b, x in zip(src, g.col, ws)}
+    assert all(fwd[(b, a)] == x for (a, b), x in fwd.items())
+    assert len(np.unique(ws)) > 500
