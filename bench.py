@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 
 # The knobs of the plain level loop that the bench takes from the tuning
 # cache (paper_2208_04514_amd/tuned_params.json, written by dawn_autotune on
-# eight other sources of the same graph; --autotune searches again live).
+# 32 other sources of the same graph; --autotune searches again live).
 PLAIN_KNOB_NAMES = ("driver", "graph_levels", "big_degree", "alpha", "beta", "block",
                     "blocks_per_cu", "pull_lane_edges")
 BATCH_KNOB_NAMES = ("batch_alpha", "batch_big_degree", "batch_wide_scan", "batch_sparse_words")
@@ -335,6 +335,37 @@ def uniform_bench(D, ctx, reps=20):
             "us_per_level": round(t / lv * 1e6, 2), "levels_per_source": round(lv / reps / src.size, 2)}
 
 
+def weighted_bench(D, ctx):
+    """Weighted graphs (the (min, +) level loop): R-MAT 20 and grid 2048^2
+    with seeded integer weights 1..100, equal in both directions; sources of
+    the plain workloads, one at a time, device output."""
+    import torch
+    import graphgen as gg
+    res = {}
+    for name, k in (("rmat20", 8), ("grid2048", 2)):
+        g, src = gg.load_config(name)
+        w = gg.gen_weights(g, 1, 100, seed=12, symmetric=True)
+        h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+        D.dawn_graph_set_weights(ctx, h, w)
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        D.dawn_sssp_weighted(ctx, h, int(src[0]), out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        se, ks, rounds = 0, 0.0, []
+        for s in src[:k]:
+            _, st = D.dawn_sssp_weighted(ctx, h, int(s), out=out)
+            se += st["source_edges"]
+            ks += st["kernel_ms"]
+            rounds.append(st["levels"])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[name] = {"sources": k, "weights": "uniform 1..100, symmetric",
+                     "ms_per_source": round(t / k * 1e3, 3), "gteps": round(se / t / 1e9, 3),
+                     "gteps_device": round(se / ks / 1e6, 3), "rounds": rounds}
+        D.dawn_graph_release(ctx, h)
+    return res
+
+
 def small_component_bench(D, ctx):
     """Sources in small components (512 components of 16..2048 nodes): one
     workgroup per source (small_n = 2048) vs the general level loop
@@ -601,7 +632,7 @@ def roofline_only(D, ctx, params_json):
         p = json.loads(params_json)
         D.dawn_set_params(ctx, h, **p)
     else:
-        p, _, _ = cached_knobs(D, ctx, h, g, 1, PLAIN_KNOB_NAMES, 1, 9001, 8, False, None)
+        p, _, _ = cached_knobs(D, ctx, h, g, 1, PLAIN_KNOB_NAMES, 1, 9001, 32, False, None)
     lk_ms, lk_launches, levels, lk_clk = level_kernel_timing(D, ctx, h, src, out)
     torch.cuda.synchronize()
     roof = roofline_entry(g, out.cpu().numpy(), lk_ms, lk_launches, levels, p, lk_clk)
@@ -665,7 +696,7 @@ def main():
     h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
     out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
 
-    knobs, knobs_from, tune_s = cached_knobs(D, ctx, h, g, 1, PLAIN_KNOB_NAMES, 1, 9001, 8,
+    knobs, knobs_from, tune_s = cached_knobs(D, ctx, h, g, 1, PLAIN_KNOB_NAMES, 1, 9001, 32,
                                              args.autotune, args.tune_file)
 
     _log("[bench] plain SSSP timed region")
@@ -713,6 +744,8 @@ def main():
         extra["apsp"] = apsp_bench(D, ctx)
         _log("[bench] grid 2048^2 level-loop drivers")
         extra["grid"] = grid_bench(D, ctx)
+        _log("[bench] weighted graphs ((min, +) level loop)")
+        extra["weighted"] = weighted_bench(D, ctx)
         _log("[bench] small components")
         extra["small_components"] = small_component_bench(D, ctx)
     if not args.no_serve:

@@ -180,6 +180,14 @@ dawn_status dawn_graph_release(dawn_ctx *ctx, int32_t graph);
 
 dawn_status dawn_graph_get_info(dawn_ctx *ctx, int32_t graph, dawn_graph_info *out);
 
+/* Attach non-negative integer edge weights to a resident graph (copied:
+ * weights[e], host, m int32, belongs to CSR entry e, the edge from e's row to
+ * col[e]).  A second call replaces them.  Every path length must fit an int32
+ * distance: max weight x (n - 1) <= 2^31 - 2.  Used by dawn_sssp_weighted
+ * only.  Errors: INVALID_ARG (null, negative or too large weights),
+ * NOT_FOUND, NO_MEMORY, DEVICE. */
+dawn_status dawn_graph_set_weights(dawn_ctx *ctx, int32_t graph, const int32_t *weights);
+
 /* Tuning knobs (see dawn_params).  set: fields left 0 keep the default;
  * invalid values give INVALID_ARG. */
 dawn_status dawn_get_params(dawn_ctx *ctx, int32_t graph, dawn_params *out);
@@ -193,6 +201,20 @@ dawn_status dawn_set_params(dawn_ctx *ctx, int32_t graph, const dawn_params *in)
  * stats may be NULL.  Errors: INVALID_ARG, NOT_FOUND, NO_MEMORY, DEVICE. */
 dawn_status dawn_sssp(dawn_ctx *ctx, int32_t graph, int32_t source, int32_t *dist,
                       uint32_t flags, dawn_run_stats *stats);
+
+/* Weighted single-source shortest paths: the paper's level loop over the
+ * (min, +) semiring, which Section 5 names as future work.  dist[v] is the
+ * least sum of weights over directed paths source -> v (int32, -1 when no
+ * path exists), for the weights of dawn_graph_set_weights.  Each round
+ * relaxes the out-edges of the nodes whose distance dropped in the previous
+ * round (an atomic minimum per edge) until a round lowers nothing; a node may
+ * join several rounds, so stats->levels counts rounds, which can exceed the
+ * hop depth.  dist: n int32 (host, or device with DAWN_DEVICE_OUT); stats may
+ * be NULL (edges_examined is not counted; source_edges and reached are as
+ * for dawn_sssp).  Errors: INVALID_ARG (also: no weights attached),
+ * NOT_FOUND, NO_MEMORY, DEVICE. */
+dawn_status dawn_sssp_weighted(dawn_ctx *ctx, int32_t graph, int32_t source, int32_t *dist,
+                               uint32_t flags, dawn_run_stats *stats);
 
 /* Single-source run that allocates nothing, for callers that cannot allocate
  * device memory (code under stream capture, tight serving loops, harnesses

@@ -295,6 +295,55 @@ dawn_status dawn_graph_get_info(dawn_ctx* c, int32_t graph, dawn_graph_info* out
   return DAWN_OK;
 }
 
+dawn_status dawn_graph_set_weights(dawn_ctx* c, int32_t graph, const int32_t* weights) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  if (!weights && g->m > 0) return fail(DAWN_E_INVALID_ARG, "null weights");
+  int32_t mx = 0;
+  for (long long e = 0; e < g->m; ++e) {
+    if (weights[e] < 0) return fail(DAWN_E_INVALID_ARG, "weights[%lld] = %d is negative", e, weights[e]);
+    mx = std::max(mx, weights[e]);
+  }
+  // every path length must fit in an int32 distance (and stay below -1 as
+  // an unsigned value, which marks "unreached")
+  if ((long long)mx * (long long)(g->n - 1) > 0x7ffffffeLL)
+    return fail(DAWN_E_INVALID_ARG, "max weight %d x (n - 1) = %lld exceeds int32 distances", mx,
+                (long long)mx * (g->n - 1));
+  DAWN_HIP(hipSetDevice(ctx->device));
+  int32_t* d = nullptr;
+  const size_t bytes = (size_t)std::max(g->m, 1LL) * 4;
+  DAWN_TRY(dev_alloc(ctx, (void**)&d, bytes));
+  hipError_t e = g->m > 0 ? hipMemcpy(d, weights, (size_t)g->m * 4, hipMemcpyHostToDevice) : hipSuccess;
+  if (e != hipSuccess) {
+    dev_free(ctx, d, bytes);
+    return fail(DAWN_E_DEVICE, "weights upload: %s", hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g->mu);
+  if (g->wt) dev_free(ctx, g->wt, bytes);
+  else g->bytes += bytes;
+  g->wt = d;
+  g->max_w = mx;
+  return DAWN_OK;
+}
+
+dawn_status dawn_sssp_weighted(dawn_ctx* c, int32_t graph, int32_t source, int32_t* dist,
+                               uint32_t flags, dawn_run_stats* stats) {
+  clear_error();
+  DAWN_TRY(check_ctx(c));
+  if (!dist) return fail(DAWN_E_INVALID_ARG, "null dist");
+  if (flags & ~DAWN_DEVICE_OUT) return fail(DAWN_E_INVALID_ARG, "unknown flags 0x%x", flags);
+  Ctx* ctx = C(c);
+  std::shared_ptr<GraphRec> g;
+  DAWN_TRY(get_graph(ctx, graph, &g));
+  if (source < 0 || source >= g->n)
+    return fail(DAWN_E_INVALID_ARG, "source %d outside [0, %d)", source, g->n);
+  DAWN_HIP(hipSetDevice(ctx->device));
+  return wsssp_run(ctx, g.get(), source, dist, (flags & DAWN_DEVICE_OUT) != 0, stats);
+}
+
 dawn_status dawn_get_params(dawn_ctx* c, int32_t graph, dawn_params* out) {
   clear_error();
   DAWN_TRY(check_ctx(c));

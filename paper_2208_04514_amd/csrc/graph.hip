@@ -246,6 +246,9 @@ GraphRec::~GraphRec() {
   batch_pool.clear();
   if (stage) dev_free(ctx, stage, stage_bytes);
   stage = nullptr;
+  wsssp_pool_free(this);
+  if (wt) dev_free(ctx, wt, (size_t)std::max(m, 1LL) * 4);
+  wt = nullptr;
   wcc_sub.reset();
   if (ctx) free_graph_buffers(this);
 }

@@ -62,6 +62,8 @@ struct GridBarrier {
 // whole 128-byte line.
 constexpr int kStripes = 16;
 constexpr int kLine = 128;
+constexpr int kClkStripes = 16;        // lines of wall-clock stamps per timed launch
+constexpr int kClkWords = kLine / 8;   // u64 per line
 
 constexpr int kPullBig = 512;     // in-degree from which a batched pull splits the in-list
 constexpr int kPullChunk = 256;   // in-edges per chunk of a split in-list
@@ -136,8 +138,10 @@ struct SsspArgs {
   int32_t lrec;
   int32_t lds_words;          // pull levels copy the visited bitmap (this many words,
                               //   = nw) into LDS; 0 = read it from global memory
-  unsigned long long* clk;    // timing mode: [0] earliest workgroup start, [1] latest
-                              //   workgroup end of this launch (GPU wall clock); null otherwise
+  unsigned long long* clk;    // timing mode: this launch's kClkStripes lines; in line s,
+                              //   [0] the earliest start and [1] the latest end (GPU wall
+                              //   clock) of the workgroups b with b % kClkStripes = s;
+                              //   null otherwise
 };
 
 // ----------------------------------------------------------- host objects --
@@ -169,7 +173,8 @@ struct SsspWs {
   int32_t* dist = nullptr;      // internal output for host-destination calls
   int32_t* level_nf = nullptr;
   uint8_t* level_dir = nullptr;
-  unsigned long long* clk = nullptr;   // timing mode: two wall-clock stamps per level launch
+  unsigned long long* clk = nullptr;   // timing mode: wall-clock stamps of the level launches
+  int32_t clk_cap = 0;                 //   (allocated on first use, clk_cap launches)
   int32_t lrec = 0;
   bool poisoned = false;        // a launch failed: never reuse these buffers
   size_t chunk_cap = 0;
@@ -219,6 +224,11 @@ struct GraphRec {
   std::mutex mu;                          // guards the pools and the WCC cache
   std::vector<std::unique_ptr<SsspWs>> sssp_pool;
   std::vector<BatchWs*> batch_pool;
+  // weighted graphs (dawn_graph_set_weights): weight of each CSR entry
+  int32_t* wt = nullptr;
+  int32_t max_w = 0;
+  std::atomic<int> wsssp_hint{0};         // rounds the last weighted run needed
+  void* wpool = nullptr;                  // pooled weighted-run workspaces (wsssp.hip)
   // device staging of host-destination batched rows, kept between calls
   int32_t* stage = nullptr;
   size_t stage_bytes = 0;
@@ -267,6 +277,11 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
 dawn_status scratch_init(int device);
 dawn_status sssp_run_noalloc(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source,
                              int32_t* d_dist, hipStream_t s, dawn_run_stats* stats);
+
+// wsssp.hip: the (min, +) level loop over a weighted graph
+dawn_status wsssp_run(Ctx* ctx, GraphRec* g, int32_t source, int32_t* dist, bool device_out,
+                      dawn_run_stats* stats);
+void wsssp_pool_free(GraphRec* g);
 
 // mssp.hip
 dawn_status mssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, const int32_t* sources,

@@ -243,28 +243,44 @@ __device__ __forceinline__ int pull_scan(const BatchArgs& a, const u64* front, c
       if ((__ballot(acc != need) & gm) == 0) break;
       continue;
     }
+    // wide groups (EPL = 1): the edges whose source has visited words, in
+    // list order, in rounds of row loads that are all in flight together;
+    // the exit test follows every round (two rows first: a hub early in the
+    // list usually covers every needed lane), so a covered node stops after
+    // the row that covered it instead of at the end of the P edges.  The
+    // groups of a wave run the rounds in step (a group with nothing left
+    // idles), so the cover test's ballot sees every lane of the wave.
+    const int j0 = j - P;
+    u64 hits = (__ballot(my_m[0] != 0) & gm) >> gb;   // bit i: edge j0 + i has visited words
+    int round = 2;
+    bool covered = false;
+    while (__ballot(hits != 0) != 0) {
+      u64 val[8];
+      int last = 0;
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) {
-      u64 hits = (__ballot(my_m[k] != 0) & gm) >> gb;   // bit i: edge i's source is on the frontier
-      while (hits) {
-        u64 val[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          val[q] = 0;
-          if (hits) {
-            const int i = __builtin_ctzll(hits);
-            hits &= hits - 1;
-            const int u = group_read<P>(my_u[k], gb, i);
-            const u64 m = group_read64<P>(my_m[k], gb, i);
-            if (((m >> w) & 1ull) && acc != need) val[q] = front[(size_t)u * W + w];
-          }
+      for (int q = 0; q < 8; ++q) {
+        val[q] = 0;
+        if (q < round && hits) {
+          const int i = __builtin_ctzll(hits);
+          hits &= hits - 1;
+          last = i;
+          const int u = group_read<P>(my_u[0], gb, i);
+          const u64 m = group_read64<P>(my_m[0], gb, i);
+          if (((m >> w) & 1ull) && acc != need) val[q] = front[(size_t)u * W + w];
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r |= val[q];
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) r |= val[q];
+      acc |= r & need;
+      const bool group_covered = (__ballot(acc != need) & gm) == 0;
+      if (group_covered && !covered) {
+        covered = true;
+        j = j0 + last + 1;
+      }
+      if (covered) hits = 0;
+      round = 8;
     }
-    acc |= r & need;
-    if ((__ballot(acc != need) & gm) == 0) break;
+    if (covered) break;
   }
   return min(j, e) - s;
 }
@@ -918,6 +934,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
                                                           const u64* __restrict__ emask,
                                                           int mode, int claim) {
   const int clear = mode & kEmitClear;
+  const bool whole_clear = clear && (mode & kEmitMarkClean);
   if (mode & kEmitFromRun) {
     const BatchRun& r = a.ctrl->run;
     if (ld_relaxed(&r.done) != 1 || ld_relaxed(&a.flags[kFlagStatus]) != 0) return;
@@ -963,6 +980,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
     if (!wm) continue;
     const bool live = v < a.n;
     const bool full = (int)(t % ntiles) * kWave + kWave <= a.n;  // no lane past the last node
+    bool cleared = false;     // the group's words were already cleared whole
     const size_t base = (size_t)(live ? v : 0) * Ws + w0;
     u64 x[EG];
     u64 pl[DMAX][EG];
@@ -997,6 +1015,24 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
               pl[d][2 * q + 1] = live ? t2.y : 0;
             }
         }
+      if (whole_clear && live) {
+        // every lane is emitted: the words just read are cleared with the
+        // same 16-byte accesses (the line is still in the cache)
+        ulonglong2* wv = reinterpret_cast<ulonglong2*>(a.vis + base);
+        const ulonglong2 z = {0ull, 0ull};
+#pragma unroll
+        for (int q = 0; q < EG / 2; ++q)
+          if ((wm >> (2 * q)) & 3u) wv[q] = z;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+          if (d < D) {
+            ulonglong2* wp = reinterpret_cast<ulonglong2*>(a.planes[d] + base);
+#pragma unroll
+            for (int q = 0; q < EG / 2; ++q)
+              if ((wm >> (2 * q)) & 3u) wp[q] = z;
+          }
+        cleared = true;
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < EG; ++e) x[e] = live && ((wm >> e) & 1u) ? a.vis[base + e] : 0;
@@ -1025,7 +1061,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_emit(BatchArgs a, int D,
 #pragma unroll
           for (int d = 0; d < DMAX; ++d) pe[d] = pl[d][k];
         }
-      if (clear && live) {
+      if (clear && live && !cleared) {
         const u64 rem = xe & ~em;
         a.vis[base + e] = rem;
 #pragma unroll

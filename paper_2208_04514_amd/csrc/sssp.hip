@@ -842,21 +842,27 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
 }
 
 // In timing mode (a.clk set) every workgroup stamps its start and end with
-// the GPU wall clock: the launch's own duration, without its dispatch gap.
+// the GPU wall clock into the line of its stripe (so that the stamps of
+// hundreds of workgroups do not queue on one line): the launch's own
+// duration, without its dispatch gap, is the latest end minus the earliest
+// start over the stripes.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
-  if (a0.clk && threadIdx.x == 0) atomicMin(&a0.clk[0], (unsigned long long)wall_clock64());
+  unsigned long long* line = a0.clk ? a0.clk + (blockIdx.x % kClkStripes) * kClkWords : nullptr;
+  if (line && threadIdx.x == 0) atomicMin(&line[0], (unsigned long long)wall_clock64());
   level_step<BLOCK>(a0, parity);
-  if (a0.clk) {
+  if (line) {
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(&a0.clk[1], (unsigned long long)wall_clock64());
+    if (threadIdx.x == 0) atomicMax(&line[1], (unsigned long long)wall_clock64());
   }
 }
 
+// Stamp lines of `launches` launches: starts at the largest value, ends at 0.
 __global__ void clk_reset(unsigned long long* clk, int launches) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < launches; i += gridDim.x * blockDim.x) {
-    clk[2 * i] = ~0ull;
-    clk[2 * i + 1] = 0ull;
+  const int lines = launches * kClkStripes;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < lines; i += gridDim.x * blockDim.x) {
+    clk[(size_t)i * kClkWords] = ~0ull;
+    clk[(size_t)i * kClkWords + 1] = 0ull;
   }
 }
 
@@ -911,7 +917,7 @@ static dawn_status ws_create(Ctx* ctx, GraphRec* g, std::unique_ptr<SsspWs>* out
   if (s == DAWN_OK) s = alloc((void**)&w->dist, (size_t)n * 4);
   if (s == DAWN_OK) s = alloc((void**)&w->level_nf, (size_t)w->lrec * 4);
   if (s == DAWN_OK) s = alloc((void**)&w->level_dir, (size_t)w->lrec);
-  if (s == DAWN_OK) s = alloc((void**)&w->clk, (size_t)w->lrec * 16);
+
   // the destructor frees each buffer and returns `bytes` to the budget at once
   if (s != DAWN_OK) return s;
   DAWN_HIP(hipMemset(w->ctrl, 0, sizeof(SsspCtrl)));
@@ -1006,8 +1012,17 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
                        source);
     DAWN_HIP(hipGetLastError());
     if (level_ms) {
-      hipLaunchKernelGGL(clk_reset, dim3(std::max(1, (w->lrec + 255) / 256)), dim3(256), 0,
-                         w->stream, w->clk, w->lrec);
+      if (!w->clk) {
+        // stamp lines for the first 4096 launches of a traversal (2 MiB per
+        // 1024 launches), kept with the workspace once timing is used
+        const int cap = std::min(w->lrec, 4096);
+        const size_t bytes = (size_t)cap * kClkStripes * kLine;
+        DAWN_TRY(dev_alloc(ctx, (void**)&w->clk, bytes));
+        w->bytes += bytes;
+        w->clk_cap = cap;
+      }
+      hipLaunchKernelGGL(clk_reset, dim3(std::max(1, (w->clk_cap * kClkStripes + 255) / 256)),
+                         dim3(256), 0, w->stream, w->clk, w->clk_cap);
       DAWN_HIP(hipGetLastError());
     }
     *launches = 1;
@@ -1015,7 +1030,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
     for (long long it = 0; it <= max_launch; ++it) {
       const int parity = (int)(it & 1);
       SsspArgs al = a;
-      if (level_ms && it < w->lrec) al.clk = w->clk + 2 * it;
+      if (level_ms && it < w->clk_cap) al.clk = w->clk + (size_t)it * kClkStripes * kClkWords;
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
       hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, al, parity);
       if (level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
@@ -1034,12 +1049,19 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
         *final_parity = parity;
         if (level_ms) {
           *launches = level_launches;
-          const int nl = std::min(level_launches, w->lrec);
-          std::vector<unsigned long long> stamps((size_t)nl * 2);
+          const int nl = std::min(level_launches, w->clk_cap);
+          std::vector<unsigned long long> stamps((size_t)nl * kClkStripes * kClkWords);
           DAWN_HIP(hipMemcpy(stamps.data(), w->clk, stamps.size() * 8, hipMemcpyDeviceToHost));
           double ticks = 0.0;
-          for (int i = 0; i < nl; ++i)
-            if (stamps[2 * i + 1] > stamps[2 * i]) ticks += (double)(stamps[2 * i + 1] - stamps[2 * i]);
+          for (int i = 0; i < nl; ++i) {
+            unsigned long long t0 = ~0ull, t1 = 0;
+            for (int sl = 0; sl < kClkStripes; ++sl) {
+              const unsigned long long* ln = &stamps[((size_t)i * kClkStripes + sl) * kClkWords];
+              t0 = std::min(t0, ln[0]);
+              t1 = std::max(t1, ln[1]);
+            }
+            if (t1 > t0) ticks += (double)(t1 - t0);
+          }
           if (clock_ms && ctx->wall_khz > 0) *clock_ms = ticks / (double)ctx->wall_khz;
         }
         return DAWN_OK;

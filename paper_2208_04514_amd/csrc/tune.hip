@@ -89,7 +89,7 @@ dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, u
   }
   cur.timing = 2;
   Tuner t{ctx, g, sources, 0};
-  const int ks = std::min<int>(k, 8);
+  const int ks = std::min<int>(k, 32);
   const int kb = std::min<int>(k, 4096);
   const size_t cap = (size_t)((what & 2) ? std::max(ks, kb) : ks) * g->n;
   t.elems = cap;

@@ -37,6 +37,7 @@ EXPORTED = (
     "dawn_graph_release", "dawn_graph_get_info", "dawn_get_params", "dawn_set_params",
     "dawn_sssp", "dawn_mssp", "dawn_apsp_wcc", "dawn_autotune", "dawn_serve_submit",
     "dawn_serve_poll", "dawn_serve_wait", "dawn_mssp_device", "dawn_sssp_noalloc",
+    "dawn_graph_set_weights", "dawn_sssp_weighted",
 )
 
 
@@ -140,6 +141,8 @@ def load(path: str | None = None):
         "dawn_serve_wait": [V, U64, I32, ctypes.POINTER(QueryStats)],
         "dawn_mssp_device": [V, I32, V, I32, V, V, V],
         "dawn_sssp_noalloc": [V, I32, I32, V, V, ctypes.POINTER(RunStats)],
+        "dawn_graph_set_weights": [V, I32, V],
+        "dawn_sssp_weighted": [V, I32, I32, V, U32, ctypes.POINTER(RunStats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -266,6 +269,28 @@ def dawn_graph_upload(ctx, row_ptr, col, flags: int = 0) -> int:
                                     flags, ctypes.byref(g)))
     _GRAPH_N[(_ctx_key(ctx), g.value)] = n
     return g.value
+
+
+def dawn_graph_set_weights(ctx, graph: int, weights) -> None:
+    """Attach int32 weights (one per CSR entry, >= 0) to a resident graph."""
+    w = _host_i32(weights).ravel()
+    m = dawn_graph_get_info(ctx, graph)["m"]
+    if w.size != m:
+        raise ValueError(f"{w.size} weights for a graph of {m} edges")
+    _check(load().dawn_graph_set_weights(ctx, graph, w.ctypes.data_as(ctypes.c_void_p)
+                                         if w.size else None))
+
+
+def dawn_sssp_weighted(ctx, graph: int, source: int, out=None):
+    """Weighted distances from `source` ((min, +) level loop).  `out`: numpy
+    int32[n] or torch int32 CUDA tensor.  Returns ``(out, stats)``."""
+    n = _graph_n(ctx, graph)
+    if out is None:
+        out = np.empty(n, dtype=np.int32)
+    ptr, flags, _keep = _out_ptr(ctx, out, (n,))
+    st = RunStats()
+    _check(load().dawn_sssp_weighted(ctx, graph, int(source), ptr, flags, ctypes.byref(st)))
+    return out, st.as_dict()
 
 
 def dawn_graph_release(ctx, graph: int) -> None:
