@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # cache (paper_2208_04514_amd/tuned_params.json, written by dawn_autotune on
 # 32 other sources of the same graph; --autotune searches again live).
 PLAIN_KNOB_NAMES = ("driver", "graph_levels", "big_degree", "alpha", "beta", "block",
-                    "blocks_per_cu", "pull_lane_edges")
+                    "blocks_per_cu", "pull_lane_edges", "small_frontier_edges")
 BATCH_KNOB_NAMES = ("batch_alpha", "batch_big_degree", "batch_wide_scan", "batch_sparse_words")
 
 # Sources that define the level-step kernel: the HBM counter record under

@@ -124,6 +124,10 @@ typedef struct dawn_params {
                                  which the whole wave scans the list (1..512; default 48) */
   int32_t batch_sparse_words; /* batched push: a frontier node with at most this many nonzero
                                  64-lane words goes one edge per lane (1..4; default 4) */
+  int32_t small_frontier_edges; /* single source, drivers 2-4: a push level whose frontier has
+                                 at most this many out-edges runs on one workgroup, which also
+                                 runs the small push levels after it in the same launch
+                                 (default 8192; -1: never) */
 } dawn_params;
 
 typedef struct dawn_graph_info {

@@ -91,6 +91,7 @@ struct LevelState {
   long long mu;               // out-degree sum of the still-unvisited nodes
   int last_nonempty;          // last level that found a node
   int push_levels, pull_levels;
+  int launches;               // level launches that ran at least one level
   unsigned prev_nf;           // nodes found by the level before the last
   u64 edges_total;
   u64 source_edges;
@@ -138,6 +139,9 @@ struct SsspArgs {
   int32_t lrec;
   int32_t lds_words;          // pull levels copy the visited bitmap (this many words,
                               //   = nw) into LDS; 0 = read it from global memory
+  int32_t small_edges;        // a push level whose frontier has at most this many out-edges
+                              //   runs on one workgroup, with the small levels after it in
+                              //   the same launch (0: never)
   unsigned long long* clk;    // timing mode: this launch's kClkStripes lines; in line s,
                               //   [0] the earliest start and [1] the latest end (GPU wall
                               //   clock) of the workgroups b with b % kClkStripes = s;

@@ -246,10 +246,11 @@ __device__ __forceinline__ void visit4(const SsspArgs& a, int L, u64* vis, const
 }
 
 // pre: the sub-queue offsets of level L-1 in LDS; `nch` its chunk count, or
-// ~0u to have them read here.
+// ~0u to have them read here.  The level's work is dealt over `nblk`
+// workgroups, this one being `bid` (the grid, or one workgroup alone).
 template <int BLOCK>
 __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQueue& q,
-                          unsigned* pre, unsigned nch) {
+                          unsigned* pre, unsigned nch, unsigned bid, unsigned nblk) {
   const LevelSlot* in = &a.ctrl->slot[(L - 1) % 3];
   if (nch == ~0u) {
     stripe_prefix(in, pre);
@@ -262,12 +263,12 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
   // iteration (one edge of each per thread)
   const int32_t* cu = chunk_u(a, L - 1);
   const int32_t* ck = chunk_k(a, L - 1);
-  for (unsigned g = blockIdx.x; g < nchunks; g += 4 * gridDim.x) {
+  for (unsigned g = bid; g < nchunks; g += 4 * nblk) {
     int v[4];
     bool has[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const unsigned gi = g + (unsigned)i * gridDim.x;
+      const unsigned gi = g + (unsigned)i * nblk;
       has[i] = false;
       v[i] = 0;
       if (gi < nchunks) {
@@ -285,8 +286,8 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
   // small-degree nodes: 64 per wave, union of their rows walked 64 edges a step
   const int lane = lane_id();
   const int wpb = BLOCK / kWave;
-  const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
-  const unsigned nwaves = gridDim.x * wpb;
+  const unsigned gw = bid * wpb + threadIdx.x / kWave;
+  const unsigned nwaves = nblk * wpb;
   const int32_t* q_in = small_q(a, L - 1);
   for (unsigned base = gw * kWave; base < nsmall; base += nwaves * kWave) {
     const unsigned i = base + lane;
@@ -515,6 +516,7 @@ __device__ void seed(const SsspArgs& a, int s) {
   st.last_nonempty = 0;
   st.push_levels = 0;
   st.pull_levels = 0;
+  st.launches = 0;
   st.prev_nf = 0;
   st.edges_total = 0;
   st.source_edges = 0;
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
 
   LevelState st;
   st.level = 0; st.cur = 0; st.pull = 0; st.done = 0; st.mu = a.m; st.last_nonempty = 0;
-  st.push_levels = 0; st.pull_levels = 0; st.prev_nf = 0; st.edges_total = 0;
+  st.push_levels = 0; st.pull_levels = 0; st.launches = 0; st.prev_nf = 0; st.edges_total = 0;
   st.source_edges = 0; st.reached = 0;
   Counters c{0, 0, 0};
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
       pull_step<BLOCK>(a, L, vcur, vnext, c, q, ps);
       st.cur ^= 1;
     } else {
-      push_step<BLOCK>(a, L, vcur, c, q, pre, ~0u);
+      push_step<BLOCK>(a, L, vcur, c, q, pre, ~0u, blockIdx.x, gridDim.x);
     }
     finish_level<BLOCK>(a, L, c, q);
     if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
@@ -754,6 +756,50 @@ __global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0, int32_t* dist, i
 // decide launch, no fences: the kernel boundary orders the two launches).
 // Workgroup 0 stores the new state in st[p].  Once the loop is done, later
 // launches only carry the final state forward.
+// The first wave of a workgroup reads the level state of the last launch
+// and, in the same round trip, the counters of all three slots (lane 16 s + i:
+// stripe i of slot s; lanes 48..50 the chunk counts), keeps the slot of level
+// `level` and reduces it: the sub-queue offsets and chunk count of that
+// level's frontier go to LDS (pre, *nchunks).  Returns the slot's sums in
+// lane 0.
+__device__ __forceinline__ SlotSum read_level_slot(const SsspArgs& a, int level, unsigned* pre,
+                                                   unsigned* nchunks) {
+  const int lane = threadIdx.x;
+  unsigned nf = 0, sc = 0, bc = 0;
+  u64 mf = 0, ed = 0;
+  if (lane < 3 * kStripes) {
+    const SlotStripe& sp = a.ctrl->slot[lane / kStripes].s[lane % kStripes];
+    nf = ld_relaxed(&sp.nf);
+    sc = ld_relaxed(&sp.small_count);
+    mf = ld_relaxed(&sp.mf);
+    ed = ld_relaxed(&sp.edges);
+  } else if (lane < 3 * kStripes + 3) {
+    bc = ld_relaxed(&a.ctrl->slot[lane - 3 * kStripes].big_chunks);
+  }
+  const int sel = level % 3;
+  const bool mine = lane < 3 * kStripes && lane / kStripes == sel;
+  if (!mine) {
+    nf = sc = 0;
+    mf = ed = 0;
+  }
+  const int sc_incl = wave_incl_scan((int)sc);
+  if (mine) pre[lane % kStripes] = (unsigned)(sc_incl - (int)sc);
+  const unsigned nsmall = (unsigned)__shfl(sc_incl, kWave - 1, kWave);
+  const SlotSum sum{wave_sum(nf), wave_sum(mf), wave_sum(ed)};
+  const unsigned nch = (unsigned)__shfl((int)bc, 3 * kStripes + sel, kWave);
+  if (lane == 0) {
+    pre[kStripes] = nsmall;
+    *nchunks = nch;
+  }
+  return sum;
+}
+
+// A push level whose frontier has at most a.small_edges out-edges is run by
+// workgroup 0 alone.
+__device__ __forceinline__ bool small_push(const SsspArgs& a, const LevelState& st, const SlotSum& sum) {
+  return a.small_edges > 0 && !st.done && !st.pull && sum.mf <= (u64)a.small_edges;
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   SsspArgs a = a0;
@@ -762,83 +808,99 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   __shared__ unsigned pre[kStripes + 1];
   __shared__ PullScratch ps[BLOCK / kWave];
   __shared__ LevelState sst;
-  __shared__ int idle;
+  __shared__ int idle, small;
   __shared__ int32_t big_v[BLOCK], big_c[BLOCK];
   __shared__ unsigned big_n, nchunks;
-  // The first wave reads the state and, in the same round trip, the counters
-  // of all three slots (lane 16 s + i: stripe i of slot s; lanes 48..50 the
-  // chunk counts), keeps the slot of the previous level and reduces it: the
-  // push step finds its sub-queue offsets and chunk count in LDS.
   if (threadIdx.x < kWave) {
-    const int lane = threadIdx.x;
     const LevelState st0 = a.ctrl->st[parity ^ 1];
-    unsigned nf = 0, sc = 0, bc = 0;
-    u64 mf = 0, ed = 0;
-    if (lane < 3 * kStripes) {
-      const SlotStripe& sp = a.ctrl->slot[lane / kStripes].s[lane % kStripes];
-      nf = sp.nf;
-      sc = sp.small_count;
-      mf = sp.mf;
-      ed = sp.edges;
-    } else if (lane < 3 * kStripes + 3) {
-      bc = a.ctrl->slot[lane - 3 * kStripes].big_chunks;
-    }
-    const int sel = st0.level % 3;
-    const bool mine = lane < 3 * kStripes && lane / kStripes == sel;
-    if (!mine) {
-      nf = sc = 0;
-      mf = ed = 0;
-    }
-    const int sc_incl = wave_incl_scan((int)sc);
-    if (mine) pre[lane % kStripes] = (unsigned)(sc_incl - (int)sc);
-    const unsigned nsmall = (unsigned)__shfl(sc_incl, kWave - 1, kWave);
-    const SlotSum sum{wave_sum(nf), wave_sum(mf), wave_sum(ed)};
-    const unsigned nch = (unsigned)__shfl((int)bc, 3 * kStripes + sel, kWave);
-    if (lane == 0) {
-      pre[kStripes] = nsmall;
-      nchunks = nch;
+    const SlotSum sum = read_level_slot(a, st0.level, pre, &nchunks);
+    if (threadIdx.x == 0) {
       big_n = 0;
       LevelState st = st0;
+      int sm = 0;
       if (!st.done) {
         decide(a, st, sum, blockIdx.x == 0);
+        sm = small_push(a, st, sum) ? 1 : 0;
         // a push level with nothing for this workgroup lets it leave at once
         const unsigned first_small = blockIdx.x * (BLOCK / kWave) * kWave;
-        idle = !st.done && !st.pull && first_small >= nsmall && blockIdx.x >= nch;
+        idle = !st.done && !st.pull && first_small >= pre[kStripes] && blockIdx.x >= nchunks;
+        if (sm) idle = blockIdx.x != 0;
       } else {
         idle = 1;
       }
+      small = sm;
       sst = st;
     }
   }
   __syncthreads();
-  const LevelState st = sst;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  LevelState st = sst;
+  const bool one_group = small != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !one_group) {
     LevelState out = st;
     if (!st.done && st.pull) out.cur ^= 1;
+    if (!st.done) out.launches += 1;
     a.ctrl->st[parity] = out;
   }
   if (st.done) return;
-  const int L = st.level;
-  if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
+  const int L0 = st.level;
+  if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L0 + 1) % 3], threadIdx.x, BLOCK);
   if (idle) return;
   WaveQueue q{qbuf[threadIdx.x / kWave], 0, big_v, big_c, &big_n};
   Counters c{0, 0, 0};
   u64* vcur = st.cur ? a.vis1 : a.vis0;
-  if (st.pull) {
-    u64* vnext = st.cur ? a.vis0 : a.vis1;
-    const u64* look = vcur;
-    if (a.lds_words) {
-      // every in-edge check of the sweep reads the bitmap: copy it to LDS
-      extern __shared__ u64 lds_vis[];
-      for (int i = threadIdx.x; i < a.lds_words; i += BLOCK) lds_vis[i] = vcur[i];
-      __syncthreads();
-      look = lds_vis;
+  if (!one_group) {
+    if (st.pull) {
+      u64* vnext = st.cur ? a.vis0 : a.vis1;
+      const u64* look = vcur;
+      if (a.lds_words) {
+        // every in-edge check of the sweep reads the bitmap: copy it to LDS
+        extern __shared__ u64 lds_vis[];
+        for (int i = threadIdx.x; i < a.lds_words; i += BLOCK) lds_vis[i] = vcur[i];
+        __syncthreads();
+        look = lds_vis;
+      }
+      pull_step<BLOCK>(a, L0, look, vnext, c, q, ps);
+    } else {
+      push_step<BLOCK>(a, L0, vcur, c, q, pre, nchunks, blockIdx.x, gridDim.x);
     }
-    pull_step<BLOCK>(a, L, look, vnext, c, q, ps);
-  } else {
-    push_step<BLOCK>(a, L, vcur, c, q, pre, nchunks);
+    finish_level<BLOCK>(a, L0, c, q);
+    return;
   }
-  finish_level<BLOCK>(a, L, c, q);
+  // Small push levels: this workgroup alone runs them one after another in
+  // this launch while each frontier's out-edges stay within a.small_edges,
+  // then hands over (the state of the last level it ran, whose counters the
+  // next launch folds and decides from as usual).  It is the only writer of
+  // every slot and queue meanwhile, so its barriers order the levels.
+  st.launches += 1;
+  for (;;) {
+    const int L = st.level;
+    push_step<BLOCK>(a, L, vcur, c, q, pre, nchunks, 0, 1);
+    finish_level<BLOCK>(a, L, c, q);
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+      const SlotSum sum = read_level_slot(a, L, pre, &nchunks);
+      if (threadIdx.x == 0) {
+        LevelState nx = st;
+        decide(a, nx, sum, true);
+        if (small_push(a, nx, sum)) {
+          small = 1;
+          sst = nx;
+        } else {
+          // done: the final state; otherwise the last level run, so that the
+          // next launch folds its counters and takes the same decision
+          small = 0;
+          a.ctrl->st[parity] = nx.done ? nx : st;
+        }
+      }
+    }
+    __syncthreads();
+    if (!small) return;
+    st = sst;
+    // the slot of the level after next is free again (its counters, two
+    // levels back, were folded); big_n was reset by the last flush
+    zero_slot(&a.ctrl->slot[(st.level + 1) % 3], threadIdx.x, BLOCK);
+    __syncthreads();
+  }
 }
 
 // In timing mode (a.clk set) every workgroup stamps its start and end with
@@ -957,6 +1019,7 @@ static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
   a.beta = p.beta;
   a.big_degree = std::max(p.big_degree, 64);
   a.lane_edges = std::max(p.pull_lane_edges, 1);
+  a.small_edges = std::max(p.small_frontier_edges, 0);
   a.level_nf = w->level_nf;
   a.level_dir = w->level_dir;
   a.lrec = w->lrec;
@@ -1093,8 +1156,8 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
                               hipMemcpyDeviceToHost, w->stream));
       DAWN_HIP(hipStreamSynchronize(w->stream));
       if (w->h_ctrl->st[1].done) {
-        // launches this traversal needed: levels 1 .. last_nonempty + 1, then the end
-        const int need = w->h_ctrl->st[1].last_nonempty + 2;
+        // launches this traversal needed: those that ran levels, then the end
+        const int need = w->h_ctrl->st[1].launches + 1;
         g->launch_hint.store(std::max(need, hint - 1), std::memory_order_relaxed);
         *final_parity = 1;
         return DAWN_OK;
@@ -1404,7 +1467,7 @@ static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, S
     DAWN_HIP(hipMemcpyAsync(fin, &a.ctrl->st[1], sizeof(LevelState), hipMemcpyDeviceToHost, s));
     DAWN_HIP(hipStreamSynchronize(s));
     if (fin->done) {
-      g->launch_hint.store(std::max(fin->last_nonempty + 2, hint - 1), std::memory_order_relaxed);
+      g->launch_hint.store(std::max(fin->launches + 1, hint - 1), std::memory_order_relaxed);
       return DAWN_OK;
     }
     batch = gl;
@@ -1453,6 +1516,7 @@ dawn_status sssp_run_noalloc(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_
   a.beta = p.beta;
   a.big_degree = std::max(p.big_degree, 64);
   a.lane_edges = std::max(p.pull_lane_edges, 1);
+  a.small_edges = std::max(p.small_frontier_edges, 0);
   LevelState fin;
   memset(&fin, 0, sizeof(fin));
   int launches = 0;

@@ -40,7 +40,7 @@ int main(void) {
          offsetof(dawn_run_stats, kernel_clock_ms));
   printf("%zu %zu %zu\n",
          sizeof(dawn_params), offsetof(dawn_params, timing),
-         offsetof(dawn_params, batch_sparse_words));
+         offsetof(dawn_params, small_frontier_edges));
   printf("%zu %zu %zu %zu\n", sizeof(dawn_graph_info), offsetof(dawn_graph_info, device_bytes),
          sizeof(dawn_query_stats), offsetof(dawn_query_stats, batch_peak));
   return 0;
@@ -56,7 +56,7 @@ int main(void) {
     got = list(map(int, out))
     want = [ctypes.sizeof(D.RunStats), D.RunStats.frontier_cap.offset,
             D.RunStats.kernel_clock_ms.offset, ctypes.sizeof(D.Params), D.Params.timing.offset,
-            D.Params.batch_sparse_words.offset,
+            D.Params.small_frontier_edges.offset,
             ctypes.sizeof(D.GraphInfo), D.GraphInfo.device_bytes.offset,
             ctypes.sizeof(D.QueryStats), D.QueryStats.batch_peak.offset]
     assert got == want

@@ -53,6 +53,12 @@ VARIANTS = [
     dict(driver=1, direction=1, big_degree=64), dict(driver=2, direction=1, big_degree=64, block=1024),
     dict(driver=1, direction=2, pull_lane_edges=1), dict(driver=1, direction=3, alpha=1e6, beta=1e-3),
     dict(driver=1, direction=3, blocks_per_cu=1), dict(driver=1, direction=3, small_n=1 << 30),
+    # one workgroup runs the small push levels: never, always, and always with
+    # the graph driver and the smallest workgroup
+    dict(driver=3, direction=3, small_frontier_edges=-1),
+    dict(driver=2, direction=1, small_frontier_edges=1 << 30),
+    dict(driver=4, direction=3, graph_levels=6, small_frontier_edges=1 << 30, block=256),
+    dict(driver=3, direction=3, graph_levels=4, small_frontier_edges=64),
 ]
 
 
