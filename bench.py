@@ -132,9 +132,10 @@ def run_plain(D, ctx, h, src, out, steps, warmup):
 
 
 def level_kernel_timing(D, ctx, h, src, out):
-    """Per-launch time of the level-step kernel, measured with HIP events that
-    bracket each launch on the stream it runs on (library timing mode 1, which
-    issues the same level launches one per host check).  The same pass also
+    """Per-launch time of the level-step kernel, measured with HIP events
+    attached to each launch on the stream it runs on (library timing mode 1,
+    which issues the same level launches one per host check; the events take
+    the dispatch's own begin and end timestamps).  The same pass also
     sums each launch's own duration by the GPU's wall clock (first workgroup
     start to last workgroup end, no dispatch gap).
     Returns (total event ms, launches, levels per source, total clock ms)."""
@@ -661,6 +662,9 @@ def main():
                     help="search the knobs live (and record them) instead of loading the cache")
     ap.add_argument("--tune-file", default=None,
                     help="tuning cache to read and write (default: the package's tuned_params.json)")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="search the knobs of the R-MAT 20 and R-MAT 18 workloads, record them in "
+                         "the tuning cache, and stop")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the level-kernel timing pass (for rocprofv3)")
     ap.add_argument("--params", default="", help="JSON knobs for --roofline-only")
@@ -681,6 +685,18 @@ def main():
     import graphgen as gg
     from paper_2208_04514_amd import dawn as D
 
+    if args.tune_only:
+        ctx = D.dawn_create(0, 0)
+        for name, width, names, what, seed, k in (
+                ("rmat20", 1, PLAIN_KNOB_NAMES, 1, 9001, 32),
+                ("rmat18", 4096, PLAIN_KNOB_NAMES + BATCH_KNOB_NAMES, 3, 9002, 4096)):
+            g, _ = gg.load_config(name)
+            h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+            knobs, _, s = cached_knobs(D, ctx, h, g, width, names, what, seed, k, True,
+                                       args.tune_file)
+            D.dawn_graph_release(ctx, h)
+            _log(f"[tune] {name} width {width}: {json.dumps(knobs)} ({s:.1f} s)")
+        return
     if args.roofline_only:
         ctx = D.dawn_create(0, 0)
         roofline_only(D, ctx, args.params)

@@ -89,7 +89,8 @@ typedef struct dawn_run_stats {
   int32_t frontier_cap;
   /* dawn_sssp with timing 1 only (output): the level launches' own durations,
    * each from its earliest workgroup start to its latest workgroup end by the
-   * GPU's wall clock, summed (kernel_ms adds each launch's dispatch gap) */
+   * GPU's wall clock, summed (kernel_ms also counts each dispatch's set-up
+   * and end-of-kernel cache write-back) */
   double kernel_clock_ms;
 } dawn_run_stats;
 
@@ -115,7 +116,8 @@ typedef struct dawn_params {
                                  nonzero 64-lane words) * batch_alpha >= n x words, else push */
   int32_t batch_lanes;        /* batched: sources per launch (64..4096, multiple of 64) */
   int32_t timing;             /* 1: kernel_ms/launches of dawn_sssp cover only the level-step
-                                 kernels, each bracketed by HIP events (driver 2 only);
+                                 kernels, each timed by HIP events attached to its dispatch
+                                 (driver 2 only);
                                  2 (default): every kernel of the call */
   int32_t batch_big_degree;   /* batched push: out-degree from which a frontier node's
                                  out-list is cut into 64-edge chunks spread over the grid
@@ -125,9 +127,10 @@ typedef struct dawn_params {
   int32_t batch_sparse_words; /* batched push: a frontier node with at most this many nonzero
                                  64-lane words goes one edge per lane (1..4; default 4) */
   int32_t small_frontier_edges; /* single source, drivers 2-4: a push level whose frontier has
-                                 at most this many out-edges runs on one workgroup, which also
-                                 runs the small push levels after it in the same launch
-                                 (default 8192; -1: never) */
+                                 at most this many out-edges (and at most 2 x block) runs on
+                                 one workgroup, which also runs the small push levels after it
+                                 in the same launch with their frontiers in LDS
+                                 (default 2048; -1: never) */
 } dawn_params;
 
 typedef struct dawn_graph_info {

@@ -101,6 +101,11 @@ struct LevelState {
 // st[p]: the state after the level run by the last launch of parity p (the
 // per-level kernels alternate parities, so a launch reads st[p ^ 1] and
 // writes st[p] without racing its own readers).
+// One stripe of the arrival count of a one-workgroup launch.
+struct alignas(kLine) ArriveStripe {
+  unsigned n;
+};
+
 struct SsspCtrl {
   GridBarrier bar;
   int32_t* dist;              // output rows and source: written by the host (one copy)
@@ -108,6 +113,11 @@ struct SsspCtrl {
   int pad;                    //   graphs do not depend on them
   LevelSlot slot[3];
   LevelState st[2];
+  // a launch that runs small levels on workgroup 0: every other workgroup
+  // adds one here (stripe blockIdx % kStripes) once it has read the counters
+  // it decides from; workgroup 0 waits for all of them before it writes any
+  // slot, then zeroes the count
+  ArriveStripe arrive[kStripes];
 };
 
 // Everything a single-source traversal kernel needs (passed by value).

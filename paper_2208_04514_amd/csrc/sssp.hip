@@ -46,6 +46,8 @@
 #include <algorithm>
 #include <functional>
 
+#include <hip/hip_ext.h>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -531,8 +533,10 @@ __device__ __forceinline__ void init_fill(const SsspArgs& a, int s) {
   for (unsigned i = tid; i < (unsigned)a.n; i += nt) a.dist[i] = (int)i == s ? 0 : -1;
   for (unsigned w = tid; w < (unsigned)a.nw; w += nt)
     a.vis0[w] = (int)w == (s >> 6) ? (1ull << (s & 63)) : 0ull;
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
     for (int i = 0; i < 3; ++i) zero_slot(&a.ctrl->slot[i], threadIdx.x, blockDim.x);
+    if (threadIdx.x < kStripes) a.ctrl->arrive[threadIdx.x].n = 0;
+  }
 }
 
 // ------------------------------------------------------- persistent driver --
@@ -794,10 +798,247 @@ __device__ __forceinline__ SlotSum read_level_slot(const SsspArgs& a, int level,
   return sum;
 }
 
-// A push level whose frontier has at most a.small_edges out-edges is run by
-// workgroup 0 alone.
+// Nodes each of the two LDS frontier lists of the one-workgroup loop holds:
+// the workgroup's queue staging area, split in two.
+template <int BLOCK>
+__device__ constexpr int small_cap() {
+  return BLOCK / kWave * kWaveBuf / 2;
+}
+
+// A push level whose frontier has at most min(a.small_edges, small_cap)
+// out-edges is run by workgroup 0 alone.  The bound also bounds the nodes the
+// level can find (each is the target of one of those edges), so they fit in
+// one LDS list.
+template <int BLOCK>
 __device__ __forceinline__ bool small_push(const SsspArgs& a, const LevelState& st, const SlotSum& sum) {
-  return a.small_edges > 0 && !st.done && !st.pull && sum.mf <= (u64)a.small_edges;
+  return a.small_edges > 0 && !st.done && !st.pull &&
+         sum.mf <= (u64)min(a.small_edges, small_cap<BLOCK>());
+}
+
+// LDS of the one-workgroup loop besides its two lists.
+struct SmallShared {
+  int arrived;         // every other workgroup of the launch has read its counters
+  unsigned n_next;     // nodes listed for the next level
+  unsigned n_small;    // hand-over: small-degree queue entries written
+  unsigned n_chunks;   // hand-over: big-degree chunks written
+  int go;              // 1 while the next level is small as well
+  unsigned nf;         // counters of the level just run
+  u64 mf, edges;
+  LevelState st;
+};
+
+// Workgroup 0 of a one-workgroup launch: wait (bounded) until every other
+// workgroup has counted itself in ctrl->arrive, then zero the count.  Every
+// thread calls it; sh.arrived = 0 if the wait timed out.
+template <int BLOCK>
+__device__ __forceinline__ void wait_arrivals(const SsspArgs& a, SmallShared& sh) {
+  if (threadIdx.x == 0) {
+    const unsigned want = gridDim.x - 1;
+    const unsigned long long t0 = wall_clock64();
+    int ok = 1;
+    for (;;) {
+      unsigned tot = 0;
+#pragma unroll
+      for (int i = 0; i < kStripes; ++i) tot += ld_relaxed(&a.ctrl->arrive[i].n);
+      if (tot >= want) break;
+      if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    for (int i = 0; i < kStripes; ++i) a.ctrl->arrive[i].n = 0;
+    sh.arrived = ok;
+  }
+  __syncthreads();
+}
+
+// Small push levels, one after another, by this workgroup alone (the rest of
+// the grid has left).  The frontier of level st.level - 1 is read from its
+// global queues once; after that each level's frontier is an LDS list: the
+// level walks the union of its nodes' rows, claims targets with the same
+// bitmap atomics as the grid-wide step, writes their distance and lists them
+// (degree > 0) in the other list.  Counters are summed in the workgroup and
+// the direction rule is applied right here.  No level's frontier has more
+// out-edges than a list holds (small_push), so a list never overflows.  When
+// the next level is no longer small, the last level's nodes and counters are
+// written to its global queue and slot as the grid-wide step leaves them (one
+// sub-queue, one stripe) and the state stays at that level, so the next
+// launch folds its counters and takes the same decision; a finished traversal
+// stores its final state instead.
+template <int BLOCK>
+__device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, int parity, u64* vis,
+                             const unsigned* pre, unsigned nchunks, int32_t* lists,
+                             SmallShared& sh) {
+  constexpr int cap = small_cap<BLOCK>();
+  const int lane = lane_id();
+  int32_t* cur = lists;
+  int32_t* nxt = lists + cap;
+  // the frontier from the global queues: the sub-queue entries, then each
+  // big-degree node once (its chunk 0)
+  {
+    const int L = st.level;
+    const unsigned nsmall = pre[kStripes];
+    const int32_t* q_in = small_q(a, L - 1);
+    for (unsigned i = threadIdx.x; i < nsmall; i += BLOCK) {
+      const int s = stripe_of(pre, i);
+      if (i < (unsigned)cap) cur[i] = q_in[(size_t)s * (size_t)a.n + (i - pre[s])];
+    }
+    if (threadIdx.x == 0) sh.n_next = nsmall;
+    __syncthreads();
+    const int32_t* cu = chunk_u(a, L - 1);
+    const int32_t* ck = chunk_k(a, L - 1);
+    for (unsigned g = threadIdx.x; g < nchunks; g += BLOCK) {
+      const bool first = ck[g] == 0;
+      const int pos = first ? (int)atomicAdd(&sh.n_next, 1u) : cap;
+      if (pos < cap) cur[pos] = cu[g];
+    }
+    __syncthreads();
+  }
+  unsigned ncur = min(sh.n_next, (unsigned)cap);
+  for (;;) {
+    const int L = st.level;
+    __syncthreads();
+    if (threadIdx.x == 0) sh.n_next = 0;
+    __syncthreads();
+    unsigned nf = 0;
+    u64 mf = 0, edges = 0;
+    for (unsigned base = (threadIdx.x / kWave) * kWave; base < ncur; base += BLOCK) {
+      const unsigned i = base + lane;
+      int rs = 0, deg = 0;
+      if (i < ncur) {
+        const int u = cur[i];
+        rs = a.rp[u];
+        deg = a.rp[u + 1] - rs;
+      }
+      const int incl = wave_incl_scan(deg);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      for (int eb = 0; eb < total; eb += 4 * kWave) {
+        int v[4];
+        bool has[4];
+        u64 w[4], bit[4], old[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = eb + k * kWave + lane;
+          has[k] = x < total;
+          const int j = wave_owner(incl, has[k] ? x : total - 1);
+          const int inc_j = __shfl(incl, j, kWave);
+          const int deg_j = __shfl(deg, j, kWave);
+          const int rs_j = __shfl(rs, j, kWave);
+          v[k] = has[k] ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          bit[k] = 1ull << (v[k] & 63);
+          w[k] = has[k] ? vis[v[k] >> 6] : bit[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) old[k] = (w[k] & bit[k]) ? bit[k] : atom_or(&vis[v[k] >> 6], bit[k]);
+        int dv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (has[k]) edges += 1;
+          const bool claim = !(old[k] & bit[k]);
+          dv[k] = claim ? a.rp[v[k] + 1] - a.rp[v[k]] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (dv[k] >= 0) {
+            a.dist[v[k]] = L;
+            nf += 1;
+            mf += (u64)dv[k];
+          }
+          const u64 mk = __ballot(dv[k] > 0);
+          if (mk) {
+            const int lead = __ffsll((unsigned long long)mk) - 1;
+            unsigned b = 0;
+            if (lane == lead) b = atomicAdd(&sh.n_next, (unsigned)__popcll(mk));
+            b = (unsigned)__shfl((int)b, lead, kWave);
+            const unsigned pos = b + (unsigned)__popcll(mk & lanes_below());
+            if (dv[k] > 0 && pos < (unsigned)cap) nxt[pos] = v[k];
+          }
+        }
+      }
+    }
+    block_sum3<BLOCK>(nf, mf, edges);
+    if (threadIdx.x == 0) {
+      LevelState nx = st;
+      const SlotSum sum{nf, mf, edges};
+      decide(a, nx, sum, true);
+      sh.nf = nf;
+      sh.mf = mf;
+      sh.edges = edges;
+      if (small_push<BLOCK>(a, nx, sum)) {
+        sh.go = 1;
+        sh.st = nx;
+      } else {
+        sh.go = 0;
+        sh.st = nx.done ? nx : st;
+      }
+    }
+    __syncthreads();
+    if (!sh.go) break;
+    st = sh.st;
+    ncur = min(sh.n_next, (unsigned)cap);
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  // the other workgroups decided from the slot of the level before this
+  // launch's first one, which the hand-over below may overwrite
+  wait_arrivals<BLOCK>(a, sh);
+  LevelState fin = sh.st;
+  if (!sh.arrived) fin.done = 2;
+  if (fin.done) {
+    if (threadIdx.x == 0) a.ctrl->st[parity] = fin;
+    return;
+  }
+  // hand over level L = fin.level: its nodes to its queue (sub-queue 0) and
+  // chunk lists, its counters to stripe 0 of its slot (the other stripes
+  // zero), and the slot of level L + 1 zeroed for the launch that runs it
+  const int L = fin.level;
+  const unsigned nl = min(sh.n_next, (unsigned)cap);
+  if (threadIdx.x == 0) {
+    sh.n_small = 0;
+    sh.n_chunks = 0;
+  }
+  {
+    // stripes 1.. of level L's slot and all of level L + 1's; stripe 0 and
+    // the chunk count of level L are written once below
+    LevelSlot* sl = &a.ctrl->slot[L % 3];
+    unsigned* w = (unsigned*)&sl->s[1];
+    const int words = (int)((sizeof(SlotStripe) * (kStripes - 1)) / 4);
+    for (int i = threadIdx.x; i < words; i += BLOCK) w[i] = 0;
+    zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
+  }
+  __syncthreads();
+  int32_t* qo = small_q(a, L);
+  int32_t* cuo = chunk_u(a, L);
+  int32_t* cko = chunk_k(a, L);
+  for (unsigned i = threadIdx.x; i < nl; i += BLOCK) {
+    const int v = nxt[i];
+    const int d = a.rp[v + 1] - a.rp[v];
+    if (d < a.big_degree) {
+      qo[atomicAdd(&sh.n_small, 1u)] = v;
+    } else {
+      const int nch = (d + BLOCK - 1) / BLOCK;
+      const unsigned b = atomicAdd(&sh.n_chunks, (unsigned)nch);
+      for (int k = 0; k < nch; ++k) {
+        cuo[b + k] = v;
+        cko[b + k] = k;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SlotStripe& s0 = a.ctrl->slot[L % 3].s[0];
+    s0.nf = sh.nf;
+    s0.small_count = sh.n_small;
+    s0.mf = sh.mf;
+    s0.edges = sh.edges;
+    a.ctrl->slot[L % 3].big_chunks = sh.n_chunks;
+    a.ctrl->st[parity] = fin;
+  }
 }
 
 template <int BLOCK>
@@ -820,7 +1061,7 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
       int sm = 0;
       if (!st.done) {
         decide(a, st, sum, blockIdx.x == 0);
-        sm = small_push(a, st, sum) ? 1 : 0;
+        sm = small_push<BLOCK>(a, st, sum) ? 1 : 0;
         // a push level with nothing for this workgroup lets it leave at once
         const unsigned first_small = blockIdx.x * (BLOCK / kWave) * kWave;
         idle = !st.done && !st.pull && first_small >= pre[kStripes] && blockIdx.x >= nchunks;
@@ -835,6 +1076,11 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   __syncthreads();
   LevelState st = sst;
   const bool one_group = small != 0;
+  if (one_group && blockIdx.x != 0) {
+    // counted in: workgroup 0 may now overwrite the counters read above
+    if (threadIdx.x == 0) atom_add(&a.ctrl->arrive[blockIdx.x % kStripes].n, 1u);
+    return;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0 && !one_group) {
     LevelState out = st;
     if (!st.done && st.pull) out.cur ^= 1;
@@ -866,41 +1112,9 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
     finish_level<BLOCK>(a, L0, c, q);
     return;
   }
-  // Small push levels: this workgroup alone runs them one after another in
-  // this launch while each frontier's out-edges stay within a.small_edges,
-  // then hands over (the state of the last level it ran, whose counters the
-  // next launch folds and decides from as usual).  It is the only writer of
-  // every slot and queue meanwhile, so its barriers order the levels.
   st.launches += 1;
-  for (;;) {
-    const int L = st.level;
-    push_step<BLOCK>(a, L, vcur, c, q, pre, nchunks, 0, 1);
-    finish_level<BLOCK>(a, L, c, q);
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-      const SlotSum sum = read_level_slot(a, L, pre, &nchunks);
-      if (threadIdx.x == 0) {
-        LevelState nx = st;
-        decide(a, nx, sum, true);
-        if (small_push(a, nx, sum)) {
-          small = 1;
-          sst = nx;
-        } else {
-          // done: the final state; otherwise the last level run, so that the
-          // next launch folds its counters and takes the same decision
-          small = 0;
-          a.ctrl->st[parity] = nx.done ? nx : st;
-        }
-      }
-    }
-    __syncthreads();
-    if (!small) return;
-    st = sst;
-    // the slot of the level after next is free again (its counters, two
-    // levels back, were folded); big_n was reset by the last flush
-    zero_slot(&a.ctrl->slot[(st.level + 1) % 3], threadIdx.x, BLOCK);
-    __syncthreads();
-  }
+  __shared__ SmallShared sh;
+  small_levels<BLOCK>(a, st, parity, vcur, pre, nchunks, &qbuf[0][0], sh);
 }
 
 // In timing mode (a.clk set) every workgroup stamps its start and end with
@@ -1094,9 +1308,15 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       const int parity = (int)(it & 1);
       SsspArgs al = a;
       if (level_ms && it < w->clk_cap) al.clk = w->clk + (size_t)it * kClkStripes * kClkWords;
-      if (level_ms) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
-      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, al, parity);
-      if (level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+      if (level_ms) {
+        // events attached to the dispatch itself: their timestamps are the
+        // kernel's own begin and end, without the marker packets' dispatch gap
+        hipExtLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), (uint32_t)shmem,
+                              w->stream, w->ev0, w->ev1, 0, al, parity);
+      } else {
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, al,
+                           parity);
+      }
       DAWN_HIP(hipGetLastError());
       *launches += 1;
       ++level_launches;

@@ -288,3 +288,20 @@ def test_small_components_one_workgroup(ctx):
                 _check_row(g, b, got, st)
     finally:
         D.dawn_graph_release(ctx, h)
+
+
+def test_level_timing_mode(ctx, upload, restore):
+    """Timing mode 1 (driver 2): the level launches alone are timed by events
+    attached to their dispatches and by the kernel's own wall-clock stamps;
+    the row is unchanged, the clock sum sits inside the event sum."""
+    h, g, src = upload("rmat12")
+    restore(h, driver=2, timing=1)
+    for s in src[:4]:
+        got, st = D.dawn_sssp(ctx, h, int(s))
+        _check_row(g, s, got, st)
+        assert st["launches"] >= st["levels"] - 1
+        assert st["kernel_ms"] > 0 and st["kernel_clock_ms"] > 0
+        assert st["kernel_clock_ms"] <= st["kernel_ms"] * 1.1 + 0.005, st
+    restore(h, driver=3, timing=2)
+    _, st = D.dawn_sssp(ctx, h, int(src[0]))
+    assert st["kernel_clock_ms"] == 0.0
