@@ -127,10 +127,10 @@ typedef struct dawn_params {
   int32_t batch_sparse_words; /* batched push: a frontier node with at most this many nonzero
                                  64-lane words goes one edge per lane (1..4; default 4) */
   int32_t small_frontier_edges; /* single source, drivers 2-4: a push level whose frontier has
-                                 at most this many out-edges (and at most 2 x block) runs on
-                                 one workgroup, which also runs the small push levels after it
-                                 in the same launch with their frontiers in LDS
-                                 (default 2048; -1: never) */
+                                 at most this many out-edges (and at most `block`) runs on one
+                                 workgroup, which also runs the small push levels after it in
+                                 the same launch with their frontiers in LDS
+                                 (default 1024; -1: never) */
 } dawn_params;
 
 typedef struct dawn_graph_info {

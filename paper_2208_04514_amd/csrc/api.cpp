@@ -100,7 +100,7 @@ dawn_params default_params(const GraphRec& g) {
   p.batch_big_degree = 64;
   p.batch_wide_scan = 48;
   p.batch_sparse_words = 4;
-  p.small_frontier_edges = 2048;
+  p.small_frontier_edges = 1024;
   (void)g;
   return p;
 }

@@ -798,32 +798,34 @@ __device__ __forceinline__ SlotSum read_level_slot(const SsspArgs& a, int level,
   return sum;
 }
 
-// Nodes each of the two LDS frontier lists of the one-workgroup loop holds:
-// the workgroup's queue staging area, split in two.
+// Frontier nodes the one-workgroup loop holds: one per thread, as a pair
+// (row start, out-degree) in each of two LDS lists.
 template <int BLOCK>
 __device__ constexpr int small_cap() {
-  return BLOCK / kWave * kWaveBuf / 2;
+  return BLOCK;
 }
 
 // A push level whose frontier has at most min(a.small_edges, small_cap)
 // out-edges is run by workgroup 0 alone.  The bound also bounds the nodes the
 // level can find (each is the target of one of those edges), so they fit in
-// one LDS list.
+// one LDS list, and it gives every thread at most one edge.
 template <int BLOCK>
 __device__ __forceinline__ bool small_push(const SsspArgs& a, const LevelState& st, const SlotSum& sum) {
   return a.small_edges > 0 && !st.done && !st.pull &&
          sum.mf <= (u64)min(a.small_edges, small_cap<BLOCK>());
 }
 
-// LDS of the one-workgroup loop besides its two lists.
+// LDS of the one-workgroup loop besides its lists.
 struct SmallShared {
   int arrived;         // every other workgroup of the launch has read its counters
-  unsigned n_next;     // nodes listed for the next level
-  unsigned n_small;    // hand-over: small-degree queue entries written
-  unsigned n_chunks;   // hand-over: big-degree chunks written
   int go;              // 1 while the next level is small as well
-  unsigned nf;         // counters of the level just run
-  u64 mf, edges;
+  unsigned n_next;     // nodes listed for the next level
+  unsigned n_small;    // this level's small-degree queue entries
+  unsigned n_chunks;   // this level's big-degree chunks
+  unsigned nf;         // this level's counters
+  u64 mf;
+  int total;           // frontier edges of this level
+  int wsum[16];        // per-wave scan totals
   LevelState st;
 };
 
@@ -853,136 +855,167 @@ __device__ __forceinline__ void wait_arrivals(const SsspArgs& a, SmallShared& sh
   __syncthreads();
 }
 
+// Workgroup-wide inclusive scan of one int per thread; returns the thread's
+// prefix and leaves the total in sh.total.  Every thread calls it.
+template <int BLOCK>
+__device__ __forceinline__ int small_scan(int x, SmallShared& sh) {
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  int incl = wave_incl_scan(x);
+  if (lane == kWave - 1) sh.wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const int y = threadIdx.x < BLOCK / kWave ? sh.wsum[threadIdx.x] : 0;
+    const int ys = wave_incl_scan(y);
+    if (threadIdx.x < BLOCK / kWave) sh.wsum[threadIdx.x] = ys - y;
+    if (threadIdx.x == kWave - 1) sh.total = ys;
+  }
+  __syncthreads();
+  return incl + sh.wsum[wv];
+}
+
 // Small push levels, one after another, by this workgroup alone (the rest of
 // the grid has left).  The frontier of level st.level - 1 is read from its
-// global queues once; after that each level's frontier is an LDS list: the
-// level walks the union of its nodes' rows, claims targets with the same
-// bitmap atomics as the grid-wide step, writes their distance and lists them
-// (degree > 0) in the other list.  Counters are summed in the workgroup and
-// the direction rule is applied right here.  No level's frontier has more
-// out-edges than a list holds (small_push), so a list never overflows.  When
-// the next level is no longer small, the last level's nodes and counters are
-// written to its global queue and slot as the grid-wide step leaves them (one
-// sub-queue, one stripe) and the state stays at that level, so the next
-// launch folds its counters and takes the same decision; a finished traversal
-// stores its final state instead.
+// global queues once; after that each level's frontier is an LDS list of
+// (row start, out-degree) pairs.  A level scans the degrees, gives thread e
+// edge e of the union of the rows (at most one per thread), claims its target
+// with one bitmap atomic, writes the distance, loads the target's row bounds
+// and lists it for the next level; its queue entry goes straight to the
+// level's global queue (sub-queue 0, or the chunk list), positions counted in
+// LDS.  Counters are summed in LDS and the direction rule is applied right
+// here.  When the next level is no longer small, the last level's counters go
+// to its slot as the grid-wide step leaves them (one stripe) and the state
+// stays at that level, so the next launch folds its counters and takes the
+// same decision; a finished traversal stores its final state instead.
 template <int BLOCK>
-__device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, int parity, u64* vis,
-                             const unsigned* pre, unsigned nchunks, int32_t* lists,
-                             SmallShared& sh) {
+__device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, int parity,
+                                             u64* vis, const unsigned* pre, unsigned nchunks,
+                                             int32_t* lists, SmallShared& sh) {
   constexpr int cap = small_cap<BLOCK>();
-  const int lane = lane_id();
+  const int t = threadIdx.x, lane = lane_id();
+  // list b: row starts at lists[2 cap b ...], degrees (then their prefix
+  // sums) at lists[2 cap b + cap ...]
   int32_t* cur = lists;
-  int32_t* nxt = lists + cap;
+  int32_t* nxt = lists + 2 * cap;
   // the frontier from the global queues: the sub-queue entries, then each
-  // big-degree node once (its chunk 0)
+  // big-degree node once (its chunk 0); then the nodes' rows
   {
     const int L = st.level;
     const unsigned nsmall = pre[kStripes];
-    const int32_t* q_in = small_q(a, L - 1);
-    for (unsigned i = threadIdx.x; i < nsmall; i += BLOCK) {
-      const int s = stripe_of(pre, i);
-      if (i < (unsigned)cap) cur[i] = q_in[(size_t)s * (size_t)a.n + (i - pre[s])];
+    if ((unsigned)t < nsmall && t < cap) {
+      const int s = stripe_of(pre, (unsigned)t);
+      cur[t] = small_q(a, L - 1)[(size_t)s * (size_t)a.n + ((unsigned)t - pre[s])];
     }
-    if (threadIdx.x == 0) sh.n_next = nsmall;
+    if (t == 0) sh.n_next = nsmall;
     __syncthreads();
     const int32_t* cu = chunk_u(a, L - 1);
     const int32_t* ck = chunk_k(a, L - 1);
-    for (unsigned g = threadIdx.x; g < nchunks; g += BLOCK) {
-      const bool first = ck[g] == 0;
-      const int pos = first ? (int)atomicAdd(&sh.n_next, 1u) : cap;
-      if (pos < cap) cur[pos] = cu[g];
+    for (unsigned g = (unsigned)t; g < nchunks; g += BLOCK) {
+      if (ck[g] == 0) {
+        const unsigned pos = atomicAdd(&sh.n_next, 1u);
+        if (pos < (unsigned)cap) cur[pos] = cu[g];
+      }
     }
     __syncthreads();
+    const unsigned nin = min(sh.n_next, (unsigned)cap);
+    if ((unsigned)t < nin) {
+      const int u = cur[t];
+      const int rs = a.rp[u];
+      cur[t] = rs;
+      cur[cap + t] = a.rp[u + 1] - rs;
+    }
   }
   unsigned ncur = min(sh.n_next, (unsigned)cap);
   for (;;) {
     const int L = st.level;
     __syncthreads();
-    if (threadIdx.x == 0) sh.n_next = 0;
+    if (t == 0) {
+      sh.n_next = 0;
+      sh.n_small = 0;
+      sh.n_chunks = 0;
+      sh.nf = 0;
+      sh.mf = 0;
+    }
+    // prefix sums of the frontier's degrees, in place
+    const int incl = small_scan<BLOCK>((unsigned)t < ncur ? cur[cap + t] : 0, sh);
+    if ((unsigned)t < ncur) cur[cap + t] = incl;
     __syncthreads();
-    unsigned nf = 0;
-    u64 mf = 0, edges = 0;
-    for (unsigned base = (threadIdx.x / kWave) * kWave; base < ncur; base += BLOCK) {
-      const unsigned i = base + lane;
-      int rs = 0, deg = 0;
-      if (i < ncur) {
-        const int u = cur[i];
-        rs = a.rp[u];
-        deg = a.rp[u + 1] - rs;
+    const int total = sh.total;
+    const int* inc = cur + cap;
+    int v = 0, rsv = 0, dv = -1;
+    if (t < total) {
+      // the row holding edge t: smallest j with inc[j] > t
+      int lo = 0, hi = (int)ncur - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (inc[mid] > t) hi = mid; else lo = mid + 1;
       }
-      const int incl = wave_incl_scan(deg);
-      const int total = __shfl(incl, kWave - 1, kWave);
-      for (int eb = 0; eb < total; eb += 4 * kWave) {
-        int v[4];
-        bool has[4];
-        u64 w[4], bit[4], old[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x = eb + k * kWave + lane;
-          has[k] = x < total;
-          const int j = wave_owner(incl, has[k] ? x : total - 1);
-          const int inc_j = __shfl(incl, j, kWave);
-          const int deg_j = __shfl(deg, j, kWave);
-          const int rs_j = __shfl(rs, j, kWave);
-          v[k] = has[k] ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          bit[k] = 1ull << (v[k] & 63);
-          w[k] = has[k] ? vis[v[k] >> 6] : bit[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) old[k] = (w[k] & bit[k]) ? bit[k] : atom_or(&vis[v[k] >> 6], bit[k]);
-        int dv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (has[k]) edges += 1;
-          const bool claim = !(old[k] & bit[k]);
-          dv[k] = claim ? a.rp[v[k] + 1] - a.rp[v[k]] : -1;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (dv[k] >= 0) {
-            a.dist[v[k]] = L;
-            nf += 1;
-            mf += (u64)dv[k];
-          }
-          const u64 mk = __ballot(dv[k] > 0);
-          if (mk) {
-            const int lead = __ffsll((unsigned long long)mk) - 1;
-            unsigned b = 0;
-            if (lane == lead) b = atomicAdd(&sh.n_next, (unsigned)__popcll(mk));
-            b = (unsigned)__shfl((int)b, lead, kWave);
-            const unsigned pos = b + (unsigned)__popcll(mk & lanes_below());
-            if (dv[k] > 0 && pos < (unsigned)cap) nxt[pos] = v[k];
-          }
-        }
+      const int excl = lo ? inc[lo - 1] : 0;
+      v = a.col[cur[lo] + (t - excl)];
+      const u64 bit = 1ull << (v & 63);
+      if (!(atom_or(&vis[v >> 6], bit) & bit)) {
+        a.dist[v] = L;
+        rsv = a.rp[v];
+        dv = a.rp[v + 1] - rsv;
       }
     }
-    block_sum3<BLOCK>(nf, mf, edges);
-    if (threadIdx.x == 0) {
+    // the claimed nodes: counters, next list, this level's queue
+    const unsigned cnf = wave_sum((unsigned)(dv >= 0 ? 1 : 0));
+    const u64 cmf = wave_sum((u64)(dv > 0 ? dv : 0));
+    if (lane == 0 && cnf) {
+      atomicAdd(&sh.nf, cnf);
+      atomicAdd(&sh.mf, cmf);
+    }
+    const u64 mk = __ballot(dv > 0);
+    if (mk) {
+      const int lead = __ffsll((unsigned long long)mk) - 1;
+      unsigned b = 0;
+      if (lane == lead) b = atomicAdd(&sh.n_next, (unsigned)__popcll(mk));
+      b = (unsigned)__shfl((int)b, lead, kWave);
+      const unsigned pos = b + (unsigned)__popcll(mk & lanes_below());
+      if (dv > 0 && pos < (unsigned)cap) {
+        nxt[pos] = rsv;
+        nxt[cap + pos] = dv;
+      }
+    }
+    const bool small = dv > 0 && dv < a.big_degree;
+    const u64 ms = __ballot(small);
+    if (ms) {
+      const int lead = __ffsll((unsigned long long)ms) - 1;
+      unsigned b = 0;
+      if (lane == lead) b = atomicAdd(&sh.n_small, (unsigned)__popcll(ms));
+      b = (unsigned)__shfl((int)b, lead, kWave);
+      if (small) small_q(a, L)[b + (unsigned)__popcll(ms & lanes_below())] = v;
+    }
+    if (dv >= a.big_degree && dv > 0) {
+      const int nch = (dv + BLOCK - 1) / BLOCK;
+      const unsigned b = atomicAdd(&sh.n_chunks, (unsigned)nch);
+      for (int k = 0; k < nch; ++k) {
+        chunk_u(a, L)[b + k] = v;
+        chunk_k(a, L)[b + k] = k;
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
       LevelState nx = st;
-      const SlotSum sum{nf, mf, edges};
+      const SlotSum sum{sh.nf, sh.mf, (u64)total};
       decide(a, nx, sum, true);
-      sh.nf = nf;
-      sh.mf = mf;
-      sh.edges = edges;
-      if (small_push<BLOCK>(a, nx, sum)) {
-        sh.go = 1;
+      // (each branch stores one named struct: a select between two of
+      // them would put both in scratch memory)
+      const int go = small_push<BLOCK>(a, nx, sum) ? 1 : 0;
+      sh.go = go;
+      if (go || nx.done) {
         sh.st = nx;
       } else {
-        sh.go = 0;
-        sh.st = nx.done ? nx : st;
+        sh.st = st;
       }
     }
     __syncthreads();
     if (!sh.go) break;
     st = sh.st;
     ncur = min(sh.n_next, (unsigned)cap);
-    int32_t* t = cur;
+    int32_t* sw = cur;
     cur = nxt;
-    nxt = t;
+    nxt = sw;
   }
   // the other workgroups decided from the slot of the level before this
   // launch's first one, which the hand-over below may overwrite
@@ -990,52 +1023,26 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
   LevelState fin = sh.st;
   if (!sh.arrived) fin.done = 2;
   if (fin.done) {
-    if (threadIdx.x == 0) a.ctrl->st[parity] = fin;
+    if (t == 0) a.ctrl->st[parity] = fin;
     return;
   }
-  // hand over level L = fin.level: its nodes to its queue (sub-queue 0) and
-  // chunk lists, its counters to stripe 0 of its slot (the other stripes
-  // zero), and the slot of level L + 1 zeroed for the launch that runs it
+  // hand over level L = fin.level (its queue is written): its counters to
+  // stripe 0 of its slot, the other stripes zero, and the slot of level
+  // L + 1 zeroed for the launch that runs it
   const int L = fin.level;
-  const unsigned nl = min(sh.n_next, (unsigned)cap);
-  if (threadIdx.x == 0) {
-    sh.n_small = 0;
-    sh.n_chunks = 0;
-  }
   {
-    // stripes 1.. of level L's slot and all of level L + 1's; stripe 0 and
-    // the chunk count of level L are written once below
     LevelSlot* sl = &a.ctrl->slot[L % 3];
     unsigned* w = (unsigned*)&sl->s[1];
     const int words = (int)((sizeof(SlotStripe) * (kStripes - 1)) / 4);
-    for (int i = threadIdx.x; i < words; i += BLOCK) w[i] = 0;
-    zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
+    for (int i = t; i < words; i += BLOCK) w[i] = 0;
+    zero_slot(&a.ctrl->slot[(L + 1) % 3], t, BLOCK);
   }
-  __syncthreads();
-  int32_t* qo = small_q(a, L);
-  int32_t* cuo = chunk_u(a, L);
-  int32_t* cko = chunk_k(a, L);
-  for (unsigned i = threadIdx.x; i < nl; i += BLOCK) {
-    const int v = nxt[i];
-    const int d = a.rp[v + 1] - a.rp[v];
-    if (d < a.big_degree) {
-      qo[atomicAdd(&sh.n_small, 1u)] = v;
-    } else {
-      const int nch = (d + BLOCK - 1) / BLOCK;
-      const unsigned b = atomicAdd(&sh.n_chunks, (unsigned)nch);
-      for (int k = 0; k < nch; ++k) {
-        cuo[b + k] = v;
-        cko[b + k] = k;
-      }
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     SlotStripe& s0 = a.ctrl->slot[L % 3].s[0];
     s0.nf = sh.nf;
     s0.small_count = sh.n_small;
     s0.mf = sh.mf;
-    s0.edges = sh.edges;
+    s0.edges = (u64)sh.total;
     a.ctrl->slot[L % 3].big_chunks = sh.n_chunks;
     a.ctrl->st[parity] = fin;
   }

@@ -174,7 +174,7 @@ dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, u
                         {4, 16, 32, 128}));
     if (st == DAWN_OK)
       st = one(variants([](dawn_params& p, double v) { p.small_frontier_edges = (int)v; },
-                        {-1, 256, 512, 1024, 2048}));
+                        {-1, 128, 256, 512, 1024}));
   }
   if (st == DAWN_OK && (what & 2)) {
     t.batched = true;
