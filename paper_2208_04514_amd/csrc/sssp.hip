@@ -247,6 +247,14 @@ __device__ __forceinline__ void visit4(const SsspArgs& a, int L, u64* vis, const
   for (int i = 0; i < 4; ++i) emit_found_deg<BLOCK>(a, L, v[i], claim[i], deg[i], c, q);
 }
 
+// Waves that share one group of 64 small-degree frontier nodes: enough to
+// give every wave of the grid a share when the frontier has few groups
+// (at most 64, one step of 256 edges each for a group of up to 16 K edges).
+__device__ __forceinline__ unsigned small_split(unsigned nsmall, unsigned nwaves) {
+  const unsigned groups = (nsmall + kWave - 1) / kWave;
+  return groups == 0 || groups >= nwaves ? 1u : min(nwaves / groups, 64u);
+}
+
 // pre: the sub-queue offsets of level L-1 in LDS; `nch` its chunk count, or
 // ~0u to have them read here.  The level's work is dealt over `nblk`
 // workgroups, this one being `bid` (the grid, or one workgroup alone).
@@ -285,14 +293,19 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
     visit4<BLOCK>(a, L, vis, v, has, c, q);
   }
 
-  // small-degree nodes: 64 per wave, union of their rows walked 64 edges a step
+  // small-degree nodes: groups of 64, the union of a group's rows walked 256
+  // edges a step; a frontier of fewer groups than the grid has waves splits
+  // each group's steps over `split` waves
   const int lane = lane_id();
   const int wpb = BLOCK / kWave;
   const unsigned gw = bid * wpb + threadIdx.x / kWave;
   const unsigned nwaves = nblk * wpb;
   const int32_t* q_in = small_q(a, L - 1);
-  for (unsigned base = gw * kWave; base < nsmall; base += nwaves * kWave) {
-    const unsigned i = base + lane;
+  const unsigned split = small_split(nsmall, nwaves);
+  const unsigned nvirt = (nsmall + kWave - 1) / kWave * split;
+  for (unsigned vw = gw; vw < nvirt; vw += nwaves) {
+    const unsigned part = vw % split;
+    const unsigned i = (vw / split) * kWave + lane;
     int rs = 0, deg = 0;
     if (i < nsmall) {
       const int s = stripe_of(pre, i);
@@ -302,8 +315,8 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
     }
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, kWave - 1, kWave);
-    // four edges per lane and step
-    for (int eb = 0; eb < total; eb += 4 * kWave) {
+    // four edges per lane and step; this wave takes steps part, part + split, ...
+    for (int eb = (int)part * 4 * kWave; eb < total; eb += (int)split * 4 * kWave) {
       int v[4];
       bool has[4];
 #pragma unroll
@@ -1070,8 +1083,11 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
         decide(a, st, sum, blockIdx.x == 0);
         sm = small_push<BLOCK>(a, st, sum) ? 1 : 0;
         // a push level with nothing for this workgroup lets it leave at once
-        const unsigned first_small = blockIdx.x * (BLOCK / kWave) * kWave;
-        idle = !st.done && !st.pull && first_small >= pre[kStripes] && blockIdx.x >= nchunks;
+        const unsigned nwaves = gridDim.x * (BLOCK / kWave);
+        const unsigned nvirt = (pre[kStripes] + kWave - 1) / kWave *
+                               small_split(pre[kStripes], nwaves);
+        idle = !st.done && !st.pull && blockIdx.x * (BLOCK / kWave) >= nvirt &&
+               blockIdx.x >= nchunks;
         if (sm) idle = blockIdx.x != 0;
       } else {
         idle = 1;
