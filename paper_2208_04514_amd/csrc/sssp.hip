@@ -247,6 +247,9 @@ __device__ __forceinline__ void visit4(const SsspArgs& a, int L, u64* vis, const
   for (int i = 0; i < 4; ++i) emit_found_deg<BLOCK>(a, L, v[i], claim[i], deg[i], c, q);
 }
 
+// Largest visited bitmap a pull level copies to LDS.
+constexpr size_t kPullLdsMax = 64 << 10;
+
 // Waves that share one group of 64 small-degree frontier nodes: enough to
 // give every wave of the grid a share when the frontier has few groups
 // (at most 64, one step of 256 edges each for a group of up to 16 K edges).
@@ -337,7 +340,6 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
 // LDS the pull step needs per wave: a rank -> lane table and hit flags.
 struct PullScratch {
   int rank_lane[kWave];
-  int hit[kWave];
 };
 
 // `vin` is the visited bitmap of the previous level, read from LDS when the
@@ -350,7 +352,6 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
   const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
   const unsigned nwaves = gridDim.x * wpb;
   PullScratch& sc = ps[threadIdx.x / kWave];
-  sc.hit[lane] = 0;
   for (unsigned w = gw; w < (unsigned)a.nw; w += nwaves) {
     const u64 word = vin[w];
     // nodes without in-edges can only be the source: treat them as settled
@@ -401,20 +402,23 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
       const int oc = __shfl(cur, owner, kWave);
       const int oe = __shfl(e, owner, kWave);
       const int idx = oc + off;
+      bool hit = false;
       if (idx < oe) {
         const int u = a.isrc[idx];
         c.edges += 1;
-        if ((vin[u >> 6] >> (u & 63)) & 1ull) sc.hit[owner] = 1;
+        hit = (vin[u >> 6] >> (u & 63)) & 1ull;
       }
+      // the helpers of the node of rank r are lanes r, r + cnt, ...: fold
+      // the wave's hit mask onto the ranks
+      const u64 hm = __ballot(hit);
+      u64 fold = 0;
+      for (int sft = 0; sft < kWave; sft += cnt) fold |= hm >> sft;
       __builtin_amdgcn_wave_barrier();
       if (searching) {
-        if (sc.hit[lane]) found = true;
+        if ((fold >> rank) & 1ull) found = true;
         cur += (kWave - rank + cnt - 1) / cnt;
         searching = !found && cur < e;
       }
-      __builtin_amdgcn_wave_barrier();
-      sc.hit[lane] = 0;
-      __builtin_amdgcn_wave_barrier();
       um = __ballot(searching);
     }
     const u64 newbits = __ballot(found);
@@ -1477,12 +1481,14 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
     return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, false);
   }
   // the visited bitmap goes to LDS for pull levels when it fits next to the
-  // kernel's own LDS
+  // kernel's own LDS and is at most kPullLdsMax bytes (every workgroup copies
+  // it at each pull level; on R-MAT 20, 128 KiB, the copy costs what the
+  // faster in-edge checks save)
   hipFuncAttributes fa;
   DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
   const size_t bitmap = (size_t)a.nw * 8;
   size_t shmem = 0;
-  if (fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
+  if (bitmap <= kPullLdsMax && fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
     shmem = bitmap;
     a.lds_words = a.nw;
     DAWN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sssp_level<BLOCK>),
@@ -1684,7 +1690,7 @@ static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, S
   DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
   const size_t bitmap = (size_t)a.nw * 8;
   size_t shmem = 0;
-  if (fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
+  if (bitmap <= kPullLdsMax && fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
     shmem = bitmap;
     a.lds_words = a.nw;
     DAWN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sssp_level<BLOCK>),
