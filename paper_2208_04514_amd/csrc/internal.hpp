@@ -152,6 +152,9 @@ struct SsspArgs {
   int32_t small_edges;        // a push level whose frontier has at most this many out-edges
                               //   runs on one workgroup, with the small levels after it in
                               //   the same launch (0: never)
+  LevelState* hst;            // host-mapped copy of ctrl->st (the level launches store the
+                              //   state there too, so the host reads it after a stream
+                              //   sync without a copy); null: none
   unsigned long long* clk;    // timing mode: this launch's kClkStripes lines; in line s,
                               //   [0] the earliest start and [1] the latest end (GPU wall
                               //   clock) of the workgroups b with b % kClkStripes = s;
@@ -194,6 +197,8 @@ struct SsspWs {
   size_t chunk_cap = 0;
   size_t bytes = 0;
   SsspCtrl* h_ctrl = nullptr;   // pinned read-back
+  LevelState* h_st = nullptr;   // coherent host memory the level launches mirror st[0..1] into
+  LevelState* d_st = nullptr;   //   ... and its device address
   // HIP graph driver cache: init + levels, and levels alone for long runs
   hipGraphExec_t gexec = nullptr;
   hipGraphExec_t gexec_more = nullptr;

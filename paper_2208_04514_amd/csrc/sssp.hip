@@ -1040,7 +1040,10 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
   LevelState fin = sh.st;
   if (!sh.arrived) fin.done = 2;
   if (fin.done) {
-    if (t == 0) a.ctrl->st[parity] = fin;
+    if (t == 0) {
+      a.ctrl->st[parity] = fin;
+      if (a.hst) a.hst[parity] = fin;
+    }
     return;
   }
   // hand over level L = fin.level (its queue is written): its counters to
@@ -1062,6 +1065,7 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
     s0.edges = (u64)sh.total;
     a.ctrl->slot[L % 3].big_chunks = sh.n_chunks;
     a.ctrl->st[parity] = fin;
+    if (a.hst) a.hst[parity] = fin;
   }
 }
 
@@ -1113,6 +1117,7 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
     if (!st.done && st.pull) out.cur ^= 1;
     if (!st.done) out.launches += 1;
     a.ctrl->st[parity] = out;
+    if (a.hst) a.hst[parity] = out;
   }
   if (st.done) return;
   const int L0 = st.level;
@@ -1186,6 +1191,7 @@ SsspWs::~SsspWs() {
   dev_free(ctx, clk, 0);
   if (ctx) ctx->used -= bytes;
   if (h_ctrl) hipHostFree(h_ctrl);
+  if (h_st) hipHostFree(h_st);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
   if (stream) hipStreamDestroy(stream);
@@ -1225,6 +1231,10 @@ static dawn_status ws_create(Ctx* ctx, GraphRec* g, std::unique_ptr<SsspWs>* out
   if (s != DAWN_OK) return s;
   DAWN_HIP(hipMemset(w->ctrl, 0, sizeof(SsspCtrl)));
   DAWN_HIP(hipHostMalloc((void**)&w->h_ctrl, sizeof(SsspCtrl), hipHostMallocDefault));
+  DAWN_HIP(hipHostMalloc((void**)&w->h_st, 2 * sizeof(LevelState),
+                         hipHostMallocCoherent | hipHostMallocMapped));
+  memset(w->h_st, 0, 2 * sizeof(LevelState));
+  DAWN_HIP(hipHostGetDevicePointer((void**)&w->d_st, w->h_st, 0));
   DAWN_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
   DAWN_HIP(hipEventCreate(&w->ev0));
   DAWN_HIP(hipEventCreate(&w->ev1));
@@ -1252,6 +1262,7 @@ static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
   a.ck0 = w->ck[0];
   a.ck1 = w->ck[1];
   a.ctrl = w->ctrl;
+  a.hst = w->d_st;
   a.dist = nullptr;
   (void)source;
   (void)dist;
@@ -1347,15 +1358,14 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       DAWN_HIP(hipGetLastError());
       *launches += 1;
       ++level_launches;
-      DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[parity], &w->ctrl->st[parity], sizeof(LevelState),
-                              hipMemcpyDeviceToHost, w->stream));
+      if (!level_ms) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
       DAWN_HIP(hipStreamSynchronize(w->stream));
       if (level_ms) {
         float ms = 0.f;
         DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
         *level_ms += ms;
       }
-      if (w->h_ctrl->st[parity].done) {
+      if (w->h_st[parity].done) {
         *final_parity = parity;
         if (level_ms) {
           *launches = level_launches;
@@ -1399,12 +1409,11 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       DAWN_HIP(hipGetLastError());
       *launches += batch;
       queued += batch;
-      DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[1], &w->ctrl->st[1], sizeof(LevelState),
-                              hipMemcpyDeviceToHost, w->stream));
+      DAWN_HIP(hipEventRecord(w->ev1, w->stream));
       DAWN_HIP(hipStreamSynchronize(w->stream));
-      if (w->h_ctrl->st[1].done) {
+      if (w->h_st[1].done) {
         // launches this traversal needed: those that ran levels, then the end
-        const int need = w->h_ctrl->st[1].launches + 1;
+        const int need = w->h_st[1].launches + 1;
         g->launch_hint.store(std::max(need, hint - 1), std::memory_order_relaxed);
         *final_parity = 1;
         return DAWN_OK;
@@ -1442,10 +1451,9 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
   for (long long it = 0; it * graph_levels <= max_launch; ++it) {
     DAWN_HIP(hipGraphLaunch(it == 0 ? w->gexec : w->gexec_more, w->stream));
     *launches += graph_levels + (it == 0 ? 1 : 0);
-    DAWN_HIP(hipMemcpyAsync(&w->h_ctrl->st[1], &w->ctrl->st[1], sizeof(LevelState),
-                            hipMemcpyDeviceToHost, w->stream));
+    DAWN_HIP(hipEventRecord(w->ev1, w->stream));
     DAWN_HIP(hipStreamSynchronize(w->stream));
-    if (w->h_ctrl->st[1].done) {
+    if (w->h_st[1].done) {
       *final_parity = 1;
       return DAWN_OK;
     }
@@ -1550,7 +1558,9 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
     default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
   }
-  if (!level_timing) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+  // the level drivers record the end event after their last launch, before
+  // the host waits; the persistent kernel and the one-workgroup path here
+  if (!level_timing && (small || p.driver == 1)) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
     hipStreamSynchronize(w->stream);
     w->poisoned = true;
@@ -1573,7 +1583,7 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     DAWN_HIP(hipMemcpyAsync(ldir.data(), w->level_dir, cap, hipMemcpyDeviceToHost, w->stream));
   }
   if (persistent || cap > 0) DAWN_HIP(hipStreamSynchronize(w->stream));
-  const LevelState& rs = w->h_ctrl->st[fp];
+  const LevelState& rs = persistent ? w->h_ctrl->st[fp] : w->h_st[fp];
   if (rs.done != 1) w->poisoned = true;
   if (persistent && w->h_ctrl->bar.abort) return fail(DAWN_E_DEVICE, "grid barrier timed out");
   if (rs.done == 2) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
