@@ -235,6 +235,16 @@ def cached_knobs(D, ctx, h, g, width, names, what, seed, k_tune, live, tune_file
     return {n: tuned[n] for n in names}, "autotune (live)", tune_s
 
 
+def batched_roofline(g, k, st):
+    words = (k + 63) // 64
+    alg = st["levels"] * (4.0 * g.n + 4.0 * g.m + 24.0 * words * g.n) + 4.0 * k * g.n
+    achieved = alg / (st["kernel_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "alg_bytes": round(alg), "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernels": "batch_seed, batch_control, batch_push, batch_pull, batch_merge, "
+                       "batch_emit (per-kernel bytes: profiles/batch_rmat18_4096_kernels_hbm.md)"}
+
+
 def batched_bench(D, ctx, live=False, tune_file=None):
     """R-MAT 18, 4096 sources in one dawn_mssp launch, and the same sources
     one at a time through dawn_sssp."""
@@ -269,6 +279,9 @@ def batched_bench(D, ctx, live=False, tune_file=None):
         "workload": "rmat18_ef16_sym_4096src_one_launch", "n": g.n, "m": g.m,
         "gteps": round(st_b["source_edges"] / tb / 1e9, 2),
         "gteps_device": round(st_b["source_edges"] / st_b["kernel_ms"] / 1e6, 2),
+        # the whole call against HBM: per level 4n + 4m (CSC/CSR) + 24 W n
+        # (row reads and writes of vis and the next frontier), once 4 k n (output)
+        "roofline": batched_roofline(g, src.size, st_b),
         "ms": round(tb * 1e3, 3), "kernel_ms": round(st_b["kernel_ms"], 3),
         "levels": st_b["levels"], "push_levels": st_b["push_levels"],
         "pull_levels": st_b["pull_levels"],
