@@ -168,6 +168,9 @@ def roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs, lk_clock_
         else:
             traffic = rec["bytes_per_launch"]
             note = rec.get("source", "")
+    # the measured traffic (counter bytes per launch, from the committed
+    # record) over the same launch time: the achieved HBM fraction
+    traffic_gbs = traffic / (lk_ms / lk_launches / 1e3) / 1e9 if traffic else None
     return {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
@@ -179,6 +182,8 @@ def roofline_entry(g, dist_rows, lk_ms, lk_launches, lk_levels, knobs, lk_clock_
         "achieved_kernel_clock": round(achieved_clk, 2) if achieved_clk else None,
         "frac_kernel_clock": round(achieved_clk / HBM_PEAK_GBS, 5) if achieved_clk else None,
         "alg_bytes_per_launch": round(alg / lk_launches, 1),
+        "achieved_traffic": round(traffic_gbs, 2) if traffic_gbs else None,
+        "frac_traffic": round(traffic_gbs / HBM_PEAK_GBS, 5) if traffic_gbs else None,
         "traffic_note": note,
     }
 
@@ -265,6 +270,7 @@ def batched_bench(D, ctx, live=False, tune_file=None):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     tb = float(np.median(times))
+    kept = out[:256].cpu().numpy()      # rows of the timed call, for the oracle leg
     del out
     row = torch.empty(g.n, dtype=torch.int32, device="cuda")
     t0 = time.perf_counter()
@@ -290,6 +296,7 @@ def batched_bench(D, ctx, live=False, tune_file=None):
         "speedup_vs_plain": round(tp / tb, 2),
         "tuned": tuned, "tuned_from": tuned_from,
         "autotune_s": round(tune_s, 2),
+        "_kept": (g, src[:256], kept),
     }
 
 
@@ -409,7 +416,7 @@ def small_component_bench(D, ctx):
     return res
 
 
-def grid_bench(D, ctx, k_src=4):
+def grid_bench(D, ctx, k_src=16):
     """The damaged 2048^2 grid (about 120 levels) under each level-loop
     driver, and the no-shortcut grid (thousands of levels) under two."""
     import torch
@@ -665,8 +672,8 @@ def roofline_only(D, ctx, params_json):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the APSP and grid sections")
     ap.add_argument("--no-cpu", action="store_true")
@@ -796,6 +803,21 @@ def main():
         if not args.no_serve:
             _log("[bench] oracle on the kept served rows")
             extra["served"]["parity"] = served_parity(served_check)
+        if "batched" in extra:
+            # the oracle on 256 of the batch's sources, one per host thread, and
+            # those rows of the timed batched call against it
+            gb, sb, kept = extra["batched"].pop("_kept")
+            import oracle
+            cores = host_cores()
+            t0 = time.perf_counter()
+            want = oracle.mssp(gb, sb, threads=cores)
+            tb_cpu = time.perf_counter() - t0
+            seb = gg.reach_edges_from_dist(gb, want)
+            extra["batched"]["cpu_parallel_sample"] = {
+                "value": round(seb / tb_cpu / 1e9, 4), "unit": "GTEPS", "cores": cores,
+                "kind": "oracle", "sample": f"rmat18, 256 of the 4096 batch sources, one per "
+                                            f"thread, {tb_cpu:.1f} s"}
+            extra["batched"]["sample_rows_bit_exact"] = bool(np.array_equal(want, kept))
         extra["parity"] = {"timed_pass_bit_exact": bool(np.array_equal(ref, timed_rows)),
                            "timing_pass_bit_exact": bool(np.array_equal(ref, dist_rows)),
                            "host_output_bit_exact": bool(np.array_equal(ref, host_rows)),
@@ -821,6 +843,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if "batched" in extra:
+        extra["batched"].pop("_kept", None)
     line.update(extra)
     print(json.dumps(line), flush=True)
 
