@@ -513,7 +513,8 @@ def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2, nq_host=300):
     """Three resident graphs, queries of 1..1024 sources (log-uniform) on a
     uniformly chosen graph, sources from its largest WCC: first saturated (a
     window of queries in flight) to find the capacity, then Poisson arrivals
-    at 0.5 and 0.9 of that query rate, and at 0.5 with host-destination rows.
+    at 0.5 and 0.9 of that query rate; then the same with host-destination
+    rows (saturated, then 0.5 of that mode's own rate).
     Each run submits `nq` queries and discards the first `skip` as warm-up
     (the host-destination run: the first `nq_host` of them, discarding a
     tenth; its rows, ~0.6 GB per query on the 2^20-node graphs, cross PCIe
@@ -546,9 +547,18 @@ def serving_bench(D, ctx, nq=2000, skip=100, seed=105, keep=2, nq_host=300):
                          "p50_ms": round(float(np.percentile(lat, 50)), 3),
                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
                          "per_graph": _per_graph(names, lat, gis)}}
+    _log("[bench]   saturated, host output")
+    dt, lat, se, ks, gis, _ = serve_run(D, ctx, graphs, queries[:nq_host], skip=nq_host // 20,
+                                        host_out=True)
+    cap_host = nq_host / dt
+    res["saturated_host_output"] = {"queries": nq_host, "qps": round(cap_host, 1),
+                                    "gteps": round(se / dt / 1e9, 2),
+                                    "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                    "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                                    "per_graph": _per_graph(names, lat, gis)}
     for label, frac, host in (("load_0.5", 0.5, False), ("load_0.9", 0.9, False),
                               ("load_0.5_host_output", 0.5, True)):
-        lam = frac * cap_qps
+        lam = frac * (cap_host if host else cap_qps)
         nrun = nq_host if host else nq
         arr = np.cumsum(rng.exponential(1.0 / lam, size=nrun))
         dt, lat, se, ks, gis, _ = serve_run(D, ctx, graphs, queries[:nrun], arrivals=arr,
