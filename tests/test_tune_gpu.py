@@ -42,7 +42,7 @@ def test_set_params_validation(ctx, upload):
     before = D.dawn_get_params(ctx, h)
     for bad in (dict(driver=9), dict(block=128), dict(batch_lanes=100), dict(big_degree=10),
                 dict(timing=1, driver=3), dict(batch_big_degree=32), dict(batch_wide_scan=600),
-                dict(batch_sparse_words=5)):
+                dict(batch_sparse_words=5), dict(small_frontier_edges=-3)):
         with pytest.raises(D.DawnError) as ei:
             D.dawn_set_params(ctx, h, **bad)
         assert ei.value.status == D.DAWN_E_INVALID_ARG
@@ -67,6 +67,26 @@ def test_batched_knob_candidates_bit_exact(ctx, upload, name, k):
                 D.dawn_set_params(ctx, h, **{knob: v})
                 got, _ = D.dawn_mssp(ctx, h, srcs)
                 assert np.array_equal(got, want), f"{name} k={k} {knob}={v}"
+            D.dawn_set_params(ctx, h, **saved)
+    finally:
+        D.dawn_set_params(ctx, h, **saved)
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid128"])
+def test_plain_knob_candidates_bit_exact(ctx, upload, name):
+    """Every value the autotuner tries for the single-source level-loop knobs
+    gives the oracle's rows."""
+    h, g, src = upload(name)
+    want = oracle.mssp(g, src[:4])
+    saved = D.dawn_get_params(ctx, h)
+    try:
+        for knob, vals in (("small_frontier_edges", (-1, 128, 256, 512, 1024)),
+                           ("big_degree", (128, 256, 512, 1024, 2048, 8192))):
+            for v in vals:
+                D.dawn_set_params(ctx, h, **{knob: v})
+                for r, s in enumerate(src[:4]):
+                    got, _ = D.dawn_sssp(ctx, h, int(s))
+                    assert np.array_equal(got, want[r]), f"{name} {knob}={v} source {s}"
             D.dawn_set_params(ctx, h, **saved)
     finally:
         D.dawn_set_params(ctx, h, **saved)
