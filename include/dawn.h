@@ -305,7 +305,11 @@ dawn_status dawn_autotune(dawn_ctx *ctx, int32_t graph, const int32_t *sources, 
  * batching).  While a level runs the scheduler polls the device without
  * sleeping (one host core busy), for up to 2 ms after its last step, then
  * in 20 us sleeps.  The caller keeps `sources` only until the call returns, but must
- * keep dist_out valid and unread until dawn_serve_poll returns DAWN_OK.
+ * keep dist_out valid and unread until dawn_serve_poll returns DAWN_OK.  A
+ * device dist_out is written later on the server's own stream, in no order
+ * with the caller's streams: work that writes it (a fill, say) must have
+ * finished before this call (the Python binding synchronizes torch's current
+ * stream first).
  * Errors: INVALID_ARG, NOT_FOUND, NO_MEMORY (the query can never fit),
  * BUSY (queue full). */
 dawn_status dawn_serve_submit(dawn_ctx *ctx, int32_t graph, const int32_t *sources, int32_t k,

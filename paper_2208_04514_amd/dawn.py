@@ -433,10 +433,13 @@ def dawn_autotune(ctx, graph: int, sources, what: int = 3) -> dict:
 
 
 def dawn_serve_submit(ctx, graph: int, sources, out) -> int:
-    """Queue a query; `out` (int32 [k, n], numpy or torch CUDA) must stay alive until done."""
+    """Queue a query; `out` (int32 [k, n], numpy or torch CUDA) must stay alive until done.
+
+    The server writes a device `out` on its own stream, later: pending work
+    on the caller's torch stream (a fill of `out`, say) is finished first, so
+    it cannot land on top of the rows."""
     src = _host_i32(sources).ravel()
-    ptr, flags, _keep = check_out(out, (src.size, _graph_n(ctx, graph)),
-                                  _CTX_DEVICE.get(_ctx_key(ctx)))
+    ptr, flags, _keep = _out_ptr(ctx, out, (src.size, _graph_n(ctx, graph)))
     t = ctypes.c_uint64(0)
     _check(load().dawn_serve_submit(ctx, graph, src.ctypes.data_as(ctypes.c_void_p), src.size,
                                     ptr, flags, ctypes.byref(t)))
