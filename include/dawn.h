@@ -74,11 +74,15 @@ typedef struct dawn_run_stats {
   int32_t levels;
   int32_t push_levels;        /* expansion steps run as push */
   int32_t pull_levels;        /* expansion steps run as pull */
-  int32_t launches;           /* traversal kernel launches covered by kernel_ms */
+  int32_t launches;           /* traversal kernel launches (driver 3: those queued, some of
+                                 which may carry the final state only) */
   int64_t edges_examined;     /* adjacency entries read by expansion steps */
   int64_t source_edges;       /* sum over sources of sum of outdeg(u), u reached */
   int64_t reached;            /* sum over sources of reached nodes (sources included) */
-  double kernel_ms;           /* device time of the traversal kernels (HIP events) */
+  double kernel_ms;           /* device time of the traversal: HIP events around its kernels;
+                                 dawn_sssp under driver 3: the GPU wall clock from the init
+                                 kernel's start to the start of the launch that found the
+                                 end (launches queued past the end are not counted) */
   double total_ms;            /* host wall time of the call */
   /* dawn_sssp only, optional inputs: when frontier_sizes is non-null it receives
    * the number of nodes found at level L (L = 0 .. min(levels, frontier_cap) - 1)
@@ -99,7 +103,12 @@ typedef struct dawn_run_stats {
 typedef struct dawn_params {
   int32_t driver;             /* 1 persistent cooperative kernel (grid barrier per level),
                                  2 one launch per level with a host read-back,
-                                 3 `graph_levels` level launches queued per host read-back,
+                                 3 level launches queued in batches (the first sized from the
+                                   graph's recent traversals, later ones `graph_levels`); the
+                                   call returns once the launch that finds the end has
+                                   reported to host memory, while launches queued past the
+                                   end (they only carry the final state) may still run on
+                                   the library's stream,
                                  4 the same launches captured once in a HIP graph and replayed */
   int32_t direction;          /* 1 push only, 2 pull only, 3 switch by alpha/beta */
   int32_t block;              /* threads per workgroup: 256, 512 or 1024 */

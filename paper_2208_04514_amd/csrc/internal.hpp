@@ -98,6 +98,19 @@ struct LevelState {
   u64 reached;
 };
 
+// Coherent host memory a direct-launch traversal reports to, so the host
+// learns of the end without a stream synchronisation.  The launch that finds
+// the end stores its state in st[parity] and the GPU wall clock in t_end,
+// then (after a system-scope fence) end_tag = (seq << 1) | parity, seq being
+// the traversal's number (never 0).  Launches that only carry a finished
+// state forward write nothing here.  t_start is the init kernel's start.
+struct HostMirror {
+  LevelState st[2];
+  unsigned long long t_start;
+  unsigned long long t_end;
+  unsigned end_tag;
+};
+
 // st[p]: the state after the level run by the last launch of parity p (the
 // per-level kernels alternate parities, so a launch reads st[p ^ 1] and
 // writes st[p] without racing its own readers).
@@ -152,9 +165,9 @@ struct SsspArgs {
   int32_t small_edges;        // a push level whose frontier has at most this many out-edges
                               //   runs on one workgroup, with the small levels after it in
                               //   the same launch (0: never)
-  LevelState* hst;            // host-mapped copy of ctrl->st (the level launches store the
-                              //   state there too, so the host reads it after a stream
-                              //   sync without a copy); null: none
+  HostMirror* hm;             // host-mapped report of the traversal (device address of a
+                              //   coherent host allocation); null: none
+  unsigned seq;               // this traversal's number in hm->end_tag (direct launches)
   unsigned long long* clk;    // timing mode: this launch's kClkStripes lines; in line s,
                               //   [0] the earliest start and [1] the latest end (GPU wall
                               //   clock) of the workgroups b with b % kClkStripes = s;
@@ -197,8 +210,14 @@ struct SsspWs {
   size_t chunk_cap = 0;
   size_t bytes = 0;
   SsspCtrl* h_ctrl = nullptr;   // pinned read-back
-  LevelState* h_st = nullptr;   // coherent host memory the level launches mirror st[0..1] into
-  LevelState* d_st = nullptr;   //   ... and its device address
+  HostMirror* h_m = nullptr;    // coherent host memory the level launches report to
+  HostMirror* d_m = nullptr;    //   ... and its device address
+  unsigned seq = 0;             // number of the last direct-launch traversal
+  // launch shape of the level kernel on this graph, per block size (256, 512,
+  // 1024), found on first use: grid, dynamic LDS, bitmap words copied to LDS
+  int shape_grid[3] = {0, 0, 0};
+  size_t shape_lds[3] = {0, 0, 0};
+  int32_t shape_words[3] = {0, 0, 0};
   // HIP graph driver cache: init + levels, and levels alone for long runs
   hipGraphExec_t gexec = nullptr;
   hipGraphExec_t gexec_more = nullptr;

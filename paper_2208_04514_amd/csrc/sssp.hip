@@ -750,6 +750,7 @@ template <int BLOCK>
 // captured graph or the persistent kernel must not depend on them).  Direct
 // launches publish them there for the level kernels.
 __global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0, int32_t* dist, int source) {
+  if (a0.hm && blockIdx.x == 0 && threadIdx.x == 0) a0.hm->t_start = wall_clock64();
   SsspArgs a = a0;
   int s = source;
   if (dist) {
@@ -813,6 +814,21 @@ __device__ __forceinline__ SlotSum read_level_slot(const SsspArgs& a, int level,
     *nchunks = nch;
   }
   return sum;
+}
+
+// The state a launch of parity `parity` leaves, to the host mirror (one
+// thread).  `ended`: this launch found the end of the traversal, so the end
+// stamp and tag follow, the tag ordered after the rest by a system-scope
+// release.
+__device__ __forceinline__ void report(const SsspArgs& a, int parity, const LevelState& s,
+                                       bool ended) {
+  if (!a.hm) return;
+  a.hm->st[parity] = s;
+  if (ended) {
+    a.hm->t_end = wall_clock64();
+    __hip_atomic_store(&a.hm->end_tag, (a.seq << 1) | (unsigned)parity, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Frontier nodes the one-workgroup loop holds: one per thread, as a pair
@@ -1042,7 +1058,7 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
   if (fin.done) {
     if (t == 0) {
       a.ctrl->st[parity] = fin;
-      if (a.hst) a.hst[parity] = fin;
+      report(a, parity, fin, true);
     }
     return;
   }
@@ -1065,7 +1081,7 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
     s0.edges = (u64)sh.total;
     a.ctrl->slot[L % 3].big_chunks = sh.n_chunks;
     a.ctrl->st[parity] = fin;
-    if (a.hst) a.hst[parity] = fin;
+    report(a, parity, fin, false);
   }
 }
 
@@ -1077,7 +1093,7 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   __shared__ unsigned pre[kStripes + 1];
   __shared__ PullScratch ps[BLOCK / kWave];
   __shared__ LevelState sst;
-  __shared__ int idle, small;
+  __shared__ int idle, small, ended;
   __shared__ int32_t big_v[BLOCK], big_c[BLOCK];
   __shared__ unsigned big_n, nchunks;
   if (threadIdx.x < kWave) {
@@ -1085,10 +1101,12 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
     const SlotSum sum = read_level_slot(a, st0.level, pre, &nchunks);
     if (threadIdx.x == 0) {
       big_n = 0;
+      ended = 0;
       LevelState st = st0;
       int sm = 0;
       if (!st.done) {
         decide(a, st, sum, blockIdx.x == 0);
+        ended = st.done ? 1 : 0;
         sm = small_push<BLOCK>(a, st, sum) ? 1 : 0;
         // a push level with nothing for this workgroup lets it leave at once
         const unsigned nwaves = gridDim.x * (BLOCK / kWave);
@@ -1117,7 +1135,7 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
     if (!st.done && st.pull) out.cur ^= 1;
     if (!st.done) out.launches += 1;
     a.ctrl->st[parity] = out;
-    if (a.hst) a.hst[parity] = out;
+    report(a, parity, out, ended != 0);
   }
   if (st.done) return;
   const int L0 = st.level;
@@ -1176,6 +1194,10 @@ __global__ void clk_reset(unsigned long long* clk, int launches) {
 
 // ------------------------------------------------------------------ host --
 SsspWs::~SsspWs() {
+  // a direct-launch traversal returns once its end is reported, while level
+  // launches queued past the end (they only carry the final state) may still
+  // be running on this stream
+  if (stream) hipStreamSynchronize(stream);
   if (gexec) hipGraphExecDestroy(gexec);
   if (gexec_more) hipGraphExecDestroy(gexec_more);
   for (int i = 0; i < 2; ++i) {
@@ -1191,7 +1213,7 @@ SsspWs::~SsspWs() {
   dev_free(ctx, clk, 0);
   if (ctx) ctx->used -= bytes;
   if (h_ctrl) hipHostFree(h_ctrl);
-  if (h_st) hipHostFree(h_st);
+  if (h_m) hipHostFree(h_m);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
   if (stream) hipStreamDestroy(stream);
@@ -1231,10 +1253,10 @@ static dawn_status ws_create(Ctx* ctx, GraphRec* g, std::unique_ptr<SsspWs>* out
   if (s != DAWN_OK) return s;
   DAWN_HIP(hipMemset(w->ctrl, 0, sizeof(SsspCtrl)));
   DAWN_HIP(hipHostMalloc((void**)&w->h_ctrl, sizeof(SsspCtrl), hipHostMallocDefault));
-  DAWN_HIP(hipHostMalloc((void**)&w->h_st, 2 * sizeof(LevelState),
+  DAWN_HIP(hipHostMalloc((void**)&w->h_m, sizeof(HostMirror),
                          hipHostMallocCoherent | hipHostMallocMapped));
-  memset(w->h_st, 0, 2 * sizeof(LevelState));
-  DAWN_HIP(hipHostGetDevicePointer((void**)&w->d_st, w->h_st, 0));
+  memset(w->h_m, 0, sizeof(HostMirror));
+  DAWN_HIP(hipHostGetDevicePointer((void**)&w->d_m, w->h_m, 0));
   DAWN_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
   DAWN_HIP(hipEventCreate(&w->ev0));
   DAWN_HIP(hipEventCreate(&w->ev1));
@@ -1262,7 +1284,7 @@ static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
   a.ck0 = w->ck[0];
   a.ck1 = w->ck[1];
   a.ctrl = w->ctrl;
-  a.hst = w->d_st;
+  a.hm = w->d_m;
   a.dist = nullptr;
   (void)source;
   (void)dist;
@@ -1365,7 +1387,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
         DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
         *level_ms += ms;
       }
-      if (w->h_st[parity].done) {
+      if (w->h_m->st[parity].done) {
         *final_parity = parity;
         if (level_ms) {
           *launches = level_launches;
@@ -1391,31 +1413,57 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
   }
   graph_levels += graph_levels & 1;
   if (driver == 3) {
-    // K level launches queued per host check of the final state.  The first
-    // batch covers what the graph's recent traversals needed (one more than
-    // their level count, for the launch that sees the end), so a typical
-    // traversal costs one host check and few launches past its end; a
-    // launch after the end only carries the final state along.
-    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
+    // K level launches queued per host check.  The first batch covers what
+    // the graph's recent traversals needed (one more than their level
+    // launches, for the launch that sees the end), so a typical traversal
+    // costs one batch and few launches past its end; a launch after the end
+    // only carries the final state along.  The host waits for the end tag in
+    // the host mirror, not for the stream: it returns as soon as the launch
+    // that found the end has reported (every level's writes are complete by
+    // then, the launches being stream-ordered), and the launches still queued
+    // behind it overlap with what the caller does next.  The stream is waited
+    // on only when a batch has run out without the end.
+    SsspArgs ad = a;
+    w->seq = w->seq % 0x7fffffffu + 1;
+    ad.seq = w->seq;
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, ad, d_dist,
                        source);
     *launches = 1;
     const int hint = g->launch_hint.load(std::memory_order_relaxed);
     int batch = hint > 0 ? std::min(hint + 1, graph_levels * 4) : graph_levels;
-    batch += batch & 1;
     long long queued = 0;
     while (queued <= max_launch) {
       for (int i = 0; i < batch; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, a, i & 1);
+        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, ad,
+                           (int)((queued + i) & 1));
       DAWN_HIP(hipGetLastError());
       *launches += batch;
       queued += batch;
       DAWN_HIP(hipEventRecord(w->ev1, w->stream));
-      DAWN_HIP(hipStreamSynchronize(w->stream));
-      if (w->h_st[1].done) {
+      int parity = -1;
+      for (unsigned spin = 1;; ++spin) {
+        const unsigned tag = __atomic_load_n(&w->h_m->end_tag, __ATOMIC_ACQUIRE);
+        if ((tag >> 1) == ad.seq) {
+          parity = (int)(tag & 1);
+          break;
+        }
+        if ((spin & 63) == 0) {
+          const hipError_t e = hipEventQuery(w->ev1);
+          if (e == hipSuccess) {
+            // the batch is over: the tag, if any, is in place
+            const unsigned t2 = __atomic_load_n(&w->h_m->end_tag, __ATOMIC_ACQUIRE);
+            if ((t2 >> 1) == ad.seq) parity = (int)(t2 & 1);
+            break;
+          }
+          if (e != hipErrorNotReady) DAWN_HIP(e);
+        }
+        __builtin_ia32_pause();
+      }
+      if (parity >= 0) {
         // launches this traversal needed: those that ran levels, then the end
-        const int need = w->h_st[1].launches + 1;
+        const int need = w->h_m->st[parity].launches + 1;
         g->launch_hint.store(std::max(need, hint - 1), std::memory_order_relaxed);
-        *final_parity = 1;
+        *final_parity = parity;
         return DAWN_OK;
       }
       batch = graph_levels;
@@ -1453,7 +1501,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
     *launches += graph_levels + (it == 0 ? 1 : 0);
     DAWN_HIP(hipEventRecord(w->ev1, w->stream));
     DAWN_HIP(hipStreamSynchronize(w->stream));
-    if (w->h_st[1].done) {
+    if (w->h_m->st[1].done) {
       *final_parity = 1;
       return DAWN_OK;
     }
@@ -1467,6 +1515,35 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
 static bool small_component(const GraphRec* g, const dawn_params& p, int32_t source) {
   return p.small_n > 0 && p.direction != 2 && !g->comp_size.empty() &&
          g->comp_size[(size_t)source] <= std::min(p.small_n, kCompMax);
+}
+
+// Launch shape of the level kernel on a graph of nw bitmap words: the
+// visited bitmap goes to LDS for pull levels when it fits next to the
+// kernel's own LDS and is at most kPullLdsMax bytes (every workgroup copies
+// it at each pull level; on R-MAT 20, 128 KiB, the copy costs what the
+// faster in-edge checks save).  Gives the dynamic LDS, the words copied and
+// the workgroups a CU holds.
+template <int BLOCK>
+static dawn_status level_shape(Ctx* ctx, int32_t nw, size_t* lds, int32_t* words, int* occ) {
+  hipFuncAttributes fa;
+  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
+  const size_t bitmap = (size_t)nw * 8;
+  *lds = 0;
+  *words = 0;
+  if (bitmap <= kPullLdsMax && fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
+    *lds = bitmap;
+    *words = nw;
+    // the largest dynamic LDS any graph's launch can ask for, so graphs
+    // sharing the kernel never lower each other's limit
+    DAWN_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&sssp_level<BLOCK>),
+        hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)std::min(kPullLdsMax, ctx->lds_per_block - fa.sharedSizeBytes)));
+  }
+  int o = 0;
+  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sssp_level<BLOCK>, BLOCK, *lds));
+  *occ = std::max(o, 1);
+  return DAWN_OK;
 }
 
 template <int BLOCK>
@@ -1488,23 +1565,16 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
     *final_parity = 1;
     return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, false);
   }
-  // the visited bitmap goes to LDS for pull levels when it fits next to the
-  // kernel's own LDS and is at most kPullLdsMax bytes (every workgroup copies
-  // it at each pull level; on R-MAT 20, 128 KiB, the copy costs what the
-  // faster in-edge checks save)
-  hipFuncAttributes fa;
-  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
-  const size_t bitmap = (size_t)a.nw * 8;
-  size_t shmem = 0;
-  if (bitmap <= kPullLdsMax && fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
-    shmem = bitmap;
-    a.lds_words = a.nw;
-    DAWN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sssp_level<BLOCK>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  }
-  int occ = 0;
-  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, shmem));
-  int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1)) : std::max(occ, 1);
+  // the shape depends on the graph and block size only: found once per
+  // workspace and block size
+  const int bi = BLOCK == 256 ? 0 : BLOCK == 512 ? 1 : 2;
+  if (w->shape_grid[bi] == 0)
+    DAWN_TRY(level_shape<BLOCK>(ctx, a.nw, &w->shape_lds[bi], &w->shape_words[bi],
+                                &w->shape_grid[bi]));
+  const size_t shmem = w->shape_lds[bi];
+  a.lds_words = w->shape_words[bi];
+  const int occ = w->shape_grid[bi];
+  const int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, occ) : occ;
   return run_levels<BLOCK>(ctx, g, w, a, per_cu * ctx->num_cu, shmem, p.driver,
                            std::max(p.graph_levels, 1), d_dist, source, launches, level_ms,
                            final_parity, clock_ms);
@@ -1551,7 +1621,12 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     DAWN_HIP(hipMemcpyAsync(&w->ctrl->dist, &w->h_ctrl->dist, sizeof(int32_t*) + sizeof(int),
                             hipMemcpyHostToDevice, w->stream));
   }
-  DAWN_HIP(hipEventRecord(w->ev0, w->stream));
+  // the direct-launch driver times a traversal by the GPU wall clock (the
+  // init kernel's start to the start of the launch that found the end), so
+  // its host wait never covers the launches queued past the end; the other
+  // drivers by events around everything they queue
+  const bool stamped = !small && p.driver == 3 && ctx->wall_khz > 0;
+  if (!stamped) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
     case 512: st = sssp_dispatch<512>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
@@ -1583,7 +1658,7 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     DAWN_HIP(hipMemcpyAsync(ldir.data(), w->level_dir, cap, hipMemcpyDeviceToHost, w->stream));
   }
   if (persistent || cap > 0) DAWN_HIP(hipStreamSynchronize(w->stream));
-  const LevelState& rs = persistent ? w->h_ctrl->st[fp] : w->h_st[fp];
+  const LevelState& rs = persistent ? w->h_ctrl->st[fp] : w->h_m->st[fp];
   if (rs.done != 1) w->poisoned = true;
   if (persistent && w->h_ctrl->bar.abort) return fail(DAWN_E_DEVICE, "grid barrier timed out");
   if (rs.done == 2) return fail(DAWN_E_DEVICE, "watchdog: more than n levels");
@@ -1596,6 +1671,8 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     float ms = 0.f;
     if (level_timing) {
       ms = (float)level_ms;
+    } else if (stamped) {
+      ms = (float)((double)(w->h_m->t_end - w->h_m->t_start) / (double)ctx->wall_khz);
     } else {
       DAWN_HIP(hipEventSynchronize(w->ev1));
       DAWN_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
@@ -1696,20 +1773,10 @@ static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, S
     DAWN_HIP(hipStreamSynchronize(s));
     return DAWN_OK;
   }
-  hipFuncAttributes fa;
-  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
-  const size_t bitmap = (size_t)a.nw * 8;
   size_t shmem = 0;
-  if (bitmap <= kPullLdsMax && fa.sharedSizeBytes + bitmap <= ctx->lds_per_block) {
-    shmem = bitmap;
-    a.lds_words = a.nw;
-    DAWN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sssp_level<BLOCK>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  }
-  int occ = 0;
-  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sssp_level<BLOCK>, BLOCK, shmem));
-  const int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, std::max(occ, 1))
-                                         : std::max(occ, 1);
+  int occ = 1;
+  DAWN_TRY(level_shape<BLOCK>(ctx, a.nw, &shmem, &a.lds_words, &occ));
+  const int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, occ) : occ;
   const int grid = per_cu * ctx->num_cu;
   // level launches queued per host check, as the direct-launch driver does
   const int hint = g->launch_hint.load(std::memory_order_relaxed);
