@@ -91,7 +91,8 @@ struct LevelState {
   long long mu;               // out-degree sum of the still-unvisited nodes
   int last_nonempty;          // last level that found a node
   int push_levels, pull_levels;
-  int launches;               // level launches that ran at least one level
+  int launches;               // launches that found the state unfinished (ran levels or
+                              //   found the end)
   unsigned prev_nf;           // nodes found by the level before the last
   u64 edges_total;
   u64 source_edges;

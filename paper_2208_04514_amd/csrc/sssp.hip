@@ -1133,7 +1133,7 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && !one_group) {
     LevelState out = st;
     if (!st.done && st.pull) out.cur ^= 1;
-    if (!st.done) out.launches += 1;
+    if (!st.done || ended) out.launches += 1;
     a.ctrl->st[parity] = out;
     report(a, parity, out, ended != 0);
   }
@@ -1337,6 +1337,11 @@ static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStre
   return DAWN_OK;
 }
 
+// Direct-launch driver: level launches queued beyond what the graph's recent
+// traversals needed (with none, R-MAT 20 calls ran out of launches often
+// enough to cost 25 us per call on average).
+constexpr int kSpareLaunches = 1;
+
 template <int BLOCK>
 static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& a, int grid,
                               size_t shmem, int driver, int graph_levels, int32_t* d_dist,
@@ -1430,7 +1435,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
                        source);
     *launches = 1;
     const int hint = g->launch_hint.load(std::memory_order_relaxed);
-    int batch = hint > 0 ? std::min(hint + 1, graph_levels * 4) : graph_levels;
+    int batch = hint > 0 ? std::min(hint + kSpareLaunches, graph_levels * 4) : graph_levels;
     long long queued = 0;
     while (queued <= max_launch) {
       for (int i = 0; i < batch; ++i)
@@ -1460,8 +1465,9 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
         __builtin_ia32_pause();
       }
       if (parity >= 0) {
-        // launches this traversal needed: those that ran levels, then the end
-        const int need = w->h_m->st[parity].launches + 1;
+        // launches this traversal needed: every one up to the one that
+        // found the end
+        const int need = w->h_m->st[parity].launches;
         g->launch_hint.store(std::max(need, hint - 1), std::memory_order_relaxed);
         *final_parity = parity;
         return DAWN_OK;
@@ -1793,7 +1799,7 @@ static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, S
     DAWN_HIP(hipMemcpyAsync(fin, &a.ctrl->st[1], sizeof(LevelState), hipMemcpyDeviceToHost, s));
     DAWN_HIP(hipStreamSynchronize(s));
     if (fin->done) {
-      g->launch_hint.store(std::max(fin->launches + 1, hint - 1), std::memory_order_relaxed);
+      g->launch_hint.store(std::max(fin->launches, hint - 1), std::memory_order_relaxed);
       return DAWN_OK;
     }
     batch = gl;
