@@ -151,14 +151,6 @@ __device__ __forceinline__ void emit_found_deg(const SsspArgs& a, int L, int v, 
   }
 }
 
-// emit_found with the out-degree loaded here.
-template <int BLOCK>
-__device__ __forceinline__ void emit_found(const SsspArgs& a, int L, int v, bool found,
-                                           Counters& c, WaveQueue& q) {
-  const int deg = found ? a.rp[v + 1] - a.rp[v] : 0;
-  emit_found_deg<BLOCK>(a, L, v, found, deg, c, q);
-}
-
 // List the chunks of the workgroup's staged big-degree nodes (every thread
 // of the workgroup calls it; resets the staging list).
 template <int BLOCK>
@@ -352,10 +344,21 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
   const unsigned gw = blockIdx.x * wpb + threadIdx.x / kWave;
   const unsigned nwaves = gridDim.x * wpb;
   PullScratch& sc = ps[threadIdx.x / kWave];
+  // the wave's next bitmap word (and its no-in-edge word) is loaded one
+  // iteration ahead, so a word's loads wait on nothing of the word before
+  u64 nword = 0, nnoin = 0;
+  if (gw < (unsigned)a.nw) {
+    nword = vin[gw];
+    nnoin = a.noin[gw];
+  }
   for (unsigned w = gw; w < (unsigned)a.nw; w += nwaves) {
-    const u64 word = vin[w];
+    const u64 word = nword;
     // nodes without in-edges can only be the source: treat them as settled
-    const u64 settled = word | a.noin[w];
+    const u64 settled = word | nnoin;
+    if (w + nwaves < (unsigned)a.nw) {
+      nword = vin[w + nwaves];
+      nnoin = a.noin[w + nwaves];
+    }
     const int v = (int)(w * kWave) + lane;
     const int valid_n = min(kWave, a.n - (int)(w * kWave));
     const u64 full = valid_n >= kWave ? ~0ull : ((1ull << valid_n) - 1ull);
@@ -364,11 +367,14 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
       continue;
     }
     bool found = false;
-    int cur = 0, e = 0;
+    int cur = 0, e = 0, deg = 0;
     const bool unvisited = lane < valid_n && !((settled >> lane) & 1ull);
     if (unvisited) {
       cur = a.ip[v];
       e = a.ip[v + 1];
+      // the out-degree, needed if the node is found, loaded with the in-list
+      // bounds rather than after the search
+      deg = a.rp[v + 1] - a.rp[v];
       // the lane's own first in-edges, four loads in flight per step
       const int lim = min(e, cur + a.lane_edges);
       for (; cur + 4 <= lim; cur += 4) {
@@ -423,7 +429,7 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
     }
     const u64 newbits = __ballot(found);
     if (lane == 0) vout[w] = word | newbits;
-    emit_found<BLOCK>(a, L, v, found, c, q);
+    emit_found_deg<BLOCK>(a, L, v, found, found ? deg : 0, c, q);
   }
 }
 
