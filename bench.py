@@ -388,9 +388,9 @@ def weighted_bench(D, ctx):
 
 
 def small_component_bench(D, ctx):
-    """Sources in small components (512 components of 16..2048 nodes): one
-    workgroup per source (small_n = 2048) vs the general level loop
-    (small_n = 0)."""
+    """Sources in small components (512 components of 16..2048 nodes): every
+    one on one workgroup (small_n = 2048), those in components of at most 512
+    nodes (the default), and none (small_n = 0, the general level loop)."""
     import torch
     import graphgen as gg
     g, src = gg.load_config("islands")
@@ -399,7 +399,7 @@ def small_component_bench(D, ctx):
     res = {"workload": f"islands: 512 symmetric components of 16..2048 nodes (n={g.n}, m={g.m}), "
                        f"{src.size} sources"}
     rows = {}
-    for label, sn in (("one_workgroup", 2048), ("level_loop", 0)):
+    for label, sn in (("one_workgroup", 2048), ("default_512", 512), ("level_loop", 0)):
         D.dawn_set_params(ctx, h, small_n=sn)
         D.dawn_sssp(ctx, h, int(src[0]), out=out)
         t0 = time.perf_counter()
@@ -411,7 +411,8 @@ def small_component_bench(D, ctx):
         t = time.perf_counter() - t0
         res[label] = {"us_per_source": round(t / src.size * 1e6, 1), "gteps": round(se / t / 1e9, 4)}
         rows[label] = out.cpu().numpy().copy()
-    res["same_last_row"] = bool(np.array_equal(rows["one_workgroup"], rows["level_loop"]))
+    res["same_last_row"] = bool(np.array_equal(rows["one_workgroup"], rows["level_loop"])
+                                and np.array_equal(rows["default_512"], rows["level_loop"]))
     D.dawn_graph_release(ctx, h)
     return res
 

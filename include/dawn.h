@@ -80,9 +80,10 @@ typedef struct dawn_run_stats {
   int64_t source_edges;       /* sum over sources of sum of outdeg(u), u reached */
   int64_t reached;            /* sum over sources of reached nodes (sources included) */
   double kernel_ms;           /* device time of the traversal: HIP events around its kernels;
-                                 dawn_sssp under driver 3: the GPU wall clock from the init
-                                 kernel's start to the start of the launch that found the
-                                 end (launches queued past the end are not counted) */
+                                 dawn_sssp under driver 3 and for a source traversed by one
+                                 workgroup (small_n): the GPU wall clock from the init
+                                 kernel's start to the point the end was found (launches
+                                 queued past the end are not counted) */
   double total_ms;            /* host wall time of the call */
   /* dawn_sssp only, optional inputs: when frontier_sizes is non-null it receives
    * the number of nodes found at level L (L = 0 .. min(levels, frontier_cap) - 1)
@@ -120,7 +121,9 @@ typedef struct dawn_params {
   int32_t graph_levels;       /* drivers 3, 4: level launches per host read-back (rounded up to even) */
   int32_t small_n;            /* a source whose weakly connected component has
                                  <= min(small_n, 2048) nodes is traversed by one workgroup
-                                 (0 = never; not when direction forces pull) */
+                                 (0 = never; not when direction forces pull; default 512:
+                                 on random components of mean degree 10 the one workgroup
+                                 wins up to about 700 nodes, the level loop above) */
   float batch_alpha;          /* batched: pull when (sum over frontier nodes of out-degree x
                                  nonzero 64-lane words) * batch_alpha >= n x words, else push */
   int32_t batch_lanes;        /* batched: sources per launch (64..4096, multiple of 64) */

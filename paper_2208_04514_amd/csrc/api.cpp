@@ -93,7 +93,7 @@ dawn_params default_params(const GraphRec& g) {
   p.alpha = 14.0f;
   p.beta = 24.0f;
   p.graph_levels = 16;
-  p.small_n = 2048;
+  p.small_n = 512;
   p.batch_alpha = 4.0f;
   p.batch_lanes = 4096;
   p.timing = 2;

@@ -605,31 +605,67 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
   if (leader) a.ctrl->st[1] = st;
 }
 
+// The state a launch of parity `parity` leaves, to the host mirror (one
+// thread).  `ended`: this launch found the end of the traversal, so the end
+// stamp and tag follow, the tag ordered after the rest by a system-scope
+// release.
+__device__ __forceinline__ void report(const SsspArgs& a, int parity, const LevelState& s,
+                                       bool ended) {
+  if (!a.hm) return;
+  a.hm->st[parity] = s;
+  if (ended) {
+    a.hm->t_end = wall_clock64();
+    __hip_atomic_store(&a.hm->end_tag, (a.seq << 1) | (unsigned)parity, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // ------------------------------------------------- one-workgroup traversal --
 // A source whose weakly connected component has at most kCompMax nodes reaches
 // at most that many: one workgroup runs its whole push level loop after the
-// grid-wide init kernel (dist = -1, visited = {source}).  The frontier lives
-// in LDS; a level's new nodes are deduplicated in an LDS hash set (so a node
-// found through several edges is claimed once without a global atomic per
-// edge), then marked visited and given their distance.
+// grid-wide init kernel (dist = -1).  The frontier lives in LDS, and so does
+// the visited set: an open-addressing hash set of every node found so far
+// (at most kCompMax in kCompHash slots, so probing always ends), which also
+// deduplicates a level's new nodes without a global atomic per edge.  A level
+// scans the frontier's degrees over the workgroup and gives each thread four
+// edges per step, their target loads in flight together.
 constexpr int kCompMax = 2048;
-constexpr int kCompHash = 4096;    // power of two >= 2 x kCompMax: probing always ends
+constexpr int kCompHash = 4096;    // power of two >= 2 x kCompMax
+
+// Insert v into the LDS hash set (Knuth's multiplicative hash, linear
+// probing); true if it was not there.
+__device__ __forceinline__ bool comp_insert(int32_t* set, int v) {
+  unsigned h = ((unsigned)v * 2654435761u) & (kCompHash - 1);
+  for (;;) {
+    const int old = atomicCAS(&set[h], -1, v);
+    if (old == -1) return true;
+    if (old == v) return false;
+    h = (h + 1) & (kCompHash - 1);
+  }
+}
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void sssp_component(SsspArgs a0) {
   SsspArgs a = a0;
   a.dist = a0.ctrl->dist;
-  // frontier and next: node, row start, out-degree
+  // frontier and next: node, row start, out-degree (the frontier's degrees
+  // become their inclusive prefix sums while it is expanded)
   __shared__ int32_t qa[kCompMax], qb[kCompMax], ra[kCompMax], rb[kCompMax], da[kCompMax],
       db[kCompMax];
-  __shared__ int32_t hset[kCompHash];
+  __shared__ int32_t seen[kCompHash];
   __shared__ unsigned nnew;
+  __shared__ int wscan[BLOCK / kWave];
+  __shared__ int ftotal;
   __shared__ u64 wsum[2][BLOCK / kWave];
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
   constexpr int NW = BLOCK / kWave;
+  constexpr int PER = kCompMax / BLOCK;    // frontier entries per thread in the scan
   const int src = a0.ctrl->source;
   int32_t *cur = qa, *nxt = qb, *cur_r = ra, *nxt_r = rb, *cur_d = da, *nxt_d = db;
+  for (int i = tid; i < kCompHash; i += BLOCK) seen[i] = -1;
+  __syncthreads();
   if (tid == 0) {
+    comp_insert(seen, src);
     qa[0] = src;
     ra[0] = a.rp[src];
     da[0] = a.rp[src + 1] - ra[0];
@@ -638,55 +674,70 @@ __global__ __launch_bounds__(BLOCK) void sssp_component(SsspArgs a0) {
   u64 edges_total = 0, source_edges = (u64)(a.rp[src + 1] - a.rp[src]), reached = 1;
   int L = 0, last = 0, expansions = 0;
   for (;;) {
-    for (int i = tid; i < kCompHash; i += BLOCK) hset[i] = -1;
     if (tid == 0) nnew = 0;
     __syncthreads();
     ++L;
     ++expansions;
-    // expand: each wave takes 64 frontier nodes and walks the union of their
-    // out-lists 64 edges a step (a lane finds its edge's node by binary
-    // search over the wave's degree prefix sums)
-    u64 my_edges = 0;
-    for (unsigned b = (unsigned)wv * kWave; b < fsize; b += NW * kWave) {
-      const unsigned i = b + (unsigned)lane;
-      int rs = 0, deg = 0;
-      if (i < fsize) {
-        rs = cur_r[i];
-        deg = cur_d[i];
-      }
-      const int incl = wave_incl_scan(deg);
-      const int total = __shfl(incl, kWave - 1, kWave);
-      if (lane == 0) my_edges += (u64)total;
-      for (int eb = 0; eb < total; eb += kWave) {
-        const int x = eb + lane;
-        const bool has = x < total;
-        const int j = wave_owner(incl, has ? x : total - 1);
-        const int inc_j = __shfl(incl, j, kWave);
-        const int deg_j = __shfl(deg, j, kWave);
-        const int rs_j = __shfl(rs, j, kWave);
-        if (!has) continue;
-        const int v = a.col[rs_j + (x - (inc_j - deg_j))];
-        if ((ld_relaxed(&a.vis0[v >> 6]) >> (v & 63)) & 1ull) continue;
-        unsigned h = ((unsigned)v * 2654435761u) & (kCompHash - 1);
-        for (;;) {
-          const int old = atomicCAS(&hset[h], -1, v);
-          if (old == -1) {
-            nxt[atomicAdd(&nnew, 1u)] = v;
-            break;
-          }
-          if (old == v) break;
-          h = (h + 1) & (kCompHash - 1);
-        }
-      }
+    // inclusive prefix sums of the frontier's degrees, in place: thread t
+    // sums entries t PER .. t PER + PER - 1, the workgroup scans the sums
+    int loc[PER];
+    int run = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const unsigned i = (unsigned)(tid * PER + k);
+      run += i < fsize ? cur_d[i] : 0;
+      loc[k] = run;
+    }
+    int incl = wave_incl_scan(run);
+    if (lane == kWave - 1) wscan[wv] = incl;
+    __syncthreads();
+    if (tid < kWave) {
+      const int y = tid < NW ? wscan[tid] : 0;
+      const int ys = wave_incl_scan(y);
+      if (tid < NW) wscan[tid] = ys - y;
+      if (tid == kWave - 1) ftotal = ys;
     }
     __syncthreads();
+    const int excl = incl - run + wscan[wv];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const unsigned i = (unsigned)(tid * PER + k);
+      if (i < fsize) cur_d[i] = excl + loc[k];
+    }
+    __syncthreads();
+    const int total = ftotal;
+    // expand: edge x of the union of the frontier's rows belongs to the
+    // smallest j with prefix[j] > x
+    for (int base = 0; base < total; base += 4 * BLOCK) {
+      int v[4];
+      bool has[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int x = base + q * BLOCK + tid;
+        has[q] = x < total;
+        v[q] = 0;
+        if (has[q]) {
+          int lo = 0, hi = (int)fsize - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cur_d[mid] > x) hi = mid; else lo = mid + 1;
+          }
+          const int before = lo ? cur_d[lo - 1] : 0;
+          v[q] = a.col[cur_r[lo] + (x - before)];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (has[q] && comp_insert(seen, v[q])) nxt[atomicAdd(&nnew, 1u)] = v[q];
+    }
+    u64 my_edges = tid == 0 ? (u64)total : 0ull;
+    __syncthreads();
     const unsigned found = nnew;
-    // mark the new nodes: distance, visited bit, out-degree sum
+    // mark the new nodes: distance, out-degree sum
     u64 my_mf = 0;
     for (unsigned i = (unsigned)tid; i < found; i += BLOCK) {
       const int v = nxt[i];
       a.dist[v] = L;
-      atom_or(&a.vis0[v >> 6], 1ull << (v & 63));
       const int rs = a.rp[v], d = a.rp[v + 1] - rs;
       nxt_r[i] = rs;
       nxt_d[i] = d;
@@ -740,21 +791,23 @@ __global__ __launch_bounds__(BLOCK) void sssp_component(SsspArgs a0) {
     st.last_nonempty = last;
     st.push_levels = expansions;
     st.pull_levels = 0;
+    st.launches = 1;
     st.prev_nf = 0;
     st.edges_total = edges_total;
     st.source_edges = source_edges;
     st.reached = reached;
     a.ctrl->st[1] = st;
+    report(a, 1, st, true);
   }
 }
 
 // ------------------------------------------------------ per-level drivers --
-// Initial state of one traversal (the source is read from the control block).
+// Initial state of one traversal.  The output row and source come as
+// arguments (direct launches), or with dist == nullptr from the control
+// block, where the host copied them (a captured graph or the persistent
+// kernel must not depend on them).  Direct launches publish them there for
+// the level kernels.
 template <int BLOCK>
-// The output row and source come as arguments (direct launches), or with
-// dist == nullptr from the control block, where the host copied them (a
-// captured graph or the persistent kernel must not depend on them).  Direct
-// launches publish them there for the level kernels.
 __global__ __launch_bounds__(BLOCK) void sssp_init(SsspArgs a0, int32_t* dist, int source) {
   if (a0.hm && blockIdx.x == 0 && threadIdx.x == 0) a0.hm->t_start = wall_clock64();
   SsspArgs a = a0;
@@ -822,20 +875,6 @@ __device__ __forceinline__ SlotSum read_level_slot(const SsspArgs& a, int level,
   return sum;
 }
 
-// The state a launch of parity `parity` leaves, to the host mirror (one
-// thread).  `ended`: this launch found the end of the traversal, so the end
-// stamp and tag follow, the tag ordered after the rest by a system-scope
-// release.
-__device__ __forceinline__ void report(const SsspArgs& a, int parity, const LevelState& s,
-                                       bool ended) {
-  if (!a.hm) return;
-  a.hm->st[parity] = s;
-  if (ended) {
-    a.hm->t_end = wall_clock64();
-    __hip_atomic_store(&a.hm->end_tag, (a.seq << 1) | (unsigned)parity, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-}
 
 // Frontier nodes the one-workgroup loop holds: one per thread, as a pair
 // (row start, out-degree) in each of two LDS lists.
@@ -1343,6 +1382,37 @@ static dawn_status capture(hipGraphExec_t* out, const std::function<void(hipStre
   return DAWN_OK;
 }
 
+// Number of the next traversal a workspace reports to its host mirror (never 0).
+static unsigned next_seq(SsspWs* w) {
+  w->seq = w->seq % 0x7fffffffu + 1;
+  return w->seq;
+}
+
+// Spin until traversal `seq` reports its end in the host mirror (*parity: the
+// parity of the state it left), or until the work queued before ev1 has all
+// run without it (*parity = -1).  The event is queried every 64 spins.
+static dawn_status wait_end(SsspWs* w, unsigned seq, int* parity) {
+  *parity = -1;
+  for (unsigned spin = 1;; ++spin) {
+    const unsigned tag = __atomic_load_n(&w->h_m->end_tag, __ATOMIC_ACQUIRE);
+    if ((tag >> 1) == seq) {
+      *parity = (int)(tag & 1);
+      return DAWN_OK;
+    }
+    if ((spin & 63) == 0) {
+      const hipError_t e = hipEventQuery(w->ev1);
+      if (e == hipSuccess) {
+        // the queued work is over: the tag, if any, is in place
+        const unsigned t2 = __atomic_load_n(&w->h_m->end_tag, __ATOMIC_ACQUIRE);
+        if ((t2 >> 1) == seq) *parity = (int)(t2 & 1);
+        return DAWN_OK;
+      }
+      if (e != hipErrorNotReady) DAWN_HIP(e);
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 // Direct-launch driver: level launches queued beyond what the graph's recent
 // traversals needed (with none, R-MAT 20 calls ran out of launches often
 // enough to cost 25 us per call on average).
@@ -1435,8 +1505,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
     // behind it overlap with what the caller does next.  The stream is waited
     // on only when a batch has run out without the end.
     SsspArgs ad = a;
-    w->seq = w->seq % 0x7fffffffu + 1;
-    ad.seq = w->seq;
+    ad.seq = next_seq(w);
     hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, ad, d_dist,
                        source);
     *launches = 1;
@@ -1452,24 +1521,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       queued += batch;
       DAWN_HIP(hipEventRecord(w->ev1, w->stream));
       int parity = -1;
-      for (unsigned spin = 1;; ++spin) {
-        const unsigned tag = __atomic_load_n(&w->h_m->end_tag, __ATOMIC_ACQUIRE);
-        if ((tag >> 1) == ad.seq) {
-          parity = (int)(tag & 1);
-          break;
-        }
-        if ((spin & 63) == 0) {
-          const hipError_t e = hipEventQuery(w->ev1);
-          if (e == hipSuccess) {
-            // the batch is over: the tag, if any, is in place
-            const unsigned t2 = __atomic_load_n(&w->h_m->end_tag, __ATOMIC_ACQUIRE);
-            if ((t2 >> 1) == ad.seq) parity = (int)(t2 & 1);
-            break;
-          }
-          if (e != hipErrorNotReady) DAWN_HIP(e);
-        }
-        __builtin_ia32_pause();
-      }
+      DAWN_TRY(wait_end(w, ad.seq, &parity));
       if (parity >= 0) {
         // launches this traversal needed: every one up to the one that
         // found the end
@@ -1563,13 +1615,20 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
                                  SsspArgs& a, int32_t source, int32_t* d_dist, int* launches,
                                  double* level_ms, int* final_parity, double* clock_ms) {
   if (small_component(g, p, source)) {
+    // the one-workgroup kernel reports its end to the host mirror too
     const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
-    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
+    SsspArgs ad = a;
+    ad.seq = next_seq(w);
+    hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, ad, d_dist,
                        source);
-    hipLaunchKernelGGL(sssp_component<BLOCK>, dim3(1), dim3(BLOCK), 0, w->stream, a);
+    hipLaunchKernelGGL(sssp_component<BLOCK>, dim3(1), dim3(BLOCK), 0, w->stream, ad);
     DAWN_HIP(hipGetLastError());
+    DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+    int parity = -1;
+    DAWN_TRY(wait_end(w, ad.seq, &parity));
+    if (parity < 0) return fail(DAWN_E_DEVICE, "one-workgroup traversal ended without a report");
     *launches = 2;
-    *final_parity = 1;
+    *final_parity = parity;
     return DAWN_OK;
   }
   if (p.driver == 1) {
@@ -1637,7 +1696,8 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
   // init kernel's start to the start of the launch that found the end), so
   // its host wait never covers the launches queued past the end; the other
   // drivers by events around everything they queue
-  const bool stamped = !small && p.driver == 3 && ctx->wall_khz > 0;
+  const bool mirrored = small || p.driver == 3;
+  const bool stamped = mirrored && ctx->wall_khz > 0;
   if (!stamped) DAWN_HIP(hipEventRecord(w->ev0, w->stream));
   dawn_status st;
   switch (p.block) {
@@ -1645,18 +1705,19 @@ dawn_status sssp_run(Ctx* ctx, GraphRec* g, const dawn_params& p, int32_t source
     case 1024: st = sssp_dispatch<1024>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
     default: st = sssp_dispatch<256>(ctx, g, w.get(), p, a, source, d_dist, &launches, lm, &fp, &clock_ms); break;
   }
-  // the level drivers record the end event after their last launch, before
-  // the host waits; the persistent kernel and the one-workgroup path here
-  if (!level_timing && (small || p.driver == 1)) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
+  // the level drivers and the one-workgroup path record the end event after
+  // their last launch, before the host waits; the persistent kernel here
+  if (!small && p.driver == 1) DAWN_HIP(hipEventRecord(w->ev1, w->stream));
   if (st != DAWN_OK) {
     hipStreamSynchronize(w->stream);
     w->poisoned = true;
     return st;
   }
   const uint64_t t_loop = now_ns();
-  // the per-level and graph drivers already read the final state back; the
-  // persistent driver's state (and its barrier's abort flag) is read here
-  const bool persistent = p.driver == 1 || small;
+  // the per-level and graph drivers and the one-workgroup path already read
+  // the final state back; the persistent driver's state (and its barrier's
+  // abort flag) is read here
+  const bool persistent = p.driver == 1 && !small;
   const int32_t cap = (stats && stats->frontier_cap > 0) ? std::min(stats->frontier_cap, w->lrec) : 0;
   std::vector<int32_t> lnf;
   std::vector<uint8_t> ldir;
