@@ -776,31 +776,46 @@ __device__ __forceinline__ void merge_level(const BatchArgs& a, int L) {
     }
     stage_chunks_wave(a, L, cstage, v0 + lane, deg, mine && deg >= a.big_b);
     __builtin_amdgcn_wave_barrier();
+    // four nodes' rows per group and step; the next step's rows are loaded
+    // before this step's atomic ORs are issued, so the wait for them never
+    // covers those atomics
+    int jq[4], dq[4];
+    bool okq[4];
+    u64 nb[4];
+    size_t idx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ib + q * npw + sub;
+      okq[q] = i < ie;
+      jq[q] = rank_j[wv][okq[q] ? i : ib];
+      dq[q] = __shfl(deg, jq[q], kWave);
+      idx[q] = (size_t)(v0 + jq[q]) * Ws + w;
+      nb[q] = (okq[q] && wok) ? nxt[idx[q]] : 0ull;
+    }
     for (int i0 = ib; i0 < ie; i0 += 4 * npw) {
-      int jq[4], dq[4];
-      bool okq[4];
-      u64 nb[4];
-      size_t idx[4];
+      int jn[4], dn[4];
+      bool okn[4];
+      u64 nbn[4];
+      size_t idn[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = i0 + q * npw + sub;
-        okq[q] = i < ie;
-        jq[q] = rank_j[wv][okq[q] ? i : ib];
-        dq[q] = __shfl(deg, jq[q], kWave);
-        idx[q] = (size_t)(v0 + jq[q]) * Ws + w;
-        nb[q] = (okq[q] && wok) ? nxt[idx[q]] : 0ull;
+        const int i = i0 + 4 * npw + q * npw + sub;
+        okn[q] = i < ie;
+        jn[q] = rank_j[wv][okn[q] ? i : ib];
+        dn[q] = __shfl(deg, jn[q], kWave);
+        idn[q] = (size_t)(v0 + jn[q]) * Ws + w;
+        nbn[q] = (okn[q] && wok) ? nxt[idn[q]] : 0ull;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        // the group's nonzero words of the node: its frontier word map
+        // the group's nonzero words of the node: its frontier word map, and
+        // the words of its visited row that may now be nonzero
         const u64 nzb = __ballot(nb[q] != 0);
         const u64 fm = (nzb >> ((sub * P) & 63)) & low_mask<P>();
         if (okq[q] && w == 0) {
           fmap[v0 + jq[q]] = fm;
           mfw += (u64)__popcll(fm) * (u64)dq[q];
-          // words of the visited row that may now be nonzero
-          const u64 vm = a.vmap[v0 + jq[q]];
-          if (fm & ~vm) atom_or(&a.vmap[v0 + jq[q]], fm);
+          if (fm) atom_or(&a.vmap[v0 + jq[q]], fm);
         }
       }
       // vis and the planes take their bits with atomic ORs that return
@@ -822,6 +837,14 @@ __device__ __forceinline__ void merge_level(const BatchArgs& a, int L) {
           se += pc * (u64)dq[q];
           act_acc |= nb[q];
         }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        jq[q] = jn[q];
+        dq[q] = dn[q];
+        okq[q] = okn[q];
+        nb[q] = nbn[q];
+        idx[q] = idn[q];
       }
     }
     __builtin_amdgcn_wave_barrier();
