@@ -177,6 +177,29 @@ def test_device_output_torch(ctx, upload):
         _check_row(g, s, got[r])
 
 
+def test_device_output_any_alignment(ctx):
+    """Device rows that start at every 4-byte offset within 16 bytes, on a
+    graph whose node count is not a multiple of 4: each row is exact and
+    nothing around it is written."""
+    import torch
+    g = gg.gen_uniform(1003, 8000, seed=17)
+    h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
+    try:
+        flat = torch.empty((g.n + 8,), dtype=torch.int32, device="cuda")
+        for off in range(4):
+            for s in (0, 1, 2, 3, 500, g.n - 1):
+                flat.fill_(7)
+                row = flat[off: off + g.n]
+                D.dawn_sssp(ctx, h, s, out=row)
+                torch.cuda.synchronize()
+                _check_row(g, s, row.cpu().numpy())
+                # nothing outside the row is written
+                rest = torch.cat([flat[:off], flat[off + g.n:]])
+                assert int(rest.ne(7).sum()) == 0
+    finally:
+        D.dawn_graph_release(ctx, h)
+
+
 def test_errors_leave_output_untouched(ctx, upload):
     h, g, src = upload("uniform4096")
     out = np.full(g.n, 123, np.int32)
