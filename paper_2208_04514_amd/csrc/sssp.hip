@@ -608,7 +608,11 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
 // The state a launch of parity `parity` leaves, to the host mirror (one
 // thread).  `ended`: this launch found the end of the traversal, so the end
 // stamp and tag follow, the tag ordered after the rest by a system-scope
-// release.
+// release, which also writes back this XCD's L2: the host returns on the tag
+// and its caller may read the distances at once.  Distances stored by other
+// waves of the workgroup must be complete before (their waves wait for
+// their stores ahead of the barrier that precedes the report); those of
+// earlier launches were written back when those launches ended.
 __device__ __forceinline__ void report(const SsspArgs& a, int parity, const LevelState& s,
                                        bool ended) {
   if (!a.hm) return;
@@ -777,6 +781,10 @@ __global__ __launch_bounds__(BLOCK) void sssp_component(SsspArgs a0) {
     if (lm == 0) break;   // the new nodes have no out-edge: nothing left to expand
     __syncthreads();
   }
+  // every wave's distance stores are complete before the end report's
+  // release (a workgroup barrier alone does not wait for them)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
   if (tid == 0) {
     if (a.lrec > 0) {
       a.level_nf[0] = 1;
@@ -1096,7 +1104,12 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
     nxt = sw;
   }
   // the other workgroups decided from the slot of the level before this
-  // launch's first one, which the hand-over below may overwrite
+  // launch's first one, which the hand-over below may overwrite.  Every wave
+  // first waits for its own stores (a workgroup barrier does not), so that
+  // the end report's release covers the distances of the last levels: the
+  // caller may read the row as soon as the report is seen, before this
+  // launch has ended
+  __builtin_amdgcn_s_waitcnt(0);
   wait_arrivals<BLOCK>(a, sh);
   LevelState fin = sh.st;
   if (!sh.arrived) fin.done = 2;
