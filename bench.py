@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # cache (paper_2208_04514_amd/tuned_params.json, written by dawn_autotune on
 # 32 other sources of the same graph; --autotune searches again live).
 PLAIN_KNOB_NAMES = ("driver", "graph_levels", "big_degree", "alpha", "beta", "block",
-                    "blocks_per_cu", "pull_lane_edges", "small_frontier_edges")
+                    "blocks_per_cu", "pull_lane_edges", "small_frontier_edges", "medium_edges",
+                    "medium_groups")
 BATCH_KNOB_NAMES = ("batch_alpha", "batch_big_degree", "batch_wide_scan", "batch_sparse_words")
 
 # Sources that define the level-step kernel: the HBM counter record under
@@ -417,19 +418,27 @@ def small_component_bench(D, ctx):
     return res
 
 
+GRID_MEDIUM = dict(medium_edges=16384, medium_groups=32, blocks_per_cu=0)
+
+
 def grid_bench(D, ctx, k_src=16):
     """The damaged 2048^2 grid (about 120 levels) under each level-loop
-    driver, and the no-shortcut grid (thousands of levels) under two."""
+    driver, and the no-shortcut grid (thousands of levels) under two; driver
+    3 also with medium push levels run on a few workgroups per launch."""
     import torch
     import graphgen as gg
     res = {}
-    for name, drivers, ks in (("grid2048", (1, 2, 3, 4), k_src), ("grid2048ns", (1, 3), 1)):
+    for name, drivers, ks in (("grid2048", (1, 2, 3, 4, "3m"), k_src), ("grid2048ns", (1, 3, "3m"), 1)):
         g, src = gg.load_config(name)
         h = D.dawn_graph_upload(ctx, g.row_ptr, g.col)
         out = torch.empty(g.n, dtype=torch.int32, device="cuda")
         entry = {}
         for drv in drivers:
-            D.dawn_set_params(ctx, h, driver=drv, graph_levels=32, blocks_per_cu=1)
+            kw = dict(driver=3 if drv == "3m" else drv, graph_levels=32, blocks_per_cu=1,
+                      medium_edges=0)
+            if drv == "3m":
+                kw.update(GRID_MEDIUM)
+            D.dawn_set_params(ctx, h, **kw)
             D.dawn_sssp(ctx, h, int(src[0]), out=out)
             t0 = time.perf_counter()
             se, lv = 0, []
@@ -439,10 +448,9 @@ def grid_bench(D, ctx, k_src=16):
                 lv.append(st["levels"])
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
-            entry[f"driver{drv}"] = {"ms_per_source": round(t / ks * 1e3, 3),
-                                     "gteps": round(se / t / 1e9, 3),
-                                     "us_per_level": round(t / sum(lv) * 1e6, 2),
-                                     "levels": lv}
+            entry["driver3_medium" if drv == "3m" else f"driver{drv}"] = {
+                "ms_per_source": round(t / ks * 1e3, 3), "gteps": round(se / t / 1e9, 3),
+                "us_per_level": round(t / sum(lv) * 1e6, 2), "levels": lv}
         res[name] = entry
         D.dawn_graph_release(ctx, h)
     return res

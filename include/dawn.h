@@ -143,6 +143,14 @@ typedef struct dawn_params {
                                  workgroup, which also runs the small push levels after it in
                                  the same launch with their frontiers in LDS
                                  (default 1024; -1: never) */
+  int32_t medium_edges;       /* single source, drivers 2-4: a push level whose frontier has
+                                 more out-edges than such a one-workgroup level and at most
+                                 this many runs on the first `medium_groups` workgroups of its
+                                 launch, which also run the push levels after it that qualify,
+                                 with a barrier between levels instead of a launch per level
+                                 (default 0: never; that keeps the level kernel without this
+                                 loop, which needs fewer registers) */
+  int32_t medium_groups;      /* workgroups of such levels (2..256; default 32) */
 } dawn_params;
 
 typedef struct dawn_graph_info {

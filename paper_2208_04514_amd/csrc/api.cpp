@@ -101,6 +101,8 @@ dawn_params default_params(const GraphRec& g) {
   p.batch_wide_scan = 48;
   p.batch_sparse_words = 4;
   p.small_frontier_edges = 1024;
+  p.medium_edges = 0;
+  p.medium_groups = 32;
   (void)g;
   return p;
 }
@@ -129,6 +131,9 @@ dawn_status check_params(const dawn_params& p) {
     return fail(DAWN_E_INVALID_ARG, "batch_sparse_words must be in [1, 4]");
   if (p.small_frontier_edges < -1)
     return fail(DAWN_E_INVALID_ARG, "small_frontier_edges must be >= -1");
+  if (p.medium_edges < 0) return fail(DAWN_E_INVALID_ARG, "medium_edges must be >= 0");
+  if (p.medium_groups < 2 || p.medium_groups > 256)
+    return fail(DAWN_E_INVALID_ARG, "medium_groups must be in [2, 256]");
   return DAWN_OK;
 }
 
@@ -371,7 +376,7 @@ dawn_status dawn_set_params(dawn_ctx* c, int32_t graph, const dawn_params* in) {
   KEEP(driver); KEEP(direction); KEEP(block); KEEP(big_degree); KEEP(pull_lane_edges);
   KEEP(alpha); KEEP(beta); KEEP(graph_levels); KEEP(batch_alpha); KEEP(batch_lanes);
   KEEP(timing); KEEP(batch_big_degree); KEEP(batch_wide_scan); KEEP(batch_sparse_words);
-  KEEP(small_frontier_edges);
+  KEEP(small_frontier_edges); KEEP(medium_groups);
 #undef KEEP
   DAWN_TRY(check_params(p));
   std::lock_guard<std::mutex> lk(g->mu);

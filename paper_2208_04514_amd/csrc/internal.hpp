@@ -94,6 +94,7 @@ struct LevelState {
   int launches;               // launches that found the state unfinished (ran levels or
                               //   found the end)
   unsigned prev_nf;           // nodes found by the level before the last
+  unsigned mbar;              // arrivals counted so far by the multi-workgroup level barrier
   u64 edges_total;
   u64 source_edges;
   u64 reached;
@@ -127,10 +128,13 @@ struct SsspCtrl {
   int pad;                    //   graphs do not depend on them
   LevelSlot slot[3];
   LevelState st[2];
-  // a launch that runs small levels on workgroup 0: every other workgroup
-  // adds one here (stripe blockIdx % kStripes) once it has read the counters
-  // it decides from; workgroup 0 waits for all of them before it writes any
-  // slot, then zeroes the count
+  // the barrier of multi-workgroup launches: arrivals, counted up through a
+  // traversal (zeroed by its init kernel)
+  alignas(kLine) unsigned mcount;
+  // a launch that runs its levels on some of its workgroups only (one or a
+  // few): every other workgroup adds one here (stripe blockIdx % kStripes)
+  // once it has read the counters it decides from; workgroup 0 waits for all
+  // of them before it writes a slot they read, then zeroes the count
   ArriveStripe arrive[kStripes];
 };
 
@@ -163,6 +167,10 @@ struct SsspArgs {
   int32_t lrec;
   int32_t lds_words;          // pull levels copy the visited bitmap (this many words,
                               //   = nw) into LDS; 0 = read it from global memory
+  int32_t medium_edges;       // push levels whose frontier has more out-edges than a small
+                              //   level and at most this many run on the first
+  int32_t medium_groups;      //   medium_groups workgroups of a launch, one after another
+                              //   with a barrier between them (0: never)
   int32_t small_edges;        // a push level whose frontier has at most this many out-edges
                               //   runs on one workgroup, with the small levels after it in
                               //   the same launch (0: never)
@@ -215,10 +223,11 @@ struct SsspWs {
   HostMirror* d_m = nullptr;    //   ... and its device address
   unsigned seq = 0;             // number of the last direct-launch traversal
   // launch shape of the level kernel on this graph, per block size (256, 512,
-  // 1024), found on first use: grid, dynamic LDS, bitmap words copied to LDS
-  int shape_grid[3] = {0, 0, 0};
-  size_t shape_lds[3] = {0, 0, 0};
-  int32_t shape_words[3] = {0, 0, 0};
+  // 1024) and variant (without, with medium levels), found on first use:
+  // grid, dynamic LDS, bitmap words copied to LDS
+  int shape_grid[6] = {0, 0, 0, 0, 0, 0};
+  size_t shape_lds[6] = {0, 0, 0, 0, 0, 0};
+  int32_t shape_words[6] = {0, 0, 0, 0, 0, 0};
   // HIP graph driver cache: init + levels, and levels alone for long runs
   hipGraphExec_t gexec = nullptr;
   hipGraphExec_t gexec_more = nullptr;

@@ -85,6 +85,26 @@ __device__ __forceinline__ int32_t* chunk_k(const SsspArgs& a, int level) {
 }
 
 // Move the staged entries to this workgroup's sub-queue of level L.  Wave-uniform.
+// Queue and chunk-list entries: plain accesses, or (CO) coherent ones, for
+// a level whose successor runs in the same launch on other XCDs.
+template <bool CO>
+__device__ __forceinline__ void q_store(int32_t* p, int32_t v) {
+  if constexpr (CO) {
+    st_relaxed(p, v);
+  } else {
+    *p = v;
+  }
+}
+template <bool CO>
+__device__ __forceinline__ int32_t q_load(const int32_t* p) {
+  if constexpr (CO) {
+    return ld_relaxed(p);
+  } else {
+    return *p;
+  }
+}
+
+template <bool CO>
 __device__ __forceinline__ void wq_flush(const SsspArgs& a, int L, WaveQueue& q) {
   if (q.cnt == 0) return;
   const int stripe = blockIdx.x % kStripes;
@@ -94,7 +114,7 @@ __device__ __forceinline__ void wq_flush(const SsspArgs& a, int L, WaveQueue& q)
   base = __shfl(base, 0, kWave);
   int32_t* dst = small_q(a, L) + (size_t)stripe * (size_t)a.n + base;
   __builtin_amdgcn_wave_barrier();
-  for (int i = lane; i < q.cnt; i += kWave) dst[i] = q.buf[i];
+  for (int i = lane; i < q.cnt; i += kWave) q_store<CO>(&dst[i], q.buf[i]);
   __builtin_amdgcn_wave_barrier();
   q.cnt = 0;
 }
@@ -102,7 +122,7 @@ __device__ __forceinline__ void wq_flush(const SsspArgs& a, int L, WaveQueue& q)
 // Record node v (claimed at level L by the calling lane when `found`, out-degree
 // deg) in the distance vector and in the next frontier.  Must be reached by the
 // whole wave.
-template <int BLOCK>
+template <int BLOCK, bool CO>
 __device__ __forceinline__ void emit_found_deg(const SsspArgs& a, int L, int v, bool found, int deg,
                                                Counters& c, WaveQueue& q) {
   if (found) {
@@ -116,7 +136,7 @@ __device__ __forceinline__ void emit_found_deg(const SsspArgs& a, int L, int v, 
     const int pos = q.cnt + __popcll(mask & lanes_below());
     if (small) q.buf[pos] = v;
     q.cnt += __popcll(mask);
-    if (q.cnt > kWaveBuf - kWave) wq_flush(a, L, q);
+    if (q.cnt > kWaveBuf - kWave) wq_flush<CO>(a, L, q);
   }
   // big-degree nodes (a middle level finds tens of thousands): staged in the
   // workgroup's LDS list, whose chunks are listed with one atomic on the
@@ -144,8 +164,8 @@ __device__ __forceinline__ void emit_found_deg(const SsspArgs& a, int L, int v, 
       int32_t* cu = chunk_u(a, L);
       int32_t* ck = chunk_k(a, L);
       for (int k = 0; k < rest; ++k) {
-        cu[gb + k] = v;
-        ck[gb + k] = (int32_t)k;
+        q_store<CO>(&cu[gb + k], v);
+        q_store<CO>(&ck[gb + k], k);
       }
     }
   }
@@ -153,7 +173,7 @@ __device__ __forceinline__ void emit_found_deg(const SsspArgs& a, int L, int v, 
 
 // List the chunks of the workgroup's staged big-degree nodes (every thread
 // of the workgroup calls it; resets the staging list).
-template <int BLOCK>
+template <int BLOCK, bool CO>
 __device__ __forceinline__ void flush_big(const SsspArgs& a, int L, WaveQueue& q) {
   __shared__ int wsum[BLOCK / kWave];
   __shared__ unsigned gbase;
@@ -185,8 +205,8 @@ __device__ __forceinline__ void flush_big(const SsspArgs& a, int L, WaveQueue& q
   int32_t* cu = chunk_u(a, L);
   int32_t* ck = chunk_k(a, L);
   for (int k = 0; k < nch; ++k) {
-    cu[b0 + k] = v;
-    ck[b0 + k] = (int32_t)k;
+    q_store<CO>(&cu[b0 + k], v);
+    q_store<CO>(&ck[b0 + k], k);
   }
 }
 
@@ -216,7 +236,7 @@ __device__ __forceinline__ int stripe_of(const unsigned* pre, unsigned i) {
 // Claim up to four targets per lane (has[i]): every visited word, then every
 // claiming atomic, then the claimed nodes' degrees are loaded as one batch
 // of independent requests before the nodes are recorded.  Wave-uniform call.
-template <int BLOCK>
+template <int BLOCK, bool CO>
 __device__ __forceinline__ void visit4(const SsspArgs& a, int L, u64* vis, const int* v,
                                        const bool* has, Counters& c, WaveQueue& q) {
   u64 w[4], old[4], bit[4];
@@ -236,7 +256,7 @@ __device__ __forceinline__ void visit4(const SsspArgs& a, int L, u64* vis, const
     deg[i] = claim[i] ? a.rp[v[i] + 1] - a.rp[v[i]] : 0;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) emit_found_deg<BLOCK>(a, L, v[i], claim[i], deg[i], c, q);
+  for (int i = 0; i < 4; ++i) emit_found_deg<BLOCK, CO>(a, L, v[i], claim[i], deg[i], c, q);
 }
 
 // Largest visited bitmap a pull level copies to LDS.
@@ -253,7 +273,7 @@ __device__ __forceinline__ unsigned small_split(unsigned nsmall, unsigned nwaves
 // pre: the sub-queue offsets of level L-1 in LDS; `nch` its chunk count, or
 // ~0u to have them read here.  The level's work is dealt over `nblk`
 // workgroups, this one being `bid` (the grid, or one workgroup alone).
-template <int BLOCK>
+template <int BLOCK, bool CO>
 __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQueue& q,
                           unsigned* pre, unsigned nch, unsigned bid, unsigned nblk) {
   const LevelSlot* in = &a.ctrl->slot[(L - 1) % 3];
@@ -277,15 +297,15 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
       has[i] = false;
       v[i] = 0;
       if (gi < nchunks) {
-        const int u = cu[gi];
-        const int start = a.rp[u] + ck[gi] * BLOCK;
+        const int u = q_load<CO>(&cu[gi]);
+        const int start = a.rp[u] + q_load<CO>(&ck[gi]) * BLOCK;
         const int end = min(start + BLOCK, a.rp[u + 1]);
         const int e = start + (int)threadIdx.x;
         has[i] = e < end;
         if (has[i]) v[i] = a.col[e];
       }
     }
-    visit4<BLOCK>(a, L, vis, v, has, c, q);
+    visit4<BLOCK, CO>(a, L, vis, v, has, c, q);
   }
 
   // small-degree nodes: groups of 64, the union of a group's rows walked 256
@@ -304,7 +324,7 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
     int rs = 0, deg = 0;
     if (i < nsmall) {
       const int s = stripe_of(pre, i);
-      const int u = q_in[(size_t)s * (size_t)a.n + (i - pre[s])];
+      const int u = q_load<CO>(&q_in[(size_t)s * (size_t)a.n + (i - pre[s])]);
       rs = a.rp[u];
       deg = a.rp[u + 1] - rs;
     }
@@ -324,7 +344,7 @@ __device__ void push_step(const SsspArgs& a, int L, u64* vis, Counters& c, WaveQ
         const int rs_j = __shfl(rs, j, kWave);
         v[i] = has[i] ? a.col[rs_j + (x - (inc_j - deg_j))] : 0;
       }
-      visit4<BLOCK>(a, L, vis, v, has, c, q);
+      visit4<BLOCK, CO>(a, L, vis, v, has, c, q);
     }
   }
 }
@@ -429,16 +449,16 @@ __device__ void pull_step(const SsspArgs& a, int L, const u64* vin, u64* vout, C
     }
     const u64 newbits = __ballot(found);
     if (lane == 0) vout[w] = word | newbits;
-    emit_found_deg<BLOCK>(a, L, v, found, found ? deg : 0, c, q);
+    emit_found_deg<BLOCK, false>(a, L, v, found, found ? deg : 0, c, q);
   }
 }
 
 // End of a level step for one workgroup: staged queue entries out, counters
 // summed over the workgroup and added to its stripe.
-template <int BLOCK>
+template <int BLOCK, bool CO>
 __device__ __forceinline__ void finish_level(const SsspArgs& a, int L, Counters& c, WaveQueue& q) {
-  wq_flush(a, L, q);
-  flush_big<BLOCK>(a, L, q);
+  wq_flush<CO>(a, L, q);
+  flush_big<BLOCK, CO>(a, L, q);
   block_sum3<BLOCK>(c.nf, c.mf, c.edges);
   if (threadIdx.x == 0) {
     LevelSlot* out = &a.ctrl->slot[L % 3];
@@ -468,11 +488,25 @@ __device__ __forceinline__ SlotSum sum_slot(const LevelSlot* s) {
   return r;
 }
 
-// Zero a slot with the calling workgroup's threads (tid / nthreads).
+// Zero a slot with the calling workgroup's threads (tid / nthreads): with
+// plain stores, or (CO) by atomics, done where every XCD counts, for a slot
+// that other XCDs count into before this launch ends.
+template <bool CO>
 __device__ __forceinline__ void zero_slot(LevelSlot* s, int tid, int nthreads) {
-  unsigned* w = (unsigned*)s;
-  const int words = (int)(sizeof(LevelSlot) / 4);
-  for (int i = tid; i < words; i += nthreads) w[i] = 0;
+  if constexpr (CO) {
+    for (int i = tid; i < kStripes; i += nthreads) {
+      SlotStripe& sp = s->s[i];
+      __hip_atomic_fetch_and(&sp.nf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_and(&sp.small_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_and(&sp.mf, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_and(&sp.edges, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) __hip_atomic_fetch_and(&s->big_chunks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    unsigned* w = (unsigned*)s;
+    const int words = (int)(sizeof(LevelSlot) / 4);
+    for (int i = tid; i < words; i += nthreads) w[i] = 0;
+  }
 }
 
 // Fold level st.level's counters into the state and choose level st.level+1.
@@ -543,6 +577,7 @@ __device__ void seed(const SsspArgs& a, int s) {
   st.pull_levels = 0;
   st.launches = 0;
   st.prev_nf = 0;
+  st.mbar = 0;
   st.edges_total = 0;
   st.source_edges = 0;
   st.reached = 0;
@@ -557,8 +592,9 @@ __device__ __forceinline__ void init_fill(const SsspArgs& a, int s) {
   for (unsigned w = tid; w < (unsigned)a.nw; w += nt)
     a.vis0[w] = (int)w == (s >> 6) ? (1ull << (s & 63)) : 0ull;
   if (blockIdx.x == 0) {
-    for (int i = 0; i < 3; ++i) zero_slot(&a.ctrl->slot[i], threadIdx.x, blockDim.x);
+    for (int i = 0; i < 3; ++i) zero_slot<false>(&a.ctrl->slot[i], threadIdx.x, blockDim.x);
     if (threadIdx.x < kStripes) a.ctrl->arrive[threadIdx.x].n = 0;
+    if (threadIdx.x == 0) a.ctrl->mcount = 0;
   }
 }
 
@@ -596,10 +632,10 @@ __global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a0) {
       pull_step<BLOCK>(a, L, vcur, vnext, c, q, ps);
       st.cur ^= 1;
     } else {
-      push_step<BLOCK>(a, L, vcur, c, q, pre, ~0u, blockIdx.x, gridDim.x);
+      push_step<BLOCK, false>(a, L, vcur, c, q, pre, ~0u, blockIdx.x, gridDim.x);
     }
-    finish_level<BLOCK>(a, L, c, q);
-    if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
+    finish_level<BLOCK, false>(a, L, c, q);
+    if (blockIdx.x == 0) zero_slot<false>(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
     if (!grid_sync(&a.ctrl->bar)) return;
   }
   if (leader) a.ctrl->st[1] = st;
@@ -904,7 +940,8 @@ __device__ __forceinline__ bool small_push(const SsspArgs& a, const LevelState& 
 // LDS of the one-workgroup loop besides its lists.
 struct SmallShared {
   int arrived;         // every other workgroup of the launch has read its counters
-  int go;              // 1 while the next level is small as well
+  int go;              // 1 while the next level is small (medium) as well
+  int ok;              // the multi-workgroup barrier completed in time
   unsigned n_next;     // nodes listed for the next level
   unsigned n_small;    // this level's small-degree queue entries
   unsigned n_chunks;   // this level's big-degree chunks
@@ -915,13 +952,13 @@ struct SmallShared {
   LevelState st;
 };
 
-// Workgroup 0 of a one-workgroup launch: wait (bounded) until every other
-// workgroup has counted itself in ctrl->arrive, then zero the count.  Every
-// thread calls it; sh.arrived = 0 if the wait timed out.
+// Workgroup 0 of a launch whose levels run on some workgroups only: wait
+// (bounded) until the `want` others have counted themselves in ctrl->arrive,
+// then zero the count.  Every thread calls it; sh.arrived = 0 if the wait
+// timed out.
 template <int BLOCK>
-__device__ __forceinline__ void wait_arrivals(const SsspArgs& a, SmallShared& sh) {
+__device__ __forceinline__ void wait_arrivals(const SsspArgs& a, SmallShared& sh, unsigned want) {
   if (threadIdx.x == 0) {
-    const unsigned want = gridDim.x - 1;
     const unsigned long long t0 = wall_clock64();
     int ok = 1;
     for (;;) {
@@ -1110,7 +1147,7 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
   // caller may read the row as soon as the report is seen, before this
   // launch has ended
   __builtin_amdgcn_s_waitcnt(0);
-  wait_arrivals<BLOCK>(a, sh);
+  wait_arrivals<BLOCK>(a, sh, gridDim.x - 1);
   LevelState fin = sh.st;
   if (!sh.arrived) fin.done = 2;
   if (fin.done) {
@@ -1129,7 +1166,7 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
     unsigned* w = (unsigned*)&sl->s[1];
     const int words = (int)((sizeof(SlotStripe) * (kStripes - 1)) / 4);
     for (int i = t; i < words; i += BLOCK) w[i] = 0;
-    zero_slot(&a.ctrl->slot[(L + 1) % 3], t, BLOCK);
+    zero_slot<false>(&a.ctrl->slot[(L + 1) % 3], t, BLOCK);
   }
   if (t == 0) {
     SlotStripe& s0 = a.ctrl->slot[L % 3].s[0];
@@ -1143,7 +1180,16 @@ __device__ __forceinline__ void small_levels(const SsspArgs& a, LevelState st, i
   }
 }
 
-template <int BLOCK>
+// Whether the push level decided in st (frontier sums `sum`) runs on a few
+// workgroups with the levels after it: more out-edges than a one-workgroup
+// level takes and at most a.medium_edges.
+__device__ __forceinline__ bool medium_push(const SsspArgs& a, const LevelState& st,
+                                            const SlotSum& sum) {
+  return a.medium_edges > 0 && a.medium_groups > 1 && !st.done && !st.pull &&
+         sum.mf <= (u64)a.medium_edges;
+}
+
+template <int BLOCK, bool MEDIUM>
 __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   SsspArgs a = a0;
   a.dist = a0.ctrl->dist;
@@ -1151,7 +1197,7 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   __shared__ unsigned pre[kStripes + 1];
   __shared__ PullScratch ps[BLOCK / kWave];
   __shared__ LevelState sst;
-  __shared__ int idle, small, ended;
+  __shared__ int idle, small, medium, ended;
   __shared__ int32_t big_v[BLOCK], big_c[BLOCK];
   __shared__ unsigned big_n, nchunks;
   if (threadIdx.x < kWave) {
@@ -1161,11 +1207,12 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
       big_n = 0;
       ended = 0;
       LevelState st = st0;
-      int sm = 0;
+      int sm = 0, md = 0;
       if (!st.done) {
         decide(a, st, sum, blockIdx.x == 0);
         ended = st.done ? 1 : 0;
         sm = small_push<BLOCK>(a, st, sum) ? 1 : 0;
+        if constexpr (MEDIUM) md = !sm && gridDim.x > 1 && medium_push(a, st, sum) ? 1 : 0;
         // a push level with nothing for this workgroup lets it leave at once
         const unsigned nwaves = gridDim.x * (BLOCK / kWave);
         const unsigned nvirt = (pre[kStripes] + kWave - 1) / kWave *
@@ -1173,17 +1220,20 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
         idle = !st.done && !st.pull && blockIdx.x * (BLOCK / kWave) >= nvirt &&
                blockIdx.x >= nchunks;
         if (sm) idle = blockIdx.x != 0;
+        if (md) idle = blockIdx.x >= min(gridDim.x, (unsigned)a.medium_groups);
       } else {
         idle = 1;
       }
       small = sm;
+      medium = md;
       sst = st;
     }
   }
   __syncthreads();
   LevelState st = sst;
   const bool one_group = small != 0;
-  if (one_group && blockIdx.x != 0) {
+  const bool few_groups = MEDIUM && medium != 0;
+  if ((one_group && blockIdx.x != 0) || (few_groups && idle)) {
     // counted in: workgroup 0 may now overwrite the counters read above
     if (threadIdx.x == 0) atom_add(&a.ctrl->arrive[blockIdx.x % kStripes].n, 1u);
     return;
@@ -1197,32 +1247,116 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
   }
   if (st.done) return;
   const int L0 = st.level;
-  if (blockIdx.x == 0) zero_slot(&a.ctrl->slot[(L0 + 1) % 3], threadIdx.x, BLOCK);
+  if (blockIdx.x == 0) zero_slot<MEDIUM>(&a.ctrl->slot[(L0 + 1) % 3], threadIdx.x, BLOCK);
   if (idle) return;
   WaveQueue q{qbuf[threadIdx.x / kWave], 0, big_v, big_c, &big_n};
-  Counters c{0, 0, 0};
   u64* vcur = st.cur ? a.vis1 : a.vis0;
-  if (!one_group) {
-    if (st.pull) {
-      u64* vnext = st.cur ? a.vis0 : a.vis1;
-      const u64* look = vcur;
-      if (a.lds_words) {
-        // every in-edge check of the sweep reads the bitmap: copy it to LDS
-        extern __shared__ u64 lds_vis[];
-        for (int i = threadIdx.x; i < a.lds_words; i += BLOCK) lds_vis[i] = vcur[i];
-        __syncthreads();
-        look = lds_vis;
+  if (!few_groups) {
+    Counters c{0, 0, 0};
+    if (!one_group) {
+      if (st.pull) {
+        u64* vnext = st.cur ? a.vis0 : a.vis1;
+        const u64* look = vcur;
+        if (a.lds_words) {
+          // every in-edge check of the sweep reads the bitmap: copy it to LDS
+          extern __shared__ u64 lds_vis[];
+          for (int i = threadIdx.x; i < a.lds_words; i += BLOCK) lds_vis[i] = vcur[i];
+          __syncthreads();
+          look = lds_vis;
+        }
+        pull_step<BLOCK>(a, L0, look, vnext, c, q, ps);
+      } else {
+        push_step<BLOCK, MEDIUM>(a, L0, vcur, c, q, pre, nchunks, blockIdx.x, gridDim.x);
       }
-      pull_step<BLOCK>(a, L0, look, vnext, c, q, ps);
-    } else {
-      push_step<BLOCK>(a, L0, vcur, c, q, pre, nchunks, blockIdx.x, gridDim.x);
+      finish_level<BLOCK, MEDIUM>(a, L0, c, q);
+      return;
     }
-    finish_level<BLOCK>(a, L0, c, q);
+    st.launches += 1;
+    __shared__ SmallShared sh;
+    small_levels<BLOCK>(a, st, parity, vcur, pre, nchunks, &qbuf[0][0], sh);
     return;
   }
-  st.launches += 1;
-  __shared__ SmallShared sh;
-  small_levels<BLOCK>(a, st, parity, vcur, pre, nchunks, &qbuf[0][0], sh);
+  if constexpr (MEDIUM) {
+    // A medium session: the first K workgroups run this push level and the
+    // medium push levels after it, one after another.  A level's work is
+    // dealt over the K workgroups as a grid-wide step deals it over the
+    // grid; between levels they meet at a counting barrier (ctrl->mcount,
+    // which only grows during a traversal: the k-th barrier of a session
+    // that found it at st.mbar waits for st.mbar + k K).  What one level
+    // hands to the next (queue entries, chunk lists, counters) is written
+    // with coherent stores or atomics and read with coherent loads, and
+    // every wave waits for its own stores before it arrives, so the barrier
+    // needs no cache write-back; distances are plain stores nothing reads
+    // during the traversal.  Each workgroup reads the level's counters and
+    // takes the same decision.  When the next level is not a medium push
+    // level (a pull level, a larger frontier, or the end), the state stays
+    // at the last level run, so the next launch folds its counters, takes
+    // the same decision and, at the end, reports it once every distance of
+    // this launch has been written back.
+    __shared__ SmallShared sh;
+    const unsigned K = min(gridDim.x, (unsigned)a.medium_groups);
+    const unsigned base = st.mbar;
+    if (threadIdx.x == 0) {
+      LevelState run = st;
+      run.launches += 1;
+      sh.st = run;
+      sh.ok = 1;
+    }
+    unsigned gen = 0;
+    bool waited = false;
+    int L = L0;
+    for (;;) {
+      Counters c{0, 0, 0};
+      push_step<BLOCK, true>(a, L, vcur, c, q, pre, nchunks, blockIdx.x, K);
+      finish_level<BLOCK, true>(a, L, c, q);
+      ++gen;
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        atom_add(&a.ctrl->mcount, 1u);
+        const unsigned long long t0 = wall_clock64();
+        while (ld_relaxed(&a.ctrl->mcount) - base < gen * K) {
+          if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
+            sh.ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __syncthreads();
+      if (!sh.ok) break;
+      if (threadIdx.x < kWave) {
+        const SlotSum sum = read_level_slot(a, L, pre, &nchunks);
+        if (threadIdx.x == 0) {
+          LevelState nx = sh.st;
+          decide(a, nx, sum, blockIdx.x == 0);
+          const int go = medium_push(a, nx, sum) ? 1 : 0;
+          sh.go = go;
+          if (go) sh.st = nx;   // else the state stays at level L
+        }
+      }
+      __syncthreads();
+      if (!sh.go) break;
+      L = sh.st.level;
+      if (blockIdx.x == 0) {
+        // the slot level L + 1 counts into held the counters of level L - 2,
+        // which the workgroups that left read before they left
+        if (!waited) wait_arrivals<BLOCK>(a, sh, gridDim.x - K);
+        waited = true;
+        zero_slot<true>(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
+      }
+    }
+    if (blockIdx.x != 0) return;
+    if (!waited) wait_arrivals<BLOCK>(a, sh, gridDim.x - K);
+    if (threadIdx.x == 0) {
+      LevelState hand = sh.st;
+      hand.mbar = base + gen * K;
+      const bool broken = !sh.ok || !sh.arrived;
+      if (broken) hand.done = 2;
+      a.ctrl->st[parity] = hand;
+      report(a, parity, hand, broken);
+    }
+  }
 }
 
 // In timing mode (a.clk set) every workgroup stamps its start and end with
@@ -1230,11 +1364,14 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
 // hundreds of workgroups do not queue on one line): the launch's own
 // duration, without its dispatch gap, is the latest end minus the earliest
 // start over the stripes.
-template <int BLOCK>
+// MEDIUM: the variant that can run medium push levels on a few workgroups
+// (its loop around the push step costs registers, so a graph whose levels
+// never qualify keeps the variant without it).
+template <int BLOCK, bool MEDIUM>
 __global__ __launch_bounds__(BLOCK) void sssp_level(SsspArgs a0, int parity) {
   unsigned long long* line = a0.clk ? a0.clk + (blockIdx.x % kClkStripes) * kClkWords : nullptr;
   if (line && threadIdx.x == 0) atomicMin(&line[0], (unsigned long long)wall_clock64());
-  level_step<BLOCK>(a0, parity);
+  level_step<BLOCK, MEDIUM>(a0, parity);
   if (line) {
     __syncthreads();
     if (threadIdx.x == 0) atomicMax(&line[1], (unsigned long long)wall_clock64());
@@ -1251,6 +1388,15 @@ __global__ void clk_reset(unsigned long long* clk, int launches) {
 }
 
 // ------------------------------------------------------------------ host --
+using LevelKernel = void (*)(SsspArgs, int);
+
+// The level kernel for these arguments: the variant with the medium-level
+// loop when the medium bound is set.
+template <int BLOCK>
+static LevelKernel level_kernel(const SsspArgs& a) {
+  return a.medium_edges > 0 ? sssp_level<BLOCK, true> : sssp_level<BLOCK, false>;
+}
+
 SsspWs::~SsspWs() {
   // a direct-launch traversal returns once its end is reported, while level
   // launches queued past the end (they only carry the final state) may still
@@ -1352,6 +1498,8 @@ static void fill_args(SsspArgs& a, GraphRec* g, SsspWs* w, const dawn_params& p,
   a.big_degree = std::max(p.big_degree, 64);
   a.lane_edges = std::max(p.pull_lane_edges, 1);
   a.small_edges = std::max(p.small_frontier_edges, 0);
+  a.medium_edges = std::max(p.medium_edges, 0);
+  a.medium_groups = std::max(p.medium_groups, 2);
   a.level_nf = w->level_nf;
   a.level_dir = w->level_dir;
   a.lrec = w->lrec;
@@ -1438,6 +1586,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
                               double* clock_ms) {
   const int fill_grid = std::max(1, std::min((a.n + BLOCK - 1) / BLOCK, ctx->num_cu * 8));
   const long long max_launch = (long long)a.n + 2;
+  const LevelKernel kern = level_kernel<BLOCK>(a);
   if (driver == 2) {
     hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, w->stream, a, d_dist,
                        source);
@@ -1465,10 +1614,10 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       if (level_ms) {
         // events attached to the dispatch itself: their timestamps are the
         // kernel's own begin and end, without the marker packets' dispatch gap
-        hipExtLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), (uint32_t)shmem,
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), (uint32_t)shmem,
                               w->stream, w->ev0, w->ev1, 0, al, parity);
       } else {
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, al,
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), shmem, w->stream, al,
                            parity);
       }
       DAWN_HIP(hipGetLastError());
@@ -1527,7 +1676,7 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
     long long queued = 0;
     while (queued <= max_launch) {
       for (int i = 0; i < batch; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, w->stream, ad,
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), shmem, w->stream, ad,
                            (int)((queued + i) & 1));
       DAWN_HIP(hipGetLastError());
       *launches += batch;
@@ -1562,11 +1711,11 @@ static dawn_status run_levels(Ctx* ctx, GraphRec* g, SsspWs* w, const SsspArgs& 
       hipLaunchKernelGGL(sssp_init<BLOCK>, dim3(fill_grid), dim3(BLOCK), 0, cs, a,
                          (int32_t*)nullptr, 0);
       for (int i = 0; i < graph_levels; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
     }));
     DAWN_TRY(capture(&w->gexec_more, [&](hipStream_t cs) {
       for (int i = 0; i < graph_levels; ++i)
-        hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), shmem, cs, a, i & 1);
     }));
     w->gexec_levels = graph_levels;
     w->gexec_block = BLOCK;
@@ -1601,9 +1750,10 @@ static bool small_component(const GraphRec* g, const dawn_params& p, int32_t sou
 // faster in-edge checks save).  Gives the dynamic LDS, the words copied and
 // the workgroups a CU holds.
 template <int BLOCK>
-static dawn_status level_shape(Ctx* ctx, int32_t nw, size_t* lds, int32_t* words, int* occ) {
+static dawn_status level_shape(Ctx* ctx, LevelKernel kern, int32_t nw, size_t* lds,
+                               int32_t* words, int* occ) {
   hipFuncAttributes fa;
-  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sssp_level<BLOCK>)));
+  DAWN_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)));
   const size_t bitmap = (size_t)nw * 8;
   *lds = 0;
   *words = 0;
@@ -1613,12 +1763,12 @@ static dawn_status level_shape(Ctx* ctx, int32_t nw, size_t* lds, int32_t* words
     // the largest dynamic LDS any graph's launch can ask for, so graphs
     // sharing the kernel never lower each other's limit
     DAWN_HIP(hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&sssp_level<BLOCK>),
+        reinterpret_cast<const void*>(kern),
         hipFuncAttributeMaxDynamicSharedMemorySize,
         (int)std::min(kPullLdsMax, ctx->lds_per_block - fa.sharedSizeBytes)));
   }
   int o = 0;
-  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sssp_level<BLOCK>, BLOCK, *lds));
+  DAWN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, BLOCK, *lds));
   *occ = std::max(o, 1);
   return DAWN_OK;
 }
@@ -1649,12 +1799,12 @@ static dawn_status sssp_dispatch(Ctx* ctx, GraphRec* g, SsspWs* w, const dawn_pa
     *final_parity = 1;
     return launch_persistent<BLOCK>(ctx, w, a, p.blocks_per_cu, false);
   }
-  // the shape depends on the graph and block size only: found once per
-  // workspace and block size
-  const int bi = BLOCK == 256 ? 0 : BLOCK == 512 ? 1 : 2;
+  // the shape depends on the graph, block size and kernel variant only:
+  // found once per workspace, block size and variant
+  const int bi = (BLOCK == 256 ? 0 : BLOCK == 512 ? 1 : 2) * 2 + (a.medium_edges > 0 ? 1 : 0);
   if (w->shape_grid[bi] == 0)
-    DAWN_TRY(level_shape<BLOCK>(ctx, a.nw, &w->shape_lds[bi], &w->shape_words[bi],
-                                &w->shape_grid[bi]));
+    DAWN_TRY(level_shape<BLOCK>(ctx, level_kernel<BLOCK>(a), a.nw, &w->shape_lds[bi],
+                                &w->shape_words[bi], &w->shape_grid[bi]));
   const size_t shmem = w->shape_lds[bi];
   a.lds_words = w->shape_words[bi];
   const int occ = w->shape_grid[bi];
@@ -1861,7 +2011,8 @@ static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, S
   }
   size_t shmem = 0;
   int occ = 1;
-  DAWN_TRY(level_shape<BLOCK>(ctx, a.nw, &shmem, &a.lds_words, &occ));
+  const LevelKernel kern = level_kernel<BLOCK>(a);
+  DAWN_TRY(level_shape<BLOCK>(ctx, kern, a.nw, &shmem, &a.lds_words, &occ));
   const int per_cu = p.blocks_per_cu > 0 ? std::min(p.blocks_per_cu, occ) : occ;
   const int grid = per_cu * ctx->num_cu;
   // level launches queued per host check, as the direct-launch driver does
@@ -1871,7 +2022,7 @@ static dawn_status noalloc_levels(Ctx* ctx, GraphRec* g, const dawn_params& p, S
   batch += batch & 1;
   for (long long queued = 0; queued <= (long long)a.n + 2;) {
     for (int i = 0; i < batch; ++i)
-      hipLaunchKernelGGL(sssp_level<BLOCK>, dim3(grid), dim3(BLOCK), shmem, s, a, i & 1);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), shmem, s, a, i & 1);
     DAWN_HIP(hipGetLastError());
     *launches += batch;
     queued += batch;

@@ -175,6 +175,12 @@ dawn_status autotune(Ctx* ctx, GraphRec* g, const int32_t* sources, int32_t k, u
     if (st == DAWN_OK)
       st = one(variants([](dawn_params& p, double v) { p.small_frontier_edges = (int)v; },
                         {-1, 128, 256, 512, 1024}));
+    if (st == DAWN_OK && cur.driver >= 2)
+      st = one(variants([](dawn_params& p, double v) { p.medium_edges = (int)v; },
+                        {0, 4096, 16384, 65536}));
+    if (st == DAWN_OK && cur.medium_edges > 0)
+      st = one(variants([](dawn_params& p, double v) { p.medium_groups = (int)v; },
+                        {8, 16, 32, 64}));
   }
   if (st == DAWN_OK && (what & 2)) {
     t.batched = true;

@@ -78,6 +78,7 @@ class Params(ctypes.Structure):
         ("batch_lanes", ctypes.c_int32), ("timing", ctypes.c_int32),
         ("batch_big_degree", ctypes.c_int32), ("batch_wide_scan", ctypes.c_int32),
         ("batch_sparse_words", ctypes.c_int32), ("small_frontier_edges", ctypes.c_int32),
+        ("medium_edges", ctypes.c_int32), ("medium_groups", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

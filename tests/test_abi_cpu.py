@@ -38,9 +38,9 @@ def test_struct_layouts_match_header():
 int main(void) {
   printf("%zu %zu %zu\n", sizeof(dawn_run_stats), offsetof(dawn_run_stats, frontier_cap),
          offsetof(dawn_run_stats, kernel_clock_ms));
-  printf("%zu %zu %zu\n",
+  printf("%zu %zu %zu %zu\n",
          sizeof(dawn_params), offsetof(dawn_params, timing),
-         offsetof(dawn_params, small_frontier_edges));
+         offsetof(dawn_params, small_frontier_edges), offsetof(dawn_params, medium_groups));
   printf("%zu %zu %zu %zu\n", sizeof(dawn_graph_info), offsetof(dawn_graph_info, device_bytes),
          sizeof(dawn_query_stats), offsetof(dawn_query_stats, batch_peak));
   return 0;
@@ -56,7 +56,7 @@ int main(void) {
     got = list(map(int, out))
     want = [ctypes.sizeof(D.RunStats), D.RunStats.frontier_cap.offset,
             D.RunStats.kernel_clock_ms.offset, ctypes.sizeof(D.Params), D.Params.timing.offset,
-            D.Params.small_frontier_edges.offset,
+            D.Params.small_frontier_edges.offset, D.Params.medium_groups.offset,
             ctypes.sizeof(D.GraphInfo), D.GraphInfo.device_bytes.offset,
             ctypes.sizeof(D.QueryStats), D.QueryStats.batch_peak.offset]
     assert got == want

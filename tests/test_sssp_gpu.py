@@ -59,6 +59,14 @@ VARIANTS = [
     dict(driver=2, direction=1, small_frontier_edges=1 << 30),
     dict(driver=4, direction=3, graph_levels=6, small_frontier_edges=1 << 30, block=256),
     dict(driver=3, direction=3, graph_levels=4, small_frontier_edges=64),
+    # medium push levels on a few workgroups of a launch: the default bound,
+    # every push level past the one-workgroup ones (two workgroups), with the
+    # one-workgroup levels off, and under the per-level and graph drivers
+    dict(driver=3, direction=3, medium_edges=65536),
+    dict(driver=3, direction=1, graph_levels=4, medium_edges=1 << 30, medium_groups=2),
+    dict(driver=3, direction=3, medium_edges=1 << 30, small_frontier_edges=-1, medium_groups=64),
+    dict(driver=2, direction=1, medium_edges=4096, medium_groups=8, block=1024),
+    dict(driver=4, direction=3, graph_levels=6, medium_edges=65536, block=256),
 ]
 
 
@@ -267,13 +275,18 @@ def test_full_size(ctx, upload, name):
         assert st["source_edges"] == int(deg[want[r] >= 0].sum())
         assert st["frontier_sizes"] == np.bincount(want[r][want[r] >= 0], minlength=lv).tolist()
     _say(f"  levels {min(s['levels'] for s in stats)}..{max(s['levels'] for s in stats)}")
-    # the other drivers on one source
+    # the other drivers on one source, and medium push levels on four sources
     saved = D.dawn_get_params(ctx, h)
     try:
         for driver in (1, 2, 4):
             D.dawn_set_params(ctx, h, driver=driver, graph_levels=32)
             got, st = D.dawn_sssp(ctx, h, int(src[0]))
             _check_row(g, src[0], got)
+        D.dawn_set_params(ctx, h, driver=3, graph_levels=32, medium_edges=65536)
+        for r in range(4):
+            got, st = D.dawn_sssp(ctx, h, int(src[r]), frontier_cap=8192)
+            assert np.array_equal(got, want[r]), f"medium levels, source {src[r]}"
+            assert st["frontier_sizes"] == stats[r]["frontier_sizes"]
     finally:
         D.dawn_set_params(ctx, h, **saved)
 

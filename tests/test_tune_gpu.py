@@ -42,7 +42,8 @@ def test_set_params_validation(ctx, upload):
     before = D.dawn_get_params(ctx, h)
     for bad in (dict(driver=9), dict(block=128), dict(batch_lanes=100), dict(big_degree=10),
                 dict(timing=1, driver=3), dict(batch_big_degree=32), dict(batch_wide_scan=600),
-                dict(batch_sparse_words=5), dict(small_frontier_edges=-3)):
+                dict(batch_sparse_words=5), dict(small_frontier_edges=-3),
+                dict(medium_edges=-1), dict(medium_groups=1), dict(medium_groups=300)):
         with pytest.raises(D.DawnError) as ei:
             D.dawn_set_params(ctx, h, **bad)
         assert ei.value.status == D.DAWN_E_INVALID_ARG
@@ -81,13 +82,19 @@ def test_plain_knob_candidates_bit_exact(ctx, upload, name):
     saved = D.dawn_get_params(ctx, h)
     try:
         for knob, vals in (("small_frontier_edges", (-1, 128, 256, 512, 1024)),
-                           ("big_degree", (128, 256, 512, 1024, 2048, 8192))):
+                           ("big_degree", (128, 256, 512, 1024, 2048, 8192)),
+                           ("medium_edges", (0, 4096, 16384, 65536))):
             for v in vals:
                 D.dawn_set_params(ctx, h, **{knob: v})
                 for r, s in enumerate(src[:4]):
                     got, _ = D.dawn_sssp(ctx, h, int(s))
                     assert np.array_equal(got, want[r]), f"{name} {knob}={v} source {s}"
             D.dawn_set_params(ctx, h, **saved)
+        for v in (8, 16, 32, 64):
+            D.dawn_set_params(ctx, h, medium_edges=65536, medium_groups=v)
+            for r, s in enumerate(src[:4]):
+                got, _ = D.dawn_sssp(ctx, h, int(s))
+                assert np.array_equal(got, want[r]), f"{name} medium_groups={v} source {s}"
     finally:
         D.dawn_set_params(ctx, h, **saved)
 
