@@ -1339,8 +1339,8 @@ __device__ __forceinline__ void level_step(const SsspArgs& a0, int parity) {
       if (!sh.go) break;
       L = sh.st.level;
       if (blockIdx.x == 0) {
-        // the slot level L + 1 counts into last held level L - 2's counters,
-        // which the workgroups that left had to read before they left
+        // the slot level L + 1 counts into held the counters of level L - 2,
+        // which the workgroups that left read before they left
         if (!waited) wait_arrivals<BLOCK>(a, sh, gridDim.x - K);
         waited = true;
         zero_slot<true>(&a.ctrl->slot[(L + 1) % 3], threadIdx.x, BLOCK);
