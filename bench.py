@@ -710,6 +710,8 @@ def main():
     ap.add_argument("--digest", action="store_true", help="print the level kernel's source digest")
     ap.add_argument("--batched-only", action="store_true",
                     help="only R-MAT 18 x 4096 sources through dawn_mssp, 3 calls (for profiling)")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="only the grid2048 section (four sources per driver), for profilers")
     args = ap.parse_args()
     if args.digest:
         print(kernel_digest())
@@ -743,6 +745,11 @@ def main():
     if args.batched_only:
         ctx = D.dawn_create(0, 0)
         batched_only(D, ctx)
+        return
+    if args.grid_only:
+        # the grid section alone (four grid2048 sources per driver), for a profiler
+        ctx = D.dawn_create(0, 0)
+        print(json.dumps({"grid_only": grid_bench(D, ctx, k_src=4)}), flush=True)
         return
 
     _log("[bench] R-MAT 20")
