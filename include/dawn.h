@@ -113,7 +113,10 @@ typedef struct dawn_params {
                                  4 the same launches captured once in a HIP graph and replayed */
   int32_t direction;          /* 1 push only, 2 pull only, 3 switch by alpha/beta */
   int32_t block;              /* threads per workgroup: 256, 512 or 1024 */
-  int32_t blocks_per_cu;      /* persistent grid: workgroups per compute unit */
+  int32_t blocks_per_cu;      /* workgroups per compute unit of the persistent kernel and of
+                                 level launches (0: as many as a compute unit holds; level
+                                 launches then use no more workgroups than a pull level has
+                                 visited-bitmap words for, and at least one per compute unit) */
   int32_t big_degree;         /* push: out-degree at which a node's edges are spread over the grid */
   int32_t pull_lane_edges;    /* pull: in-edges one lane scans before its wave helps */
   float alpha;                /* switch push -> pull when frontier edges > unvisited edges / alpha */
